@@ -1,0 +1,91 @@
+"""Mesh and numbering pins: the paper's printed DoF counts, Euler's relation, geometric consistency."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import geometry as geo
+from workloads import configs, mesh as wm
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "dof_tables.json")))
+
+
+@pytest.mark.parametrize("row", GOLD["periodic_boxes"], ids=lambda r: r["cite"])
+def test_periodic_tables(row):
+    nx, ny = row["n"]
+    m = wm.structured_box(nx, ny, 0.0, float(nx), 0.0, float(ny), True, True, p=row["p"], nz=row["nz"])
+    assert m.n_s == row["dof_surface"]
+    assert m.n_v == row["dof_volume"]
+    if m.n_eh <= 40000:
+        assert np.unique(m.eh_nodes).size == m.n_s
+
+
+@pytest.mark.parametrize("row", GOLD["walled_boxes"], ids=lambda r: r["cite"])
+def test_walled_tables(row):
+    nx, ny = row["n"]
+    m = wm.structured_box(nx, ny, 0.0, 38.0, 0.0, 1.0, False, False, p=row["p"], nz=row["nz"])
+    assert m.n_s == row["dof_surface"]
+    assert m.n_v == row["dof_volume"]
+
+
+@pytest.mark.parametrize("row", GOLD["column_factor"], ids=lambda r: r["cite"])
+def test_column_factor(row):
+    lev = row["p"] * row["nz"] + 1
+    assert row["dof_volume"] % lev == 0
+    if "dof_surface" in row:
+        assert row["dof_surface"] * lev == row["dof_volume"]
+
+
+def test_config_counts():
+    assert configs.c1().mesh.n_v == 288
+    assert configs.c2().mesh.n_v == 840000
+    m4 = configs.c4().mesh
+    assert (m4.n_s, m4.n_v) == (26001, 546021)
+    m5 = configs.c5().mesh
+    assert (m5.n_s, m5.n_v, m5.n_e) == (1180416, 43675392, 196608)
+    assert configs.p1().mesh.n_v == 1114112
+
+
+def test_cylinder_mesh_topology():
+    m = configs.c3().mesh
+    quads = m.extra["quads"]
+    assert m.n_eh == 48 * 24 + 60 * 30 - 144 == 2808
+    edges = set()
+    for q in quads:
+        for a, b in ((0, 1), (1, 2), (2, 3), (3, 0)):
+            edges.add((min(q[a], q[b]), max(q[a], q[b])))
+    V = len(np.unique(quads))
+    E = len(edges)
+    F = len(quads)
+    assert V - E + F == 0          # planar domain with one hole
+    p = m.p
+    assert m.n_s == V + (p - 1) * E + (p - 1) ** 2 * F
+    assert m.n_v == m.n_s * (p * m.nz + 1)
+    # counter-clockwise quads everywhere (positive horizontal Jacobian)
+    xh = geo.horizontal_coords(m)
+    geo.check_numbering(m, xh)
+
+
+@pytest.mark.parametrize("name", ["C1", "C2", "C4", "P1"])
+def test_numbering_consistency(name):
+    m = configs.ALL[name]().mesh
+    geo.check_numbering(m)
+
+
+def test_numbering_inconsistency_detected():
+    m = wm.structured_box(4, 3, 0.0, 2.0, 0.0, 1.5, True, False, p=3, nz=1)
+    bad = m.eh_nodes.copy()
+    bad[0, 1], bad[0, 3] = bad[0, 3], bad[0, 1]      # node 3 is shared with the next element
+    m.eh_nodes = bad
+    with pytest.raises(ValueError):
+        geo.check_numbering(m)
+
+
+def test_layer_major_surface_slice():
+    m = configs.c1().mesh
+    dofs = geo.dof_map(m)
+    top = dofs.reshape(m.n_e, m.p + 1, m.p + 1)[m.nz - 1::m.nz, m.p, :]
+    # the top node level of the top layer is the contiguous slice [p nz n_s, (p nz + 1) n_s)
+    assert top.min() == m.p * m.nz * m.n_s and top.max() == m.n_v - 1

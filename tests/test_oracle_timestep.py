@@ -1,0 +1,180 @@
+"""Pins for the free-surface RHS (Eqs. 2-3), ERK4 (Sec. 3.2), relaxation (Sec. 3.3) and diagnostics."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import geometry as geo
+from oracle import operator as op
+from oracle import solve as sv
+from oracle import surface as sf
+from oracle import timestep as ts
+from workloads import configs, mesh as wm, waves
+
+
+def _rk4_amp(z):
+    return 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+
+
+def test_rhs_degenerate_cases():
+    m = wm.structured_box(3, 3, 0.0, 2.0, 0.0, 2.0, True, True, p=4, nz=1)
+    x, y = geo.node_xy(m)
+    eta = 0.1 * np.sin(np.pi * x) * np.cos(np.pi * y)
+    w = 0.3 * np.cos(np.pi * x + 0.2)
+    z = np.zeros(m.n_s)
+    de, dp = sf.free_surface_rhs(m, z, z, w, 9.81)
+    np.testing.assert_allclose(de, w, atol=1e-14)
+    np.testing.assert_allclose(dp, 0.5 * w * w, atol=1e-14)
+    de, dp = sf.free_surface_rhs(m, eta, z, z, 9.81)
+    np.testing.assert_allclose(de, 0.0, atol=1e-14)
+    np.testing.assert_allclose(dp, -9.81 * eta, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rhs_pointwise_closed_form(dim):
+    """Smooth prescribed eta, phi_s, w: the lumped RHS converges to Eqs. 2-3 pointwise."""
+    k = np.pi
+    errs = []
+    for p in (3, 5, 7, 9):
+        if dim == 3:
+            m = wm.structured_box(3, 3, 0.0, 2.0, 0.0, 2.0, True, True, p=p, nz=1)
+        else:
+            m = wm.structured_slice(3, 0.0, 2.0, True, p=p, nz=1)
+        x, y = geo.node_xy(m)
+        eta = 0.2 * np.sin(k * x) * np.cos(k * y)
+        ex = 0.2 * k * np.cos(k * x) * np.cos(k * y)
+        ey = -0.2 * k * np.sin(k * x) * np.sin(k * y)
+        ph = 0.5 * np.cos(k * (x + y))
+        px = py = -0.5 * k * np.sin(k * (x + y))
+        if dim == 2:
+            ey = py = 0.0 * x
+            eta = 0.2 * np.sin(k * x)
+            ex = 0.2 * k * np.cos(k * x)
+            ph = 0.5 * np.cos(k * x)
+            px = -0.5 * k * np.sin(k * x)
+        w = 0.4 * np.cos(k * x + 0.3)
+        g = 9.81
+        ee = ex * ex + ey * ey
+        Ek = -(ex * px + ey * py) + w * (1 + ee)
+        Ed = -g * eta - 0.5 * (px * px + py * py) + 0.5 * w * w * (1 + ee)
+        de, dp = sf.free_surface_rhs(m, eta, ph, w, g)
+        errs.append(max(np.abs(de - Ek).max(), np.abs(dp - Ed).max()))
+    assert errs[-1] < 1e-6
+    assert all(e1 < e0 / 5 for e0, e1 in zip(errs, errs[1:]))
+
+
+def test_rk4_combination_linear_ode():
+    """With the stage replaced by a linear ODE y' = L y, one step equals R(L dt) y exactly."""
+    wl = configs.c1()
+    md = ts.Model(wl, solver="dense")
+    lam_e, lam_p = -0.7, 0.4
+
+    def fake(eta, phi_s, h=None, phi_guess=None):
+        return lam_e * eta, lam_p * phi_s, np.zeros(wl.mesh.n_v), None
+
+    md.stage = fake
+    eta0 = np.linspace(0.5, 1.5, wl.mesh.n_s)
+    phi0 = np.linspace(-1.0, 2.0, wl.mesh.n_s)
+    dt = 0.3
+    e1, p1 = md.rk4_step(eta0, phi0, 0.0, dt)
+    np.testing.assert_allclose(e1, _rk4_amp(lam_e * dt) * eta0, rtol=1e-15)
+    np.testing.assert_allclose(p1, _rk4_amp(lam_p * dt) * phi0, rtol=1e-15)
+
+
+def test_relaxation_limits():
+    wl = configs.c4(nx=8, ny=2, nz=1, p=2, nsteps=1)
+    md = ts.Model(wl, solver="dense")
+    cr, ec, es, pc, ps = md.relax
+    eta = np.random.default_rng(0).standard_normal(wl.mesh.n_s)
+    phi = np.random.default_rng(1).standard_normal(wl.mesh.n_s)
+    t = 1.234
+    e1, p1 = md.relax_apply(eta, phi, t)
+    zero = cr == 0.0
+    np.testing.assert_array_equal(e1[zero], eta[zero])
+    one = cr >= 1.0 - 1e-15
+    assert one.any() and zero.any()
+    r = ts.ramp(t, wl.t_ramp)
+    om = wl.relax_wave.omega
+    x = md.x
+    gen = x < 8.0 * 38.0 / 38.0
+    target = np.where(gen, r * wl.relax_wave.eta(x, md.y, t), 0.0)
+    np.testing.assert_allclose(e1[one], target[one], atol=1e-15)
+    np.testing.assert_allclose(p1[one], np.where(gen, r * wl.relax_wave.phi(x, md.y, t), 0.0)[one], atol=1e-15)
+    assert ts.ramp(0.0, 5.0) == 0.0 and ts.ramp(5.0, 5.0) == 1.0 and abs(ts.ramp(2.5, 5.0) - 0.5) < 1e-15
+
+
+def _dtn_eigenvalue(wl):
+    m = wl.mesh
+    x, _ = geo.node_xy(m)
+    k = wl.meta["k"]
+    h = np.ones(m.n_s)
+    G, _, _ = geo.factors(m, np.zeros(m.n_s), h)
+    phi = sv.solve_dense(m, op.assemble_dense(m, G), np.cos(k * x))
+    w = sf.w_surface(m, phi, np.zeros(m.n_s), h)
+    # nodal cos(kx) is an eigenvector of the discrete DtN map only up to the non-uniform
+    # GLL spacing (a few 1e-6 here); its Rayleigh quotient in the surface mass is the mode's
+    # eigenvalue to second order in that defect
+    ms = sf.surface_mass(m)
+    c = np.cos(k * x)
+    lam = (ms @ (c * w)) / (ms @ (c * c))
+    assert np.abs(w - lam * c).max() < 1e-4 * lam
+    return float(lam)
+
+
+def test_c1_standing_wave_dispersion_and_energy():
+    """C1: 32 ERK4 steps of a linear standing wave against the RK4/dispersion closed forms."""
+    wl = configs.c1()
+    md = ts.Model(wl, solver="dense")
+    k, g, dt = wl.meta["k"], wl.g, wl.dt
+    lam = _dtn_eigenvalue(wl)
+    assert abs(lam / (k * math.tanh(k)) - 1) < 3e-3          # discretisation error of C1's DtN
+    omega_h = math.sqrt(g * lam)
+    R = _rk4_amp(1j * omega_h * dt)
+    omega_rk = np.angle(R) / dt
+    basis = np.cos(k * md.x)
+    series = []
+
+    def cb(n, t, eta, phi_s):
+        series.append((t, (md.ms @ (eta * basis)) / (md.ms @ (basis * basis)), eta.copy(), phi_s.copy()))
+
+    eta0, phi0 = md.initial_state()
+    E0 = md.energy(eta0, phi0)
+    M0 = md.mass(eta0)
+    md.run(callback=cb)
+    t = np.array([s[0] for s in series])
+    zc = np.array([s[1] for s in series])
+    # least-squares fit a cos(omega t): grid search + Newton-free refinement by scipy
+    from scipy.optimize import least_squares
+    fit = least_squares(lambda q: q[0] * np.cos(q[1] * t) - zc, [1e-3, omega_h], xtol=1e-15, ftol=1e-15)
+    omega_fit = fit.x[1]
+    assert abs(omega_fit - omega_rk) / omega_rk < 2e-5
+    assert abs(omega_fit / wl.meta["omega"] - 1) < 2e-3
+    # amplitude and energy decay follow |R(i theta)|^n
+    assert abs(fit.x[0] / 1e-3 - 1) < 2e-5
+    E1 = md.energy(series[-1][2], series[-1][3])
+    assert abs(E1 / E0 - abs(R) ** 64) < 5e-6
+    # mass: the initial mode has zero mean; drift stays at rounding level
+    assert abs(md.mass(series[-1][2]) - M0) < 1e-12
+
+
+def test_complex_step_matches_central_differences():
+    """Complex-step directional derivative of a gauge loss vs central FD (small bar case)."""
+    wl = configs.c4(nx=8, ny=2, nz=1, p=2, nsteps=3)
+    md = ts.Model(wl, solver="dense")
+    x = md.x
+    P = ts.gauge_matrix(wl.mesh, [[10.0, 0.5], [21.0, 0.25]])
+    eta0 = 0.01 * np.cos(2 * np.pi * x / 38.0 * 4)
+    phi0 = 0.02 * np.sin(2 * np.pi * x / 38.0 * 4)
+    h = md.h
+    dt = 0.05
+    obs = np.zeros((3, 2)) + 0.001
+    rng = np.random.default_rng(3)
+    dh = rng.standard_normal(wl.mesh.n_s) * 0.01
+    de = rng.standard_normal(wl.mesh.n_s) * 0.001
+    d_cs = ts.complex_step_derivative(md, P, obs, 3, dt, eta0, phi0, h, de, dh)
+    eps = 1e-4
+    Jp = ts.gauge_loss(md, P, obs, 3, dt, eta0 + eps * de, phi0, h + eps * dh)
+    Jm = ts.gauge_loss(md, P, obs, 3, dt, eta0 - eps * de, phi0, h - eps * dh)
+    d_fd = (Jp - Jm) / (2 * eps)
+    assert abs(d_cs - d_fd) < 1e-7 * abs(d_fd) + 1e-18

@@ -1,0 +1,213 @@
+#!/usr/bin/env python
+"""Benchmark of the per-RK4-stage Laplace-solve path on one MI355X.
+
+A "step" is one ERK4 step of the whole path (4 x [geometry, Dirichlet lift, PCG solve,
+w recovery, free-surface RHS + stage update], relaxation) on the synthetic C5 workload:
+256 x 128 x 6 hexes, p = 6 (43,675,392 DoF), periodic in y, walls in x, seeded Fourier
+bathymetry and a JONSWAP irregular sea.  Inputs are resident in HBM before timing.
+
+Printed JSON line:
+  value            GDOF/s of the FP64 matrix-free Laplace apply (n_v / mean apply time,
+                   HIP events around a loop of applies on the launch stream)
+  ms_per_step      mean wall time of one mixed-precision ERK4 step at rtol 1e-8
+  s_per_rk4_step   FP64 and mixed step times at rtol 1e-8
+  roofline         the FP64 apply against the 8 TB/s HBM peak (algorithmic bytes)
+  cpu_baseline     the oracle's apply on a bounded sample of the same mesh, host cores
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/forward ratio"
+
+
+def apply_bytes(n_v, n_q, word):
+    """Algorithmic bytes of one apply: x read once, y written once, 6 factors per point read once."""
+    return word * (2 * n_v + 6 * n_q)
+
+
+def time_applies(ctx, x, reps, warm=3):
+    import torch
+    y = torch.empty_like(x)
+    for _ in range(warm):
+        ctx.laplace_apply(x, y)
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ctx.laplace_apply(x, y)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def run_steps(s, wl, opts, nsteps, t0=0.0, eta=None, phi=None):
+    import torch
+    e = (s.eta0 if eta is None else eta).clone()
+    p = (s.phi0 if phi is None else phi).clone()
+    t = t0
+    iters = []
+    for _ in range(nsteps):
+        info = s.ctx.rk4_step(e, p, s.h, t, wl.dt, opts=opts)
+        iters.append([i["iters"] for i in info])
+        t += wl.dt
+    return e, p, t, iters
+
+
+def cpu_baseline(wl, target_s=10.0):
+    """Oracle apply (numpy, FP64) on a bounded sample of columns of the same mesh."""
+    import numpy as np
+    from oracle import geometry as geo
+    from oracle import operator as op
+    m = wl.mesh
+    ncol = min(m.n_eh, 2048)
+    cols = np.arange(ncol)
+    xh = geo.horizontal_coords(m) if m.n_eh <= 4096 else None
+    if xh is None:
+        # horizontal coordinates of the sampled columns only (same oracle routine on a sub-mesh view)
+        from workloads.mesh import HexMesh
+        sub = HexMesh(dim=m.dim, p=m.p, nz=m.nz, n_s=m.n_s, eh_nodes=m.eh_nodes[cols],
+                      eh_corner=m.eh_corner[cols], eh_face_tag=m.eh_face_tag[cols],
+                      eh_arc=None if m.eh_arc is None else m.eh_arc[cols])
+        xh_s = geo.horizontal_coords(sub)
+        xh = np.zeros((m.n_eh,) + xh_s.shape[1:])
+        xh[cols] = xh_s
+    x, y = geo.node_xy(m) if m.n_eh <= 4096 else (None, None)
+    if x is None:
+        # node coordinates of the sample from its element coordinates
+        x = np.zeros(m.n_s)
+        y = np.zeros(m.n_s)
+        x[m.eh_nodes[cols].ravel()] = xh[cols][..., 0].ravel()
+        y[m.eh_nodes[cols].ravel()] = xh[cols][..., 1].ravel()
+    h = np.asarray(wl.depth(x, y))
+    eta = np.asarray(wl.eta0(x, y))
+    G, _, _ = geo.factors(m, eta, h, xh, cols=cols)
+    dofs = geo.dof_map(m, cols=cols)
+    rng = np.random.default_rng(0)
+    xv = rng.standard_normal(m.n_v)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        op.apply(m, G, xv, dofs)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or reps >= 200:
+            break
+    dof_per_col = m.n_v / m.n_eh
+    gdofs = ncol * dof_per_col * reps / el / 1e9
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    except Exception:
+        pass
+    cores = threads or len(os.sched_getaffinity(0))
+    return dict(value=gdofs, unit="GDOF/s", cores=int(cores), kind="oracle",
+                sample=f"numpy R2 apply over {ncol} of {m.n_eh} columns ({ncol * m.nz} elements), "
+                       f"{reps} reps in {el:.1f} s; DoF counted as columns x n_v/n_eh")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C5")
+    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-steps", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps(dict(error="this build runs on exactly one GPU; multi-GPU runs are not supported",
+                              n_gpus=args.gpus)))
+        sys.exit(2)
+
+    import torch
+    from paper_2506_09435_amd import fnpf
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    wl = configs.ALL[args.workload]()
+    m = wl.mesh
+    t_setup = time.perf_counter()
+    s = fnpf.setup_workload(wl, fp32=True)
+    ctx = s.ctx
+    print(f"[bench] {wl.name}: n_v={m.n_v} n_e={m.n_e} p={m.p} colours={ctx.n_colours} "
+          f"setup {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    # -- apply throughput (FP64 and FP32) at the initial geometry -----------------------
+    ctx.geom(s.eta0, s.h)
+    torch.cuda.synchronize()
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x64 = torch.randn(m.n_v, dtype=torch.float64, device="cuda", generator=g)
+    t64 = time_applies(ctx, x64, args.apply_reps)
+    t32 = time_applies(ctx, x64.float(), args.apply_reps)
+    n_q = m.n_e * (m.p + 1) ** m.dim
+    print(f"[bench] apply f64 {t64 * 1e3:.3f} ms ({m.n_v / t64 / 1e9:.1f} GDOF/s), "
+          f"f32 {t32 * 1e3:.3f} ms ({m.n_v / t32 / 1e9:.1f} GDOF/s)", file=sys.stderr, flush=True)
+
+    # -- ERK4 steps --------------------------------------------------------------------
+    o_mixed = fnpf.default_opts(precision=1, rtol=args.rtol, inner_rtol=1e-4, check_every=25, max_outer=30)
+    o_f64 = fnpf.default_opts(precision=0, rtol=args.rtol, check_every=25)
+    ctx.set_warm_start(None)
+    e, p, t, _ = run_steps(s, wl, o_mixed, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e2, p2, _, it_mixed = run_steps(s, wl, o_mixed, args.steps, t0=t, eta=e, phi=p)
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] mixed step {t_mixed:.3f} s, iters {it_mixed}", file=sys.stderr, flush=True)
+    t_f64 = None
+    it_f64 = None
+    if not args.no_fp64_steps:
+        ctx.set_warm_start(None)
+        e, p, t, _ = run_steps(s, wl, o_f64, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e3, p3, _, it_f64 = run_steps(s, wl, o_f64, args.steps, t0=t, eta=e, phi=p)
+        torch.cuda.synchronize()
+        t_f64 = (time.perf_counter() - t0) / args.steps
+        print(f"[bench] fp64 step {t_f64:.3f} s, iters {it_f64}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl)
+        print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
+
+    bytes64 = apply_bytes(m.n_v, n_q, 8)
+    achieved = bytes64 / t64 / 1e9
+    out = dict(
+        metric=METRIC, value=m.n_v / t64 / 1e9, unit="GDOF/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=t_mixed * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+        data="synthetic",
+        config=dict(workload=f"{wl.name}: 256x128x6 hexes, p=6, periodic y, walls x, Fourier bathymetry, "
+                             f"JONSWAP sea (128 components)", n_v=m.n_v, n_e=m.n_e, p=m.p, rtol=args.rtol,
+                    parallelism="single GPU"),
+        apply_gdofs=dict(f64=m.n_v / t64 / 1e9, f32=m.n_v / t32 / 1e9),
+        apply_ms=dict(f64=t64 * 1e3, f32=t32 * 1e3),
+        s_per_rk4_step=dict(f64=t_f64, mixed=t_mixed),
+        pcg_iters_per_stage=dict(f64=it_f64, mixed=it_mixed),
+        adjoint_forward_ratio=None,
+        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                      traffic=None, kernel="k_apply<6,3,double> (4 colour launches = one apply)",
+                      algorithmic_bytes_per_apply=bytes64),
+        cpu_baseline=cpu,
+    )
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

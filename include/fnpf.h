@@ -1,0 +1,237 @@
+/*
+ * fnpf.h - C ABI of the MI355X (gfx950) FNPF-SEM per-stage Laplace-solve library.
+ *
+ * The library implements, on one GPU, the hot path of the fully nonlinear
+ * potential-flow spectral element model of Visbech, Melander and
+ * Engsig-Karup ("FNPF-SEM", 2025): at every explicit RK4 stage
+ *   Step 4.1  move the extruded mesh to the current surface elevation eta,
+ *   Step 4.2  impose phi = phi_eta on the free surface (Dirichlet),
+ *   Step 4.3  solve the Laplace problem (Eq. 1, weak form Eq. 4) by PCG,
+ *   Step 4.4-4.5  recover the vertical velocity w_eta at the surface,
+ *   Step 4.6  evaluate the Zakharov free-surface conditions (Eqs. 2-3),
+ *   Step 3    accumulate the ERK4 stages (Sec. 3.2),
+ *   Step 4.7  apply relaxation zones (Sec. 3.3).
+ *
+ * Discretisation (readings of the paper where it is silent):
+ *   - hexahedral elements extruded from quadrilaterals (3D) or intervals
+ *     (2D x-z slices); GLL nodes of degree p with collocated GLL quadrature;
+ *   - node level v of a column sits at z = -h + sigma_v (eta + h);
+ *   - volume vectors are layer-major: index = v * n_s + hn, v = 0 (bottom)
+ *     .. p*nz (free surface), hn the horizontal node; the paper's surface
+ *     map m is therefore the slice [p*nz*n_s, (p*nz+1)*n_s);
+ *   - w recovery is the lumped-GLL L2 projection of d(phi)/dz; the
+ *     free-surface right-hand side uses the lumped GLL surface mass.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments documented as "device" are device pointers on the
+ *     context's GPU, owned by the caller, contiguous, 8-byte (double) or
+ *     4-byte (float) elements.  "host" arrays are read (or written) during
+ *     the call only.  The library never keeps a caller pointer after a call
+ *     returns; it owns only its internal workspaces, freed by fnpf_destroy.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Calls that need a scalar answer (fnpf_solve, fnpf_rk4_step and the
+ *     adjoint solve) synchronise the stream; all others are asynchronous.
+ *   - Every call returns a status and never aborts or throws across the ABI.
+ *     Argument validation happens before any HIP call.  fnpf_last_error
+ *     returns a message for the last failing call on a context.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef FNPF_H
+#define FNPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fnpf_ctx_s *fnpf_ctx;
+
+typedef enum {
+  FNPF_OK = 0,
+  FNPF_ERR_ARG = 1,       /* invalid argument (null pointer, size, ordering of calls) */
+  FNPF_ERR_ALLOC = 2,     /* device or host allocation failed */
+  FNPF_ERR_HIP = 3,       /* a HIP runtime call failed */
+  FNPF_ERR_GEOM = 4,      /* eta + h <= 0 at some node, or a non-positive Jacobian */
+  FNPF_ERR_NOCONV = 5,    /* PCG reached max_iter before rtol/atol */
+  FNPF_ERR_BREAKDOWN = 6, /* p^T A p <= 0 in PCG */
+  FNPF_ERR_NAN = 7,       /* NaN/Inf in the residual */
+  FNPF_ERR_STATE = 8      /* call sequence error, e.g. an apply before any fnpf_geom */
+} fnpf_status;
+
+typedef enum { FNPF_F64 = 0, FNPF_F32 = 1 } fnpf_dtype;
+
+/* Mesh description (host data, copied by fnpf_create).
+ * dim 2: vertical x-z slice, horizontal elements are intervals;
+ * dim 3: horizontal elements are quadrilaterals.  nh = (p+1)^(dim-1).
+ *   eh_nodes    [n_eh][nh]   global horizontal node id (0..n_s-1) of each
+ *                            element-local GLL node, local order i (xi)
+ *                            fastest then j (eta); periodicity is folded in.
+ *   eh_corner   [n_eh][2^(dim-1)][dim-1]  unwrapped physical corners; quads
+ *                            ordered (-1,-1),(+1,-1),(+1,+1),(-1,+1) and
+ *                            counter-clockwise; intervals (-1),(+1).
+ *   eh_arc      NULL or [n_eh][4][3]: per quad edge (cx, cy, R) of a circle
+ *                            the edge follows (R = 0 straight).  Edges:
+ *                            e0 c0->c1, e1 c1->c2, e2 c3->c2, e3 c0->c3,
+ *                            parametrised linearly in angle (shorter arc).
+ *                            Interior node positions follow the Gordon-Hall
+ *                            transfinite map of the four edges.
+ *   eh_face_tag NULL or [n_eh][2(dim-1)]: 0 interior/periodic, 1 wall,
+ *                            2 body (both impermeable: natural Neumann).
+ *                            Quad sides are ordered like the edges; interval
+ *                            sides are (xi=-1, xi=+1).
+ *   layer_s     NULL (uniform) or [nz+1] increasing fractions, 0 .. 1.
+ *   g           gravitational acceleration.                                */
+typedef struct {
+  int32_t dim;
+  int32_t p;          /* 1 .. 8 */
+  int32_t nz;         /* >= 1 */
+  int32_t n_eh;       /* >= 1 */
+  int64_t n_s;
+  const int32_t *eh_nodes;
+  const double *eh_corner;
+  const double *eh_arc;
+  const int32_t *eh_face_tag;
+  const double *layer_s;
+  double g;
+} fnpf_mesh_desc;
+
+/* PCG options.
+ *   precision 0: FP64 PCG.  1: mixed - FP64 outer defect correction
+ *                (residual with the FP64 operator, FP64 solution update)
+ *                around an FP32 inner PCG (FP32 geometric factors, vectors
+ *                and apply; FP64 dot products and scalars).
+ *   precond   1: Jacobi (assembled diagonal); the only preconditioner of
+ *                this build (other values are rejected with FNPF_ERR_ARG).
+ *   Stop when ||r||_2 <= max(rtol ||b||_2, atol), b = f_I - A_IS phi_s
+ *   (unpreconditioned 2-norms over the non-surface nodes).
+ *   max_iter bounds the total PCG iterations (inner ones for mixed);
+ *   check_every is the number of iterations between host convergence checks
+ *   (the iterations after convergence are skipped on the device, so results
+ *   do not depend on it).  inner_rtol: relative reduction of each inner FP32
+ *   solve; max_outer bounds the defect-correction sweeps.                  */
+typedef struct {
+  int32_t precision;
+  int32_t precond;
+  double rtol;
+  double atol;
+  int32_t max_iter;
+  int32_t check_every;
+  double inner_rtol;
+  int32_t max_outer;
+} fnpf_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* PCG iterations (inner iterations summed for mixed) */
+  int32_t outer_iters;  /* FP64 residual evaluations of the mixed path (0 for FP64) */
+  double rel_res;       /* final FP64 ||r|| / ||b|| */
+  double bnorm;         /* ||b||_2 */
+} fnpf_solve_info;
+
+/* Defaults: FP64, Jacobi, rtol 1e-8, atol 0, max_iter 20000, check_every 25,
+ * inner_rtol 1e-4, max_outer 30. */
+void fnpf_default_opts(fnpf_solve_opts *opts);
+
+/* Create a context on the current HIP device: validates and copies the mesh,
+ * computes GLL data, horizontal metrics (Gordon-Hall coordinates), the greedy
+ * column colouring used for conflict-free scatter, and allocates the FP64
+ * workspaces (FP32 ones on first mixed use).  Errors: ARG (invalid mesh, e.g.
+ * node ids out of range or unused, a non-positive horizontal Jacobian), ALLOC,
+ * HIP.  *out is NULL on failure. */
+fnpf_status fnpf_create(const fnpf_mesh_desc *mesh, fnpf_ctx *out);
+fnpf_status fnpf_destroy(fnpf_ctx ctx);
+/* Message of the last failing call on ctx; with ctx == NULL, the message of
+ * the last failed fnpf_create on this thread. */
+const char *fnpf_last_error(fnpf_ctx ctx);
+const char *fnpf_status_string(fnpf_status s);
+
+/* Sizes: volume nodes n_v = n_s (p nz + 1), surface nodes n_s, elements
+ * n_e = n_eh nz, number of colours of the column colouring. Any pointer may be NULL. */
+fnpf_status fnpf_sizes(fnpf_ctx ctx, int64_t *n_v, int64_t *n_s, int64_t *n_e, int32_t *n_colours);
+
+/* GLL data of degree p (host, no context): nodes[p+1], weights[p+1] and
+ * D[(p+1)*(p+1)] row-major, D[i*(p+1)+j] = l_j'(x_i).  Any output may be NULL. */
+fnpf_status fnpf_gll(int32_t p, double *nodes, double *weights, double *D);
+
+/* Host copy of the physical coordinates of every horizontal node:
+ * xy[n_s][dim-1] (periodic nodes: the first element's image). */
+fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy);
+
+/* Enable the FP32 path: allocates FP32 factors and the inner-PCG vectors;
+ * every later fnpf_geom also produces the FP32 factors.  fnpf_rk4_step with
+ * precision 1 enables it by itself. */
+fnpf_status fnpf_enable_fp32(fnpf_ctx ctx);
+
+/* Step 4.1: per-point geometric factors for surface elevation eta[n_s] and
+ * depth h[n_s] (device, FP64): G = w_q det(J) J^{-1} J^{-T} (6 symmetric
+ * entries in 3D, 3 in 2D), the assembled Jacobi diagonal of the Laplace
+ * operator, and FP32 copies when the mixed path is in use.  A node with
+ * eta + h <= 0 raises a device flag reported as FNPF_ERR_GEOM by the next
+ * synchronising call (fnpf_solve, fnpf_rk4_step, fnpf_sync). */
+fnpf_status fnpf_geom(fnpf_ctx ctx, const double *eta, const double *h, void *stream);
+
+/* Device copies of the factors of the last fnpf_geom (parity checks):
+ * G[n_e][ng][(p+1)^dim] (ng = 6 in 3D ordered 00,01,02,11,12,22; 3 in 2D
+ * ordered 00,01,11; element e = column * nz + layer; local node (k, j, i),
+ * i fastest) in FP64 (dtype F64) or FP32, and diag[n_v] FP64.  Either may be NULL. */
+fnpf_status fnpf_export_geometry(fnpf_ctx ctx, fnpf_dtype dtype, void *G, double *diag, void *stream);
+
+/* Eq. 4: y = A x with the matrix-free sum-factorised stiffness operator of
+ * the current geometry, x and y [n_v] device arrays of `dtype` (F32 uses the
+ * FP32 factors).  mask_dirichlet != 0 sets the free-surface rows of y to 0.
+ * x and y must not overlap.  Errors: STATE if fnpf_geom was never called
+ * (or, for F32, never called since the FP32 path was enabled). */
+fnpf_status fnpf_laplace_apply(fnpf_ctx ctx, fnpf_dtype dtype, const void *x, void *y, int32_t mask_dirichlet,
+                               void *stream);
+
+/* Eq. 1 boundary data: f_i = sum over the bottom and the wall/body faces of
+ * int (q . n) l_i dS for a nodal flux field q[dim][n_v] (device, FP64,
+ * physical components x, (y,) z), with the current geometry.  f[n_v] device. */
+fnpf_status fnpf_neumann_load(fnpf_ctx ctx, const double *q, double *f, void *stream);
+
+/* Steps 4.2-4.3: solve the Laplace problem with phi = phi_surface[n_s] on the
+ * free surface and Neumann load neumann_f[n_v] (NULL = homogeneous).  phi[n_v]
+ * (device) holds the initial guess on entry (its surface level is
+ * overwritten) and the solution on exit; on NOCONV/BREAKDOWN it holds the last
+ * iterate.  info (host, may be NULL) is filled in every case. */
+fnpf_status fnpf_solve(fnpf_ctx ctx, const double *phi_surface, const double *neumann_f, double *phi,
+                       const fnpf_solve_opts *opts, fnpf_solve_info *info, void *stream);
+
+/* Steps 4.4-4.5: w_s[n_s] = recovered d(phi)/dz at the free-surface nodes for
+ * phi[n_v] and the geometry of the last fnpf_geom (eta, h of that call). */
+fnpf_status fnpf_w_surface(fnpf_ctx ctx, const double *phi, double *w_s, void *stream);
+
+/* Step 4.6 / Eqs. 2-3: deta[n_s], dphi[n_s] from eta, phi_s, w_s [n_s] (all device FP64). */
+fnpf_status fnpf_rhs(fnpf_ctx ctx, const double *eta, const double *phi_s, const double *w_s, double *deta,
+                     double *dphi, void *stream);
+
+/* Step 4.7 relaxation zones (host arrays [n_s], copied): after every full
+ * step f <- (1 - cr) f + cr * ramp(t) * (f_c cos(omega t) + f_s sin(omega t))
+ * for f = eta (eta_c, eta_s) and phi_s (phi_c, phi_s_); ramp(t) =
+ * (1 - cos(pi t / t_ramp))/2 for t < t_ramp, else 1 (t_ramp <= 0: 1).
+ * cr == NULL removes the relaxation. */
+fnpf_status fnpf_set_relaxation(fnpf_ctx ctx, const double *cr, const double *eta_c, const double *eta_s,
+                                const double *phi_c, const double *phi_s_, double omega, double t_ramp);
+
+/* One ERK4 step (Sec. 3.2) of the Zakharov system from time t with step dt,
+ * in place on eta[n_s] and phi_s[n_s] (device FP64), depth h[n_s] (device),
+ * followed by relaxation at t + dt.  The volume potential of the previous
+ * stage is the PCG warm start (kept in the context).  tape (device, may be
+ * NULL) receives the four stage potentials [4][n_v]; info (host, may be NULL)
+ * receives one record per stage. */
+fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phi_s, const double *h, double t, double dt,
+                          const fnpf_solve_opts *opts, double *tape, fnpf_solve_info *info, void *stream);
+
+/* Copy the context's warm-start potential to/from phi[n_v] (device FP64);
+ * phi == NULL in set_ resets it to zero. */
+fnpf_status fnpf_get_warm_start(fnpf_ctx ctx, double *phi, void *stream);
+fnpf_status fnpf_set_warm_start(fnpf_ctx ctx, const double *phi, void *stream);
+
+/* Synchronise `stream` and report a pending device-side error (FNPF_ERR_GEOM). */
+fnpf_status fnpf_sync(fnpf_ctx ctx, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FNPF_H */

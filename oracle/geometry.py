@@ -131,43 +131,51 @@ def sigma_levels(mesh):
     return sig
 
 
-def dof_map(mesh):
+def dof_map(mesh, cols=None):
     """Global volume index (layer-major: v * n_s + hn) of every element node: [n_e, n1^dim]."""
     p, n1, nz = mesh.p, mesh.p + 1, mesh.nz
+    nodes = mesh.eh_nodes if cols is None else mesh.eh_nodes[np.asarray(cols)]
+    n_eh = nodes.shape[0]
     k = np.arange(n1)
-    if mesh.dim == 3:
-        hn = mesh.eh_nodes.reshape(mesh.n_eh, 1, 1, n1 * n1)
-        lev = (np.arange(nz)[None, :, None, None] * p + k[None, None, :, None])
-        idx = lev * mesh.n_s + hn
-        return idx.reshape(mesh.n_eh * nz, n1 ** 3)
-    hn = mesh.eh_nodes.reshape(mesh.n_eh, 1, 1, n1)
+    nh = n1 * n1 if mesh.dim == 3 else n1
+    hn = nodes.reshape(n_eh, 1, 1, nh).astype(np.int64)
     lev = (np.arange(nz)[None, :, None, None] * p + k[None, None, :, None])
     idx = lev * mesh.n_s + hn
-    return idx.reshape(mesh.n_eh * nz, n1 * n1)
+    return idx.reshape(n_eh * nz, n1 * nh)
 
 
-def element_coords(mesh, eta, h, xh=None):
-    """Nodal physical coordinates [n_e, n1, (n1,) n1, dim] for surface eta and depth h."""
+def element_coords(mesh, eta, h, xh=None, cols=None):
+    """Nodal physical coordinates [n_e, n1, (n1,) n1, dim] for surface eta and depth h.
+
+    ``cols`` restricts the result to the elements of the given columns (in that
+    order, layers inside each column); ``xh`` must then be the full array.
+    """
     if xh is None:
         xh = horizontal_coords(mesh)
+    nodes = mesh.eh_nodes
+    if cols is not None:
+        cols = np.asarray(cols)
+        xh = xh[cols]
+        nodes = nodes[cols]
     p, n1, nz = mesh.p, mesh.p + 1, mesh.nz
+    n_eh = nodes.shape[0]
     sig = sigma_levels(mesh)
     dt = np.result_type(eta, h, np.float64)
-    eta_e = np.asarray(eta)[mesh.eh_nodes]   # [n_eh, nh]
-    h_e = np.asarray(h)[mesh.eh_nodes]
+    eta_e = np.asarray(eta)[nodes]   # [n_eh, nh]
+    h_e = np.asarray(h)[nodes]
     lev = (np.arange(nz)[:, None] * p + np.arange(n1)[None, :])   # [nz, n1]
     s = sig[lev]                                                  # [nz, n1]
     z = -h_e[:, None, None, :] + s[None, :, :, None] * (eta_e + h_e)[:, None, None, :]   # [n_eh, nz, k, nh]
     if mesh.dim == 3:
-        X = np.zeros((mesh.n_eh, nz, n1, n1, n1, 3), dtype=dt)
-        X[..., 0] = xh[:, None, None, :, 0].reshape(mesh.n_eh, 1, 1, n1, n1)
-        X[..., 1] = xh[:, None, None, :, 1].reshape(mesh.n_eh, 1, 1, n1, n1)
-        X[..., 2] = z.reshape(mesh.n_eh, nz, n1, n1, n1)
-        return X.reshape(mesh.n_eh * nz, n1, n1, n1, 3)
-    X = np.zeros((mesh.n_eh, nz, n1, n1, 2), dtype=dt)
+        X = np.zeros((n_eh, nz, n1, n1, n1, 3), dtype=dt)
+        X[..., 0] = xh[:, None, None, :, 0].reshape(n_eh, 1, 1, n1, n1)
+        X[..., 1] = xh[:, None, None, :, 1].reshape(n_eh, 1, 1, n1, n1)
+        X[..., 2] = z.reshape(n_eh, nz, n1, n1, n1)
+        return X.reshape(n_eh * nz, n1, n1, n1, 3)
+    X = np.zeros((n_eh, nz, n1, n1, 2), dtype=dt)
     X[..., 0] = xh[:, None, None, :, 0]
     X[..., 1] = z
-    return X.reshape(mesh.n_eh * nz, n1, n1, 2)
+    return X.reshape(n_eh * nz, n1, n1, 2)
 
 
 def jacobian(mesh, X):
@@ -185,9 +193,9 @@ def quad_weights(mesh):
     return w[:, None] * w[None, :]
 
 
-def factors(mesh, eta, h, xh=None):
+def factors(mesh, eta, h, xh=None, cols=None):
     """Return (G, wdetJ, J) with G[e, nodes..., a, b] = w det(J) (J^-1 J^-T)_ab."""
-    X = element_coords(mesh, eta, h, xh)
+    X = element_coords(mesh, eta, h, xh, cols)
     J = jacobian(mesh, X)
     det = np.linalg.det(J)
     if np.any(np.real(det) <= 0.0):

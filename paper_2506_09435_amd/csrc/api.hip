@@ -1,0 +1,618 @@
+// C ABI of the FNPF-SEM Laplace-solve library: context management, argument validation and
+// the host drivers of the PCG solve and the ERK4 step.  Kernels live in kernels_*.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fnpf_internal.h"
+
+using namespace fnpf;
+
+struct fnpf_ctx_s {
+  Ctx c;
+};
+
+static thread_local std::string g_create_error;
+
+namespace {
+
+const double kRkB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+const double kRkC[4] = {0.0, 0.5, 0.5, 1.0};
+
+fnpf_status fail(Ctx *c, fnpf_status st, const std::string &msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+fnpf_status hipfail(Ctx *c, hipError_t e, const char *where) {
+  if (c) c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return FNPF_ERR_HIP;
+}
+
+#define HIPCHK(expr)                                 \
+  do {                                               \
+    hipError_t e__ = (expr);                         \
+    if (e__ != hipSuccess) return hipfail(&c, e__, #expr); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc((void **)p, n * sizeof(T));
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+void free_all(Ctx &c) {
+  dfree(c.d_eh_nodes);
+  dfree(c.d_cols);
+  dfree(c.d_flags);
+  dfree(c.d_face_tag);
+  dfree(c.d_hm);
+  dfree(c.d_sigma);
+  dfree(c.d_layer_s);
+  dfree(c.d_mlump_w);
+  dfree(c.d_mlump_s);
+  dfree(c.d_G64);
+  dfree(c.d_G32);
+  dfree(c.d_diag);
+  dfree(c.d_dinv);
+  dfree(c.d_dinv32);
+  dfree(c.d_err);
+  dfree(c.d_r);
+  dfree(c.d_p);
+  dfree(c.d_q);
+  dfree(c.d_phi);
+  dfree(c.d_r32);
+  dfree(c.d_p32);
+  dfree(c.d_q32);
+  dfree(c.d_d32);
+  for (int k = 0; k < 2; ++k) {
+    dfree(c.d_sa[k]);
+    dfree(c.d_sp[k]);
+  }
+  dfree(c.d_acc_e);
+  dfree(c.d_acc_p);
+  dfree(c.d_w);
+  dfree(c.d_geoH);
+  dfree(c.d_geoh);
+  dfree(c.d_wnum);
+  dfree(c.d_nk);
+  dfree(c.d_nd);
+  dfree(c.d_partial);
+  dfree(c.d_sc);
+  if (c.h_sc) (void)hipHostFree(c.h_sc);
+  c.h_sc = nullptr;
+  dfree(c.d_cr);
+  dfree(c.d_rec);
+  dfree(c.d_res);
+  dfree(c.d_rpc);
+  dfree(c.d_rps);
+}
+
+template <typename T>
+hipError_t upload(T **d, const T *h, size_t n) {
+  hipError_t e = dalloc(d, n);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*d, h, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Enable the FP32 path (allocates FP32 factors and inner PCG vectors on first use).
+fnpf_status ensure32(Ctx &c) {
+  if (c.want32) return FNPF_OK;
+  HIPCHK(dalloc(&c.d_G32, (size_t)c.n_e * c.ng * c.np));
+  HIPCHK(dalloc(&c.d_dinv32, c.n_v));
+  HIPCHK(dalloc(&c.d_r32, c.n_v));
+  HIPCHK(dalloc(&c.d_p32, c.n_v));
+  HIPCHK(dalloc(&c.d_q32, c.n_v));
+  HIPCHK(dalloc(&c.d_d32, c.n_v));
+  c.want32 = true;
+  c.have_geom32 = false;
+  return FNPF_OK;
+}
+
+fnpf_status check_err_flag(Ctx &c, hipStream_t s) {
+  int32_t flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, c.d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (flag) {
+    HIPCHK(launch_zero_i32(c.d_err, 1, s));
+    return fail(&c, FNPF_ERR_GEOM, "eta + h <= 0 (or non-finite) at a surface node: the column collapsed");
+  }
+  return FNPF_OK;
+}
+
+int apply_blocks(const Ctx &c) { return c.max_colour_blocks; }
+
+// PCG on A_II (FP64), x = phi holds the guess with its surface level set.
+fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, int &iters, hipStream_t s) {
+  PcgScalars *sc = c.d_sc;
+  HIPCHK(launch_apply(c, FNPF_F64, x, c.d_q, true, nullptr, nullptr, s));
+  HIPCHK(launch_pcg_init<double>(f, c.d_q, c.d_r, c.d_p, c.d_dinv, c.n_v, c.n_s, c.d_partial, sc, false, 0.0, s));
+  const int nb = apply_blocks(c);
+  iters = 0;
+  for (;;) {
+    for (int k = 0; k < o.check_every; ++k) {
+      HIPCHK(launch_apply(c, FNPF_F64, c.d_p, c.d_q, true, c.d_partial, &sc->done, s));
+      HIPCHK(launch_finalize_pq(c.d_partial, nb, sc, s));
+      HIPCHK((launch_pcg_update<double, double>(x, c.d_r, c.d_p, c.d_q, c.d_dinv, c.n_v, c.d_partial, sc, s)));
+      HIPCHK(launch_pcg_dir<double>(c.d_p, c.d_r, c.d_dinv, c.n_v, sc, s));
+    }
+    HIPCHK(hipMemcpyAsync(c.h_sc, c.d_sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    iters = c.h_sc[0].iters;
+    if (c.h_sc[0].done || iters >= o.max_iter) break;
+  }
+  if (c.h_sc[0].breakdown == 2) return fail(&c, FNPF_ERR_NAN, "non-finite residual in PCG");
+  if (c.h_sc[0].breakdown == 1) return fail(&c, FNPF_ERR_BREAKDOWN, "PCG breakdown: p^T A p <= 0");
+  if (!c.h_sc[0].done) return fail(&c, FNPF_ERR_NOCONV, "PCG did not reach the tolerance within max_iter");
+  return FNPF_OK;
+}
+
+// Mixed precision: FP64 residual and update around FP32 PCG (defect correction).
+fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, int &iters, int &outer,
+                      hipStream_t s) {
+  PcgScalars *so = c.d_sc, *si = c.d_sc + 1;
+  const int nb = apply_blocks(c);
+  iters = 0;
+  outer = 0;
+  for (;;) {
+    HIPCHK(launch_apply(c, FNPF_F64, x, c.d_q, true, nullptr, nullptr, s));
+    HIPCHK(launch_resid_to32(f, c.d_q, c.d_r32, c.d_p32, c.d_d32, c.d_dinv32, c.n_v, c.n_s, c.d_partial, so, si,
+                             o.inner_rtol, s));
+    ++outer;
+    HIPCHK(hipMemcpyAsync(c.h_sc, c.d_sc, 2 * sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (c.h_sc[0].breakdown == 2) return fail(&c, FNPF_ERR_NAN, "non-finite residual in the FP64 defect correction");
+    if (c.h_sc[0].done) break;
+    if (outer > o.max_outer || iters >= o.max_iter)
+      return fail(&c, FNPF_ERR_NOCONV, "mixed-precision solve did not reach the tolerance");
+    for (;;) {
+      for (int k = 0; k < o.check_every; ++k) {
+        HIPCHK(launch_apply(c, FNPF_F32, c.d_p32, c.d_q32, true, c.d_partial, &si->done, s));
+        HIPCHK(launch_finalize_pq(c.d_partial, nb, si, s));
+        HIPCHK((launch_pcg_update<float, float>(c.d_d32, c.d_r32, c.d_p32, c.d_q32, c.d_dinv32, c.n_v, c.d_partial,
+                                                si, s)));
+        HIPCHK(launch_pcg_dir<float>(c.d_p32, c.d_r32, c.d_dinv32, c.n_v, si, s));
+      }
+      HIPCHK(hipMemcpyAsync(c.h_sc + 1, si, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (c.h_sc[1].done || iters + c.h_sc[1].iters >= o.max_iter) break;
+    }
+    iters += c.h_sc[1].iters;
+    if (c.h_sc[1].breakdown == 2) return fail(&c, FNPF_ERR_NAN, "non-finite residual in the FP32 inner PCG");
+    // a breakdown of the inner solve still leaves a usable correction; the outer loop decides
+    HIPCHK(launch_add_f32(x, c.d_d32, c.n_v, s));
+  }
+  return FNPF_OK;
+}
+
+fnpf_status validate_opts(Ctx &c, const fnpf_solve_opts &o) {
+  if (o.precision != 0 && o.precision != 1) return fail(&c, FNPF_ERR_ARG, "opts.precision must be 0 or 1");
+  if (o.precond != 1) return fail(&c, FNPF_ERR_ARG, "opts.precond must be 1 (Jacobi)");
+  if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || (o.rtol == 0.0 && o.atol == 0.0))
+    return fail(&c, FNPF_ERR_ARG, "opts.rtol/atol must be >= 0 and not both 0");
+  if (o.max_iter < 1 || o.check_every < 1) return fail(&c, FNPF_ERR_ARG, "opts.max_iter and check_every must be >= 1");
+  if (o.precision == 1 && (!(o.inner_rtol > 0.0) || !(o.inner_rtol < 1.0) || o.max_outer < 1))
+    return fail(&c, FNPF_ERR_ARG, "opts.inner_rtol must be in (0,1) and max_outer >= 1 for the mixed path");
+  return FNPF_OK;
+}
+
+// Solve with the current geometry: phi (guess in, solution out), surface data phis.
+fnpf_status solve_impl(Ctx &c, const double *phis, const double *f, double *phi, const fnpf_solve_opts &o,
+                       fnpf_solve_info *info, hipStream_t s) {
+  if (info) std::memset(info, 0, sizeof(*info));
+  // ||b|| with b = f - A [0; phi_s]
+  HIPCHK(launch_set_lift(c.d_p, phis, c.n_v, c.n_s, s));
+  HIPCHK(launch_apply(c, FNPF_F64, c.d_p, c.d_q, true, nullptr, nullptr, s));
+  HIPCHK(launch_bnorm(f, c.d_q, c.n_v, c.n_s, c.d_partial, c.d_sc, o.rtol, o.atol, s));
+  HIPCHK(launch_copy_top(phi, phis, c.n_v, c.n_s, s));
+  fnpf_status st = check_err_flag(c, s);
+  if (st != FNPF_OK) return st;
+  int iters = 0, outer = 0;
+  if (o.precision == 0)
+    st = pcg64(c, f, phi, o, iters, s);
+  else
+    st = pcg_mixed(c, f, phi, o, iters, outer, s);
+  if (info) {
+    info->iters = iters;
+    info->outer_iters = outer;
+    info->bnorm = std::sqrt(c.h_sc[0].bnorm2);
+    info->rel_res = c.h_sc[0].bnorm2 > 0 ? std::sqrt(c.h_sc[0].rr / c.h_sc[0].bnorm2) : std::sqrt(c.h_sc[0].rr);
+  }
+  return st;
+}
+
+fnpf_status geom_impl(Ctx &c, const double *eta, const double *h, hipStream_t s) {
+  HIPCHK(launch_geom(c, eta, h, s));
+  c.have_geom = true;
+  c.have_geom32 = c.want32;
+  return FNPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fnpf_default_opts(fnpf_solve_opts *o) {
+  if (!o) return;
+  o->precision = 0;
+  o->precond = 1;
+  o->rtol = 1e-8;
+  o->atol = 0.0;
+  o->max_iter = 20000;
+  o->check_every = 25;
+  o->inner_rtol = 1e-4;
+  o->max_outer = 30;
+}
+
+const char *fnpf_status_string(fnpf_status s) {
+  switch (s) {
+    case FNPF_OK: return "ok";
+    case FNPF_ERR_ARG: return "invalid argument";
+    case FNPF_ERR_ALLOC: return "allocation failed";
+    case FNPF_ERR_HIP: return "HIP runtime error";
+    case FNPF_ERR_GEOM: return "geometry error (eta + h <= 0)";
+    case FNPF_ERR_NOCONV: return "PCG did not converge";
+    case FNPF_ERR_BREAKDOWN: return "PCG breakdown";
+    case FNPF_ERR_NAN: return "non-finite values";
+    case FNPF_ERR_STATE: return "invalid call sequence";
+  }
+  return "unknown status";
+}
+
+const char *fnpf_last_error(fnpf_ctx ctx) { return ctx ? ctx->c.err.c_str() : g_create_error.c_str(); }
+
+fnpf_status fnpf_gll(int32_t p, double *nodes, double *weights, double *D) {
+  if (p < 1 || p > kMaxP) return FNPF_ERR_ARG;
+  gll_host(p, nodes, weights, D);
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
+  g_create_error.clear();
+  if (!out) {
+    g_create_error = "out is NULL";
+    return FNPF_ERR_ARG;
+  }
+  *out = nullptr;
+  if (!m) {
+    g_create_error = "mesh is NULL";
+    return FNPF_ERR_ARG;
+  }
+  if ((m->dim != 2 && m->dim != 3) || m->p < 1 || m->p > kMaxP || m->nz < 1 || m->n_eh < 1 || m->n_s < 1 ||
+      !m->eh_nodes || !m->eh_corner || !(m->g > 0.0)) {
+    g_create_error = "invalid mesh header (dim 2|3, 1 <= p <= 8, nz >= 1, n_eh >= 1, n_s >= 1, g > 0, "
+                     "eh_nodes and eh_corner required)";
+    return FNPF_ERR_ARG;
+  }
+  if (m->dim == 2 && m->eh_arc) {
+    g_create_error = "eh_arc is only meaningful for dim 3";
+    return FNPF_ERR_ARG;
+  }
+  fnpf_ctx_s *h = new (std::nothrow) fnpf_ctx_s();
+  if (!h) return FNPF_ERR_ALLOC;
+  Ctx &c = h->c;
+  std::vector<double> hm, mw, ms;
+  std::vector<uint8_t> flags;
+  std::vector<int32_t> cols;
+  std::string e = build_host_mesh(*m, c, hm, flags, cols, mw, ms);
+  if (!e.empty()) {
+    g_create_error = e;
+    delete h;
+    return FNPF_ERR_ARG;
+  }
+  // total apply blocks over colours (partials of the fused dot product)
+  {
+    const int cpb = 256 / c.nh;
+    int tot = 0;
+    for (const auto &cr : c.colours) tot += (cr.count + cpb - 1) / cpb;
+    c.max_colour_blocks = tot;
+  }
+  hipError_t he = hipGetDevice(&c.device);
+  auto bad = [&](hipError_t err) {
+    g_create_error = std::string("HIP error during create: ") + hipGetErrorString(err);
+    free_all(c);
+    delete h;
+    return err == hipErrorOutOfMemory ? FNPF_ERR_ALLOC : FNPF_ERR_HIP;
+  };
+  if (he != hipSuccess) return bad(he);
+  static bool uploaded[64] = {false};
+  if (c.device >= 0 && c.device < 64 && !uploaded[c.device]) {
+    he = upload_constants(c.device);
+    if (he != hipSuccess) return bad(he);
+    uploaded[c.device] = true;
+  }
+  const int nsides = 2 * (c.dim - 1);
+  std::vector<int32_t> tags((size_t)c.n_eh * nsides, 0);
+  if (m->eh_face_tag)
+    for (size_t k = 0; k < tags.size(); ++k) tags[k] = m->eh_face_tag[k];
+#define UP(dst, src, n)                       \
+  do {                                        \
+    he = upload(&dst, src, n);                \
+    if (he != hipSuccess) return bad(he);     \
+  } while (0)
+#define AL(dst, n)                            \
+  do {                                        \
+    he = dalloc(&dst, n);                     \
+    if (he != hipSuccess) return bad(he);     \
+  } while (0)
+  UP(c.d_eh_nodes, c.h_eh_nodes.data(), c.h_eh_nodes.size());
+  UP(c.d_cols, cols.data(), cols.size());
+  UP(c.d_flags, flags.data(), flags.size());
+  UP(c.d_face_tag, tags.data(), tags.size());
+  UP(c.d_hm, hm.data(), hm.size());
+  UP(c.d_sigma, c.h_sigma.data(), c.h_sigma.size());
+  UP(c.d_layer_s, c.h_layer_s.data(), c.h_layer_s.size());
+  UP(c.d_mlump_w, mw.data(), mw.size());
+  UP(c.d_mlump_s, ms.data(), ms.size());
+  AL(c.d_G64, (size_t)c.n_e * c.ng * c.np);
+  AL(c.d_diag, c.n_v);
+  AL(c.d_dinv, c.n_v);
+  AL(c.d_err, 1);
+  AL(c.d_r, c.n_v);
+  AL(c.d_p, c.n_v);
+  AL(c.d_q, c.n_v);
+  AL(c.d_phi, c.n_v);
+  for (int k = 0; k < 2; ++k) {
+    AL(c.d_sa[k], c.n_s);
+    AL(c.d_sp[k], c.n_s);
+  }
+  AL(c.d_acc_e, c.n_s);
+  AL(c.d_acc_p, c.n_s);
+  AL(c.d_w, c.n_s);
+  AL(c.d_geoH, c.n_s);
+  AL(c.d_geoh, c.n_s);
+  AL(c.d_wnum, c.n_s);
+  AL(c.d_nk, c.n_s);
+  AL(c.d_nd, c.n_s);
+  c.n_partial = std::max(3 * kVecBlocks, c.max_colour_blocks) + 16;
+  AL(c.d_partial, c.n_partial);
+  AL(c.d_sc, 2);
+#undef UP
+#undef AL
+  he = hipHostMalloc((void **)&c.h_sc, 2 * sizeof(PcgScalars), hipHostMallocDefault);
+  if (he != hipSuccess) return bad(he);
+  std::memset(c.h_sc, 0, 2 * sizeof(PcgScalars));
+  if ((he = hipMemset(c.d_err, 0, sizeof(int32_t))) != hipSuccess) return bad(he);
+  if ((he = hipMemset(c.d_phi, 0, c.n_v * sizeof(double))) != hipSuccess) return bad(he);
+  if ((he = hipMemset(c.d_sc, 0, 2 * sizeof(PcgScalars))) != hipSuccess) return bad(he);
+  if ((he = hipDeviceSynchronize()) != hipSuccess) return bad(he);
+  *out = h;
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_destroy(fnpf_ctx ctx) {
+  if (!ctx) return FNPF_ERR_ARG;
+  (void)hipDeviceSynchronize();
+  free_all(ctx->c);
+  delete ctx;
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_sizes(fnpf_ctx ctx, int64_t *n_v, int64_t *n_s, int64_t *n_e, int32_t *n_colours) {
+  if (!ctx) return FNPF_ERR_ARG;
+  if (n_v) *n_v = ctx->c.n_v;
+  if (n_s) *n_s = ctx->c.n_s;
+  if (n_e) *n_e = ctx->c.n_e;
+  if (n_colours) *n_colours = (int32_t)ctx->c.colours.size();
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy) {
+  if (!ctx || !xy) return ctx ? fail(&ctx->c, FNPF_ERR_ARG, "xy is NULL") : FNPF_ERR_ARG;
+  std::memcpy(xy, ctx->c.h_node_xy.data(), ctx->c.h_node_xy.size() * sizeof(double));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_enable_fp32(fnpf_ctx ctx) {
+  if (!ctx) return FNPF_ERR_ARG;
+  return ensure32(ctx->c);
+}
+
+fnpf_status fnpf_geom(fnpf_ctx ctx, const double *eta, const double *h, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!eta || !h) return fail(&c, FNPF_ERR_ARG, "fnpf_geom: eta and h must be device pointers");
+  return geom_impl(c, eta, h, (hipStream_t)stream);
+}
+
+fnpf_status fnpf_export_geometry(fnpf_ctx ctx, fnpf_dtype dtype, void *G, double *diag, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype != FNPF_F64 && dtype != FNPF_F32) return fail(&c, FNPF_ERR_ARG, "bad dtype");
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_export_geometry before fnpf_geom");
+  if (dtype == FNPF_F32 && !c.have_geom32) return fail(&c, FNPF_ERR_STATE, "no FP32 factors (enable the mixed path)");
+  const size_t ng = (size_t)c.n_e * c.ng * c.np;
+  if (G) {
+    if (dtype == FNPF_F64)
+      HIPCHK(hipMemcpyAsync(G, c.d_G64, ng * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else
+      HIPCHK(hipMemcpyAsync(G, c.d_G32, ng * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  if (diag) HIPCHK(hipMemcpyAsync(diag, c.d_diag, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_laplace_apply(fnpf_ctx ctx, fnpf_dtype dtype, const void *x, void *y, int32_t mask, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!x || !y) return fail(&c, FNPF_ERR_ARG, "fnpf_laplace_apply: x and y must be device pointers");
+  if (x == y) return fail(&c, FNPF_ERR_ARG, "fnpf_laplace_apply: x and y must not alias");
+  if (dtype != FNPF_F64 && dtype != FNPF_F32) return fail(&c, FNPF_ERR_ARG, "bad dtype");
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_laplace_apply before fnpf_geom");
+  if (dtype == FNPF_F32 && !c.have_geom32)
+    return fail(&c, FNPF_ERR_STATE, "no FP32 factors: call fnpf_enable_fp32, then fnpf_geom");
+  HIPCHK(launch_apply(c, dtype, x, y, mask != 0, nullptr, nullptr, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_neumann_load(fnpf_ctx ctx, const double *q, double *f, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!q || !f) return fail(&c, FNPF_ERR_ARG, "fnpf_neumann_load: q and f must be device pointers");
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_neumann_load before fnpf_geom");
+  HIPCHK(launch_neumann(c, q, f, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_solve(fnpf_ctx ctx, const double *phis, const double *f, double *phi, const fnpf_solve_opts *opts,
+                       fnpf_solve_info *info, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!phis || !phi) return fail(&c, FNPF_ERR_ARG, "fnpf_solve: phi_surface and phi must be device pointers");
+  fnpf_solve_opts o;
+  fnpf_default_opts(&o);
+  if (opts) o = *opts;
+  fnpf_status st = validate_opts(c, o);
+  if (st != FNPF_OK) return st;
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_solve before fnpf_geom");
+  if (o.precision == 1 && !c.have_geom32)
+    return fail(&c, FNPF_ERR_STATE, "mixed solve needs FP32 factors: call fnpf_enable_fp32, then fnpf_geom");
+  return solve_impl(c, phis, f, phi, o, info, (hipStream_t)stream);
+}
+
+fnpf_status fnpf_w_surface(fnpf_ctx ctx, const double *phi, double *w, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!phi || !w) return fail(&c, FNPF_ERR_ARG, "fnpf_w_surface: phi and w_s must be device pointers");
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_w_surface before fnpf_geom");
+  HIPCHK(launch_wsurf(c, phi, w, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_rhs(fnpf_ctx ctx, const double *eta, const double *phis, const double *w, double *deta,
+                     double *dphi, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!eta || !phis || !w || !deta || !dphi) return fail(&c, FNPF_ERR_ARG, "fnpf_rhs: null device pointer");
+  if (deta == eta || deta == phis || dphi == eta || dphi == phis)
+    return fail(&c, FNPF_ERR_ARG, "fnpf_rhs: outputs must not alias the inputs");
+  RkStageArgs a{};
+  a.stage = -1;
+  a.out_e = deta;
+  a.out_p = dphi;
+  HIPCHK(launch_rhs(c, eta, phis, w, a, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_set_relaxation(fnpf_ctx ctx, const double *cr, const double *ec, const double *es, const double *pc,
+                                const double *ps, double omega, double t_ramp) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!cr) {
+    c.have_relax = false;
+    return FNPF_OK;
+  }
+  if (!ec || !es || !pc || !ps) return fail(&c, FNPF_ERR_ARG, "fnpf_set_relaxation: null host array");
+  for (int64_t n = 0; n < c.n_s; ++n)
+    if (!(cr[n] >= 0.0 && cr[n] <= 1.0)) return fail(&c, FNPF_ERR_ARG, "relaxation weights must lie in [0, 1]");
+  const double *src[5] = {cr, ec, es, pc, ps};
+  double **dst[5] = {&c.d_cr, &c.d_rec, &c.d_res, &c.d_rpc, &c.d_rps};
+  for (int k = 0; k < 5; ++k) {
+    if (!*dst[k]) HIPCHK(dalloc(dst[k], c.n_s));
+    HIPCHK(hipMemcpy(*dst[k], src[k], c.n_s * sizeof(double), hipMemcpyHostToDevice));
+  }
+  c.relax_omega = omega;
+  c.relax_tramp = t_ramp;
+  c.have_relax = true;
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double *h, double t, double dt,
+                          const fnpf_solve_opts *opts, double *tape, fnpf_solve_info *info, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  hipStream_t s = (hipStream_t)stream;
+  if (!eta || !phis || !h) return fail(&c, FNPF_ERR_ARG, "fnpf_rk4_step: eta, phi_s and h must be device pointers");
+  if (!(dt > 0.0)) return fail(&c, FNPF_ERR_ARG, "fnpf_rk4_step: dt must be > 0");
+  fnpf_solve_opts o;
+  fnpf_default_opts(&o);
+  if (opts) o = *opts;
+  fnpf_status st = validate_opts(c, o);
+  if (st != FNPF_OK) return st;
+  if (o.precision == 1) {
+    st = ensure32(c);
+    if (st != FNPF_OK) return st;
+  }
+  if (info) std::memset(info, 0, 4 * sizeof(fnpf_solve_info));
+  const double *ein = eta, *pin = phis;
+  for (int stg = 0; stg < 4; ++stg) {
+    st = geom_impl(c, ein, h, s);
+    if (st != FNPF_OK) return st;
+    st = solve_impl(c, pin, nullptr, c.d_phi, o, info ? info + stg : nullptr, s);
+    if (st != FNPF_OK) return st;
+    if (tape) HIPCHK(hipMemcpyAsync(tape + (size_t)stg * c.n_v, c.d_phi, c.n_v * sizeof(double),
+                                    hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_wsurf(c, c.d_phi, c.d_w, s));
+    RkStageArgs a{};
+    a.eta0 = eta;
+    a.phi0 = phis;
+    a.acc_e = c.d_acc_e;
+    a.acc_p = c.d_acc_p;
+    a.stage = stg;
+    a.bdt = kRkB[stg] * dt;
+    if (stg < 3) {
+      a.cdt = kRkC[stg + 1] * dt;
+      a.out_e = c.d_sa[stg & 1];
+      a.out_p = c.d_sp[stg & 1];
+    } else {
+      a.out_e = eta;
+      a.out_p = phis;
+      if (c.have_relax) {
+        const double tn = t + dt;
+        double r = 1.0;
+        if (c.relax_tramp > 0.0 && tn < c.relax_tramp) r = 0.5 * (1.0 - std::cos(M_PI * tn / c.relax_tramp));
+        a.cr = c.d_cr;
+        a.ec = c.d_rec;
+        a.es = c.d_res;
+        a.pc = c.d_rpc;
+        a.ps = c.d_rps;
+        a.rc = r * std::cos(c.relax_omega * tn);
+        a.rs = r * std::sin(c.relax_omega * tn);
+      }
+    }
+    HIPCHK(launch_rhs(c, ein, pin, c.d_w, a, s));
+    ein = a.out_e;
+    pin = a.out_p;
+  }
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_get_warm_start(fnpf_ctx ctx, double *phi, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!phi) return fail(&c, FNPF_ERR_ARG, "phi is NULL");
+  HIPCHK(hipMemcpyAsync(phi, c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_set_warm_start(fnpf_ctx ctx, const double *phi, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (phi)
+    HIPCHK(hipMemcpyAsync(c.d_phi, phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  else
+    HIPCHK(launch_fill(c.d_phi, 0.0, c.n_v, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_sync(fnpf_ctx ctx, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  return check_err_flag(c, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Internal declarations shared by the host driver and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fnpf.h"
+
+namespace fnpf {
+
+constexpr int kMaxP = 8;
+constexpr int kMaxN1 = kMaxP + 1;
+constexpr int kDStride = kMaxN1 * kMaxN1;  // per-degree stride of the D tables
+constexpr uint8_t kFirst = 1;              // column is the first writer of this horizontal node
+constexpr uint8_t kLast = 2;               // column is the last writer (sees the final sum)
+
+// Horizontal metric components stored per (column, local horizontal node).
+// 3D: A = J_h^{-1} (A00, A01, A10, A11), det J_h, J_h (x_xi, x_eta, y_xi, y_eta).
+// 2D: 1/x_xi, x_xi.
+constexpr int kHm3 = 9;
+constexpr int kHm2 = 2;
+
+// Device-side PCG scalars (FP64 even for the FP32 inner solve).
+struct PcgScalars {
+  double rz;       // r^T z of the current iterate
+  double rr;       // r^T r of the current iterate
+  double pq;       // p^T A p
+  double alpha;
+  double beta;
+  double tol2;     // squared absolute stopping threshold
+  double bnorm2;   // ||b||^2
+  double rr0;      // r^T r at the start of this (inner) solve
+  int32_t done;
+  int32_t iters;
+  int32_t breakdown;
+  int32_t pad;
+};
+
+// Launch helpers for one colour of the column colouring.
+struct ColourRange {
+  int32_t offset;
+  int32_t count;
+};
+
+template <typename T>
+struct DevBuf {
+  T *ptr = nullptr;
+  size_t n = 0;
+};
+
+struct Ctx;
+
+// Kernel launchers (kernels_*.hip). All return hipSuccess or the launch error.
+hipError_t upload_constants(int device);
+hipError_t launch_geom(Ctx &c, const double *eta, const double *h, hipStream_t s);
+hipError_t launch_apply(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
+                        const int32_t *skip, hipStream_t s);
+hipError_t launch_neumann(Ctx &c, const double *q, double *f, hipStream_t s);
+hipError_t launch_wsurf(Ctx &c, const double *phi, double *w, hipStream_t s);
+struct RkStageArgs {
+  const double *eta0;   // state at the start of the step
+  const double *phi0;
+  double *acc_e;        // stage accumulators
+  double *acc_p;
+  double *out_e;        // next stage state (stage < 3) or the final state (stage 3, may alias eta0)
+  double *out_p;
+  double bdt;           // b_s dt
+  double cdt;           // c_{s+1} dt (stage < 3)
+  int stage;            // 0..3, or -1: plain RHS into out_e/out_p
+  // relaxation (stage 3 only): f <- (1-cr) f + cr (rc f_c + rs f_s)
+  const double *cr, *ec, *es, *pc, *ps;
+  double rc, rs;
+};
+hipError_t launch_rhs(Ctx &c, const double *eta, const double *phi_s, const double *w, const RkStageArgs &a,
+                      hipStream_t s);
+
+// vector kernels (kernels_vec.hip)
+hipError_t launch_set_lift(double *v, const double *phis, int64_t n_v, int64_t n_s, hipStream_t s);
+hipError_t launch_copy_top(double *x, const double *phis, int64_t n_v, int64_t n_s, hipStream_t s);
+hipError_t launch_bnorm(const double *f, const double *y, int64_t n_v, int64_t n_s, double *partial,
+                        PcgScalars *sc, double rtol, double atol, hipStream_t s);
+template <typename T>
+hipError_t launch_pcg_init(const double *f, const T *Ax, T *r, T *p, const T *dinv, int64_t n_v, int64_t n_s,
+                           double *partial, PcgScalars *sc, bool relative_tol, double inner_rtol, hipStream_t s);
+hipError_t launch_resid_to32(const double *f, const double *Ax, float *r, float *p, float *d, const float *dinv,
+                             int64_t n_v, int64_t n_s, double *partial, PcgScalars *outer, PcgScalars *inner,
+                             double inner_rtol, hipStream_t s);
+hipError_t launch_finalize_pq(const double *partial, int np, PcgScalars *sc, hipStream_t s);
+template <typename T, typename TX>
+hipError_t launch_pcg_update(TX *x, T *r, const T *p, const T *q, const T *dinv, int64_t n_v, double *partial,
+                             PcgScalars *sc, hipStream_t s);
+hipError_t launch_finalize_rz(const double *partial, int np, PcgScalars *sc, hipStream_t s);
+template <typename T>
+hipError_t launch_pcg_dir(T *p, const T *r, const T *dinv, int64_t n_v, PcgScalars *sc, hipStream_t s);
+hipError_t launch_add_f32(double *x, const float *d, int64_t n_v, hipStream_t s);
+hipError_t launch_cast_f32(const double *a, float *b, int64_t n, hipStream_t s);
+hipError_t launch_fill(double *v, double val, int64_t n, hipStream_t s);
+hipError_t launch_zero_i32(int32_t *v, int64_t n, hipStream_t s);
+
+constexpr int kVecBlocks = 1024;   // fixed grid of the grid-stride vector kernels (deterministic partials)
+constexpr int kVecThreads = 256;
+
+struct Ctx {
+  // mesh
+  int dim = 3, p = 1, nz = 1, n_eh = 0;
+  int64_t n_s = 0, n_v = 0, n_e = 0;
+  int nh = 1, np = 1, ng = 6;
+  double g = 9.81;
+  std::vector<int32_t> h_eh_nodes;
+  std::vector<double> h_node_xy;          // [n_s][dim-1]
+  std::vector<double> h_layer_s;          // [nz+1]
+  std::vector<double> h_sigma;            // [p nz + 1]
+  std::vector<ColourRange> colours;
+  int max_colour_blocks = 0;              // sum over colours of apply blocks
+  // device mesh data
+  int32_t *d_eh_nodes = nullptr;
+  int32_t *d_cols = nullptr;              // columns grouped by colour
+  uint8_t *d_flags = nullptr;             // [n_eh][nh] first/last writer flags
+  int32_t *d_face_tag = nullptr;          // [n_eh][2(dim-1)]
+  double *d_hm = nullptr;                 // [ncomp][n_eh*nh]
+  double *d_sigma = nullptr;              // [p nz + 1]
+  double *d_layer_s = nullptr;            // [nz + 1]
+  double *d_mlump_w = nullptr;            // [n_s] sum_e w_i w_j w_p det J_h (w recovery denominator)
+  double *d_mlump_s = nullptr;            // [n_s] sum_e w_i w_j det J_h (surface mass)
+  // geometry state
+  double *d_G64 = nullptr;
+  float *d_G32 = nullptr;
+  double *d_diag = nullptr;
+  double *d_dinv = nullptr;
+  float *d_dinv32 = nullptr;
+  const double *geom_eta = nullptr;       // eta/h of the last fnpf_geom (caller-owned, used by w recovery)
+  const double *geom_h = nullptr;
+  bool have_geom = false;
+  bool have_geom32 = false;
+  bool want32 = false;
+  int32_t *d_err = nullptr;               // device error flag (GEOM)
+  // workspaces
+  double *d_r = nullptr, *d_p = nullptr, *d_q = nullptr, *d_phi = nullptr;
+  float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr, *d_d32 = nullptr;
+  double *d_sa[2] = {nullptr, nullptr};   // stage states (eta) ping-pong
+  double *d_sp[2] = {nullptr, nullptr};   // stage states (phi_s)
+  double *d_acc_e = nullptr, *d_acc_p = nullptr;
+  double *d_w = nullptr;                  // recovered w at the surface
+  double *d_geoH = nullptr, *d_geoh = nullptr;    // eta + h and h of the last fnpf_geom
+  double *d_wnum = nullptr, *d_nk = nullptr, *d_nd = nullptr;  // surface scatter scratch
+  double *d_partial = nullptr;
+  int n_partial = 0;
+  PcgScalars *d_sc = nullptr;             // [2]: outer/plain, inner
+  PcgScalars *h_sc = nullptr;             // pinned host mirror
+  // relaxation
+  double *d_cr = nullptr, *d_rec = nullptr, *d_res = nullptr, *d_rpc = nullptr, *d_rps = nullptr;
+  double relax_omega = 0.0, relax_tramp = 0.0;
+  bool have_relax = false;
+  std::string err;
+  int device = 0;
+};
+
+// host setup (setup.cpp)
+void gll_host(int p, double *x, double *w, double *D);
+std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double> &hm, std::vector<uint8_t> &flags,
+                            std::vector<int32_t> &cols, std::vector<double> &mlump_w, std::vector<double> &mlump_s);
+
+}  // namespace fnpf

@@ -1,0 +1,810 @@
+// Column kernels of the extruded spectral-element mesh (gfx950, wave64).
+//
+// Work decomposition shared by every kernel here: a workgroup holds CPB
+// element columns; one thread per (column, horizontal GLL node (i, j)) walks
+// its vertical node line bottom to top, layer by layer, keeping the line in
+// registers.  Element tiles of one layer are staged in LDS for the xi/eta
+// contractions; the zeta contraction stays in registers.  The node level
+// shared by two stacked layers is carried in a register, so each thread
+// writes every volume node of its line exactly once.
+//
+// Assembly across columns uses a colouring of the columns (columns of one
+// colour share no horizontal node), one launch per colour, no atomics: the
+// first colour that touches a horizontal node stores, later colours
+// read-add-store, and the last one sees the assembled value (used for fused
+// dot products, w recovery and the RK4 update).
+//
+// Notation: D is the GLL derivative matrix, W the GLL weights, G the six
+// (3D) or three (2D) symmetric per-point factors w_q det(J) (J^-1 J^-T)_ab of
+// the Laplace bilinear form (paper Eq. 4).  Volume vectors are layer-major:
+// index = v * n_s + hn.
+
+#include <hip/hip_runtime.h>
+
+#include "fnpf_internal.h"
+
+namespace fnpf {
+
+__constant__ double c_D64[kMaxN1 * kDStride];
+__constant__ float c_D32[kMaxN1 * kDStride];
+__constant__ double c_W[kMaxN1 * kMaxN1];
+
+hipError_t upload_constants(int /*device*/) {
+  static double D64[kMaxN1 * kDStride];
+  static float D32[kMaxN1 * kDStride];
+  static double W[kMaxN1 * kMaxN1];
+  for (int p = 1; p <= kMaxP; ++p) {
+    double x[kMaxN1], w[kMaxN1], D[kMaxN1 * kMaxN1];
+    gll_host(p, x, w, D);
+    const int n1 = p + 1;
+    for (int i = 0; i < n1 * n1; ++i) {
+      D64[p * kDStride + i] = D[i];
+      D32[p * kDStride + i] = (float)D[i];
+    }
+    for (int i = 0; i < n1; ++i) W[p * kMaxN1 + i] = w[i];
+  }
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_D64), D64, sizeof(D64));
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_D32), D32, sizeof(D32));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_W), W, sizeof(W));
+}
+
+template <int P, int DIM>
+struct Sh {
+  static constexpr int N1 = P + 1;
+  static constexpr int NH = DIM == 3 ? N1 * N1 : N1;
+  static constexpr int NP = NH * N1;
+  static constexpr int NG = DIM == 3 ? 6 : 3;
+  static constexpr int CPB = 256 / NH;
+  static constexpr int NT = CPB * NH;
+};
+
+template <typename T>
+__device__ __forceinline__ T dmat(int P, int r, int c);
+template <>
+__device__ __forceinline__ double dmat<double>(int P, int r, int c) {
+  return c_D64[P * kDStride + r * (P + 1) + c];
+}
+template <>
+__device__ __forceinline__ float dmat<float>(int P, int r, int c) {
+  return c_D32[P * kDStride + r * (P + 1) + c];
+}
+__device__ __forceinline__ double wgt(int P, int i) { return c_W[P * kMaxN1 + i]; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deterministic block sum: wave shuffles, then wave partials in LDS summed in order.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v) {
+  constexpr int NW = (NT + 63) / 64;
+  __shared__ double s_red[NW];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) s_red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NW; ++k) s += s_red[k];
+  return s;
+}
+
+// Assemble one value into a global vector following the colour schedule.
+// Returns the value now stored (the assembled one when this column is last).
+template <typename T>
+__device__ __forceinline__ T scatter(T *y, int64_t idx, T val, uint8_t fl) {
+  if (fl & kFirst) {
+    y[idx] = val;
+    return val;
+  }
+  T s = y[idx] + val;
+  y[idx] = s;
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stiffness apply y = A x (paper Eq. 4), sum-factorised, stored geometric factors.
+// ---------------------------------------------------------------------------------------------
+template <int P, int DIM, typename T, bool MASK, bool DOT>
+__global__ __launch_bounds__(256) void k_apply(const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ G,
+                                               const int32_t *__restrict__ eh_nodes, const uint8_t *__restrict__ flags,
+                                               const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
+                                               double *__restrict__ partial, const int32_t *__restrict__ skip) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, NG = S::NG, CPB = S::CPB;
+  __shared__ T su[CPB * NP];
+  __shared__ T sx[CPB * NP];
+  __shared__ T sy[DIM == 3 ? CPB * NP : 1];
+  if (skip != nullptr && *skip) return;
+
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? cols[ci] : 0;
+  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
+  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
+
+  T Dri[N1], Drj[N1], Dci[N1], Dcj[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    Dri[m] = dmat<T>(P, i, m);
+    Dci[m] = dmat<T>(P, m, i);
+    Drj[m] = dmat<T>(P, j, m);
+    Dcj[m] = dmat<T>(P, m, j);
+  }
+  T *u_c = su + lc * NP;
+  T *x_c = sx + lc * NP;
+  T *y_c = sy + (DIM == 3 ? lc * NP : 0);
+
+  T ucol[N1];
+  T carry = T(0);
+  double dot = 0.0;
+  ucol[0] = active ? x[hn] : T(0);
+  const int64_t e0 = (int64_t)col * nz;
+  const int vtop = P * nz;
+
+  for (int l = 0; l < nz; ++l) {
+#pragma unroll
+    for (int k = 1; k < N1; ++k) ucol[k] = active ? x[(int64_t)(l * P + k) * n_s + hn] : T(0);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) u_c[k * NH + t] = ucol[k];
+    __syncthreads();
+
+    const T *Ge = G + (e0 + l) * (int64_t)(NG * NP);
+    T vz[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      T ux = T(0), uy = T(0), uz = T(0);
+#pragma unroll
+      for (int m = 0; m < N1; ++m) ux += Dri[m] * u_c[k * NH + j * N1 + m];
+      if constexpr (DIM == 3) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) uy += Drj[m] * u_c[k * NH + m * N1 + i];
+      }
+#pragma unroll
+      for (int m = 0; m < N1; ++m) uz += dmat<T>(P, k, m) * ucol[m];
+      const int q = k * NH + t;
+      if constexpr (DIM == 3) {
+        T g00 = active ? Ge[0 * NP + q] : T(0);
+        T g01 = active ? Ge[1 * NP + q] : T(0);
+        T g02 = active ? Ge[2 * NP + q] : T(0);
+        T g11 = active ? Ge[3 * NP + q] : T(0);
+        T g12 = active ? Ge[4 * NP + q] : T(0);
+        T g22 = active ? Ge[5 * NP + q] : T(0);
+        x_c[q] = g00 * ux + g01 * uy + g02 * uz;
+        y_c[q] = g01 * ux + g11 * uy + g12 * uz;
+        vz[k] = g02 * ux + g12 * uy + g22 * uz;
+      } else {
+        T g00 = active ? Ge[0 * NP + q] : T(0);
+        T g01 = active ? Ge[1 * NP + q] : T(0);
+        T g11 = active ? Ge[2 * NP + q] : T(0);
+        x_c[q] = g00 * ux + g01 * uz;
+        vz[k] = g01 * ux + g11 * uz;
+      }
+    }
+    __syncthreads();
+
+    T yk[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int m = 0; m < N1; ++m) acc += Dci[m] * x_c[k * NH + j * N1 + m];
+      if constexpr (DIM == 3) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) acc += Dcj[m] * y_c[k * NH + m * N1 + i];
+      }
+#pragma unroll
+      for (int m = 0; m < N1; ++m) acc += dmat<T>(P, m, k) * vz[m];
+      yk[k] = acc;
+    }
+    yk[0] += carry;
+    if (active) {
+      const int kend = (l == nz - 1) ? N1 : P;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        if (k < kend) {
+          const int v = l * P + k;
+          const int64_t idx = (int64_t)v * n_s + hn;
+          T val;
+          if (MASK && v == vtop) {
+            y[idx] = T(0);
+            val = T(0);
+          } else {
+            val = scatter(y, idx, yk[k], fl);
+          }
+          if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
+        }
+      }
+    }
+    carry = yk[P];
+    ucol[0] = ucol[P];
+  }
+  if constexpr (DOT) {
+    double s = block_sum<S::NT>(dot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Geometry (paper Sec. 3.1.2, Step 4.1): z = -h + sigma_v (eta + h) per node level; per point
+// G = w det(J) J^-1 J^-T with J = [[J_h, 0], [z_xi, z_eta, z_zeta]]; assembled Jacobi diagonal.
+// ---------------------------------------------------------------------------------------------
+template <int P, int DIM>
+__global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, const double *__restrict__ hb,
+                                              const double *__restrict__ hm, int64_t hstride,
+                                              const int32_t *__restrict__ eh_nodes, const uint8_t *__restrict__ flags,
+                                              const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
+                                              const double *__restrict__ sigma, const double *__restrict__ layer_s,
+                                              double *__restrict__ G64, float *__restrict__ G32,
+                                              double *__restrict__ diag, double *__restrict__ dinv,
+                                              float *__restrict__ dinv32, double *__restrict__ Hout,
+                                              double *__restrict__ hout, int32_t *__restrict__ err) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, NG = S::NG, CPB = S::CPB;
+  __shared__ double sH[CPB * NH];
+  __shared__ double sh[CPB * NH];
+  __shared__ double s0[CPB * NP];
+  __shared__ double s1[DIM == 3 ? CPB * NP : 1];
+
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? cols[ci] : 0;
+  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
+  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
+  const int64_t ho = (int64_t)col * NH + t;
+
+  const double Hn = active ? eta[hn] + hb[hn] : 1.0;
+  const double hnv = active ? hb[hn] : 0.0;
+  if (active && !(Hn > 0.0)) *err = 1;
+  if (active && (fl & kFirst)) {
+    Hout[hn] = Hn;
+    hout[hn] = hnv;
+  }
+  sH[lc * NH + t] = Hn;
+  sh[lc * NH + t] = hnv;
+  __syncthreads();
+  double Hx = 0.0, hx = 0.0, Hy = 0.0, hy = 0.0;
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    Hx += dmat<double>(P, i, m) * sH[lc * NH + j * N1 + m];
+    hx += dmat<double>(P, i, m) * sh[lc * NH + j * N1 + m];
+  }
+  if constexpr (DIM == 3) {
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      Hy += dmat<double>(P, j, m) * sH[lc * NH + m * N1 + i];
+      hy += dmat<double>(P, j, m) * sh[lc * NH + m * N1 + i];
+    }
+  }
+  double A00, A01 = 0.0, A10 = 0.0, A11 = 0.0, detJh;
+  if constexpr (DIM == 3) {
+    A00 = active ? hm[0 * hstride + ho] : 1.0;
+    A01 = active ? hm[1 * hstride + ho] : 0.0;
+    A10 = active ? hm[2 * hstride + ho] : 0.0;
+    A11 = active ? hm[3 * hstride + ho] : 1.0;
+    detJh = active ? hm[4 * hstride + ho] : 1.0;
+  } else {
+    A00 = active ? hm[0 * hstride + ho] : 1.0;
+    detJh = active ? hm[1 * hstride + ho] : 1.0;
+  }
+  const double wh = DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i);
+  double Dci2[N1], Dcj2[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    double a = dmat<double>(P, m, i), b = dmat<double>(P, m, j);
+    Dci2[m] = a * a;
+    Dcj2[m] = b * b;
+  }
+  const double Dii = dmat<double>(P, i, i), Djj = dmat<double>(P, j, j);
+
+  double carry = 0.0;
+  const int64_t e0 = (int64_t)col * nz;
+  for (int l = 0; l < nz; ++l) {
+    const double zz = 0.5 * (layer_s[l + 1] - layer_s[l]) * Hn;   // z_zeta (sigma-linear per layer)
+    double gz[N1], c01[N1], c02[N1], c12[N1];
+    double *Ge64 = G64 + (e0 + l) * (int64_t)(NG * NP);
+    float *Ge32 = G32 ? G32 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const double sg = sigma[l * P + k];
+      const double zx = -hx + sg * Hx;
+      const double f = wh * wgt(P, k) * detJh * zz;
+      const int q = k * NH + t;
+      if constexpr (DIM == 3) {
+        const double zy = -hy + sg * Hy;
+        const double b2x = -(zx * A00 + zy * A10) / zz;
+        const double b2y = -(zx * A01 + zy * A11) / zz;
+        const double b2z = 1.0 / zz;
+        const double g00 = f * (A00 * A00 + A01 * A01);
+        const double g01 = f * (A00 * A10 + A01 * A11);
+        const double g02 = f * (A00 * b2x + A01 * b2y);
+        const double g11 = f * (A10 * A10 + A11 * A11);
+        const double g12 = f * (A10 * b2x + A11 * b2y);
+        const double g22 = f * (b2x * b2x + b2y * b2y + b2z * b2z);
+        if (active) {
+          Ge64[0 * NP + q] = g00;
+          Ge64[1 * NP + q] = g01;
+          Ge64[2 * NP + q] = g02;
+          Ge64[3 * NP + q] = g11;
+          Ge64[4 * NP + q] = g12;
+          Ge64[5 * NP + q] = g22;
+          if (Ge32) {
+            Ge32[0 * NP + q] = (float)g00;
+            Ge32[1 * NP + q] = (float)g01;
+            Ge32[2 * NP + q] = (float)g02;
+            Ge32[3 * NP + q] = (float)g11;
+            Ge32[4 * NP + q] = (float)g12;
+            Ge32[5 * NP + q] = (float)g22;
+          }
+        }
+        s0[lc * NP + q] = g00;
+        s1[lc * NP + q] = g11;
+        gz[k] = g22;
+        c01[k] = g01;
+        c02[k] = g02;
+        c12[k] = g12;
+      } else {
+        const double b1x = -zx * A00 / zz;
+        const double b1z = 1.0 / zz;
+        const double g00 = f * A00 * A00;
+        const double g01 = f * A00 * b1x;
+        const double g11 = f * (b1x * b1x + b1z * b1z);
+        if (active) {
+          Ge64[0 * NP + q] = g00;
+          Ge64[1 * NP + q] = g01;
+          Ge64[2 * NP + q] = g11;
+          if (Ge32) {
+            Ge32[0 * NP + q] = (float)g00;
+            Ge32[1 * NP + q] = (float)g01;
+            Ge32[2 * NP + q] = (float)g11;
+          }
+        }
+        s0[lc * NP + q] = g00;
+        gz[k] = g11;
+        c01[k] = g01;
+      }
+    }
+    __syncthreads();
+    double dk[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      double d = 0.0;
+#pragma unroll
+      for (int m = 0; m < N1; ++m) d += Dci2[m] * s0[lc * NP + k * NH + j * N1 + m];
+#pragma unroll
+      for (int m = 0; m < N1; ++m) {
+        const double a = dmat<double>(P, m, k);
+        d += a * a * gz[m];
+      }
+      const double Dkk = dmat<double>(P, k, k);
+      if constexpr (DIM == 3) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) d += Dcj2[m] * s1[lc * NP + k * NH + m * N1 + i];
+        d += 2.0 * (Dii * Djj * c01[k] + Dii * Dkk * c02[k] + Djj * Dkk * c12[k]);
+      } else {
+        d += 2.0 * Dii * Dkk * c01[k];
+      }
+      dk[k] = d;
+    }
+    __syncthreads();
+    dk[0] += carry;
+    if (active) {
+      const int kend = (l == nz - 1) ? N1 : P;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        if (k < kend) {
+          const int v = l * P + k;
+          const int64_t idx = (int64_t)v * n_s + hn;
+          const double val = scatter(diag, idx, dk[k], fl);
+          if (fl & kLast) {
+            const double di = (v == P * nz) ? 0.0 : 1.0 / val;
+            dinv[idx] = di;
+            if (dinv32) dinv32[idx] = (float)di;
+          }
+        }
+      }
+    }
+    carry = dk[P];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Neumann load (paper Eq. 1): f_i = sum over bottom and wall/body faces of int (q.n) l_i dS.
+// ---------------------------------------------------------------------------------------------
+template <int P, int DIM>
+__global__ __launch_bounds__(256) void k_neumann(const double *__restrict__ qv, double *__restrict__ f,
+                                                 const double *__restrict__ Hg, const double *__restrict__ hg,
+                                                 const double *__restrict__ hm, int64_t hstride,
+                                                 const int32_t *__restrict__ eh_nodes,
+                                                 const uint8_t *__restrict__ flags, const int32_t *__restrict__ tags,
+                                                 const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
+                                                 int64_t n_v, const double *__restrict__ sigma,
+                                                 const double *__restrict__ layer_s) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, CPB = S::CPB;
+  __shared__ double sH[CPB * NH];
+  __shared__ double sh[CPB * NH];
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? cols[ci] : 0;
+  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
+  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
+  const int64_t ho = (int64_t)col * NH + t;
+  const double Hn = active ? Hg[hn] : 1.0;
+  sH[lc * NH + t] = Hn;
+  sh[lc * NH + t] = active ? hg[hn] : 0.0;
+  __syncthreads();
+  double Hx = 0.0, hx = 0.0, Hy = 0.0, hy = 0.0;
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    Hx += dmat<double>(P, i, m) * sH[lc * NH + j * N1 + m];
+    hx += dmat<double>(P, i, m) * sh[lc * NH + j * N1 + m];
+    if constexpr (DIM == 3) {
+      Hy += dmat<double>(P, j, m) * sH[lc * NH + m * N1 + i];
+      hy += dmat<double>(P, j, m) * sh[lc * NH + m * N1 + i];
+    }
+  }
+  if (!active) return;   // no barriers below
+  constexpr int NS = DIM == 3 ? 4 : 2;
+  int tg[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) tg[s] = tags ? tags[(int64_t)col * NS + s] : 0;
+  const int nlev = P * nz + 1;
+  for (int v = 0; v < nlev; ++v) {
+    const int l = v == P * nz ? nz - 1 : v / P;
+    const int k = v - l * P;
+    const double sg = sigma[v];
+    const double zz = 0.5 * (layer_s[l + 1] - layer_s[l]) * Hn;
+    const double zx = -hx + sg * Hx;
+    const int64_t idx = (int64_t)v * n_s + hn;
+    // a node on a layer interface (k = 0 or P, inside the column) belongs to two layers:
+    // side faces of both layers contribute with their own vertical weights
+    double val = 0.0;
+    if constexpr (DIM == 3) {
+      const double xxi = hm[5 * hstride + ho], xet = hm[6 * hstride + ho];
+      const double yxi = hm[7 * hstride + ho], yet = hm[8 * hstride + ho];
+      const double zy = -hy + sg * Hy;
+      const double qx = qv[idx], qy = qv[n_v + idx], qz = qv[2 * n_v + idx];
+      const double wi = wgt(P, i), wj = wgt(P, j);
+      if (v == 0) {   // bottom: -(J_xi x J_eta)
+        const double nx = -(yxi * zy - zx * yet), ny = -(zx * xet - xxi * zy), nzv = -(xxi * yet - yxi * xet);
+        val += wi * wj * (qx * nx + qy * ny + qz * nzv);
+      }
+      // vertical weight of this node: one or two layers
+      for (int pass = 0; pass < 2; ++pass) {
+        int ll, kk;
+        if (pass == 0) {
+          ll = l;
+          kk = k;
+        } else {
+          if (!(k == 0 && l > 0)) break;
+          ll = l - 1;
+          kk = P;
+        }
+        const double zzl = 0.5 * (layer_s[ll + 1] - layer_s[ll]) * Hn;
+        const double wk = wgt(P, kk);
+        if (j == 0 && tg[0]) val += wi * wk * (-(-zzl * yxi) * qx - (zzl * xxi) * qy);
+        if (i == P && tg[1]) val += wj * wk * ((yet * zzl) * qx + (-xet * zzl) * qy);
+        if (j == P && tg[2]) val += wi * wk * ((-zzl * yxi) * qx + (zzl * xxi) * qy);
+        if (i == 0 && tg[3]) val += wj * wk * (-(yet * zzl) * qx - (-xet * zzl) * qy);
+      }
+      (void)zz;
+    } else {
+      const double xxi = hm[1 * hstride + ho];
+      const double qx = qv[idx], qz = qv[n_v + idx];
+      const double wi = wgt(P, i);
+      if (v == 0) val += wi * (zx * qx - xxi * qz);
+      for (int pass = 0; pass < 2; ++pass) {
+        int ll, kk;
+        if (pass == 0) {
+          ll = l;
+          kk = k;
+        } else {
+          if (!(k == 0 && l > 0)) break;
+          ll = l - 1;
+          kk = P;
+        }
+        const double zzl = 0.5 * (layer_s[ll + 1] - layer_s[ll]) * Hn;
+        const double wk = wgt(P, kk);
+        if (i == 0 && tg[0]) val += wk * (-zzl * qx);
+        if (i == P && tg[1]) val += wk * (zzl * qx);
+      }
+      (void)zz;
+    }
+    scatter(f, idx, val, fl);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Vertical velocity at the free surface (Steps 4.4-4.5): lumped-GLL L2 projection of dphi/dz.
+// For extruded elements d/dz = (1/z_zeta) d/dzeta and det J = det J_h z_zeta, and z_zeta at a
+// surface node is the same in every adjacent top element, so
+//   w_n = sum_e w_i w_j w_p det J_h (dphi/dzeta)_e / (z_zeta sum_e w_i w_j w_p det J_h).
+// ---------------------------------------------------------------------------------------------
+template <int P, int DIM>
+__global__ __launch_bounds__(256) void k_wsurf(const double *__restrict__ phi, const int32_t *__restrict__ eh_nodes,
+                                               const uint8_t *__restrict__ flags, const int32_t *__restrict__ cols,
+                                               int ncols, int nz, int64_t n_s, const double *__restrict__ hm,
+                                               int64_t hstride, const double *__restrict__ Hg,
+                                               const double *__restrict__ mlump, double half_ds,
+                                               double *__restrict__ wnum, double *__restrict__ w) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, CPB = S::CPB;
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  if (ci >= ncols) return;
+  const int col = cols[ci];
+  const int hn = eh_nodes[(int64_t)col * NH + t];
+  const uint8_t fl = flags[(int64_t)col * NH + t];
+  const int64_t ho = (int64_t)col * NH + t;
+  const int v0 = (nz - 1) * P;
+  double dz = 0.0;
+#pragma unroll
+  for (int m = 0; m < N1; ++m) dz += dmat<double>(P, P, m) * phi[(int64_t)(v0 + m) * n_s + hn];
+  const double det = DIM == 3 ? hm[4 * hstride + ho] : hm[1 * hstride + ho];
+  const double wq = (DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i)) * wgt(P, P);
+  const double num = scatter(wnum, hn, wq * det * dz, fl);
+  if (fl & kLast) w[hn] = num / (half_ds * Hg[hn] * mlump[hn]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Free-surface right-hand side (Step 4.6, Eqs. 2-3, lumped surface mass), fused with the ERK4
+// stage update (Sec. 3.2) and, after the last stage, the relaxation zones (Sec. 3.3).
+// ---------------------------------------------------------------------------------------------
+template <int P, int DIM>
+__global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ eta, const double *__restrict__ phs,
+                                             const double *__restrict__ wv, const int32_t *__restrict__ eh_nodes,
+                                             const uint8_t *__restrict__ flags, const int32_t *__restrict__ cols,
+                                             int ncols, const double *__restrict__ hm, int64_t hstride,
+                                             const double *__restrict__ mlump_s, double g, double *__restrict__ nk,
+                                             double *__restrict__ nd, RkStageArgs a) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, CPB = S::CPB;
+  __shared__ double se[CPB * NH];
+  __shared__ double sp[CPB * NH];
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? cols[ci] : 0;
+  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
+  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
+  const int64_t ho = (int64_t)col * NH + t;
+  const double en = active ? eta[hn] : 0.0;
+  const double pn = active ? phs[hn] : 0.0;
+  se[lc * NH + t] = en;
+  sp[lc * NH + t] = pn;
+  __syncthreads();
+  if (!active) return;
+  double exi = 0.0, pxi = 0.0, eet = 0.0, pet = 0.0;
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    exi += dmat<double>(P, i, m) * se[lc * NH + j * N1 + m];
+    pxi += dmat<double>(P, i, m) * sp[lc * NH + j * N1 + m];
+    if constexpr (DIM == 3) {
+      eet += dmat<double>(P, j, m) * se[lc * NH + m * N1 + i];
+      pet += dmat<double>(P, j, m) * sp[lc * NH + m * N1 + i];
+    }
+  }
+  double ex, ey = 0.0, px, py = 0.0, det, ws;
+  if constexpr (DIM == 3) {
+    const double A00 = hm[0 * hstride + ho], A01 = hm[1 * hstride + ho];
+    const double A10 = hm[2 * hstride + ho], A11 = hm[3 * hstride + ho];
+    det = hm[4 * hstride + ho];
+    ex = A00 * exi + A10 * eet;
+    ey = A01 * exi + A11 * eet;
+    px = A00 * pxi + A10 * pet;
+    py = A01 * pxi + A11 * pet;
+    ws = wgt(P, i) * wgt(P, j);
+  } else {
+    const double A = hm[0 * hstride + ho];
+    det = hm[1 * hstride + ho];
+    ex = A * exi;
+    px = A * pxi;
+    ws = wgt(P, i);
+  }
+  const double w = wv[hn];
+  const double ee = ex * ex + ey * ey;
+  const double Ek = -(ex * px + ey * py) + w * (1.0 + ee);
+  const double Ed = -g * en - 0.5 * (px * px + py * py) + 0.5 * w * w * (1.0 + ee);
+  const double ms = ws * det;
+  const double sk = scatter(nk, hn, ms * Ek, fl);
+  const double sd = scatter(nd, hn, ms * Ed, fl);
+  if (!(fl & kLast)) return;
+  const double ke = sk / mlump_s[hn];
+  const double kp = sd / mlump_s[hn];
+  if (a.stage < 0) {
+    a.out_e[hn] = ke;
+    a.out_p[hn] = kp;
+    return;
+  }
+  const double ae = (a.stage == 0 ? 0.0 : a.acc_e[hn]) + a.bdt * ke;
+  const double ap = (a.stage == 0 ? 0.0 : a.acc_p[hn]) + a.bdt * kp;
+  if (a.stage < 3) {
+    a.acc_e[hn] = ae;
+    a.acc_p[hn] = ap;
+    a.out_e[hn] = a.eta0[hn] + a.cdt * ke;
+    a.out_p[hn] = a.phi0[hn] + a.cdt * kp;
+    return;
+  }
+  double ne = a.eta0[hn] + ae;
+  double np = a.phi0[hn] + ap;
+  if (a.cr) {
+    const double c = a.cr[hn];
+    ne = (1.0 - c) * ne + c * (a.rc * a.ec[hn] + a.rs * a.es[hn]);
+    np = (1.0 - c) * np + c * (a.rc * a.pc[hn] + a.rs * a.ps[hn]);
+  }
+  a.out_e[hn] = ne;
+  a.out_p[hn] = np;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host-side dispatch over (dim, p).
+// ---------------------------------------------------------------------------------------------
+#define FNPF_DISPATCH(DIMV, PV, CALL)                       \
+  switch (PV) {                                             \
+    case 1: { constexpr int P_ = 1; CALL; } break;          \
+    case 2: { constexpr int P_ = 2; CALL; } break;          \
+    case 3: { constexpr int P_ = 3; CALL; } break;          \
+    case 4: { constexpr int P_ = 4; CALL; } break;          \
+    case 5: { constexpr int P_ = 5; CALL; } break;          \
+    case 6: { constexpr int P_ = 6; CALL; } break;          \
+    case 7: { constexpr int P_ = 7; CALL; } break;          \
+    case 8: { constexpr int P_ = 8; CALL; } break;          \
+    default: return hipErrorInvalidValue;                   \
+  }
+
+template <int P, int DIM>
+static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, hipStream_t s) {
+  using S = Sh<P, DIM>;
+  const int64_t hs = (int64_t)c.n_eh * c.nh;
+  for (const auto &cr : c.colours) {
+    if (cr.count == 0) continue;
+    const int nb = (cr.count + S::CPB - 1) / S::CPB;
+    k_geom<P, DIM><<<nb, S::NT, 0, s>>>(eta, h, c.d_hm, hs, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count,
+                                        c.nz, c.n_s, c.d_sigma, c.d_layer_s, c.d_G64, c.want32 ? c.d_G32 : nullptr,
+                                        c.d_diag, c.d_dinv, c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh,
+                                        c.d_err);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_geom(Ctx &c, const double *eta, const double *h, hipStream_t s) {
+  if (c.dim == 3) {
+    FNPF_DISPATCH(3, c.p, return (geom_impl<P_, 3>(c, eta, h, s)));
+  } else {
+    FNPF_DISPATCH(2, c.p, return (geom_impl<P_, 2>(c, eta, h, s)));
+  }
+  return hipSuccess;
+}
+
+template <int P, int DIM, typename T, bool MASK, bool DOT>
+static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *partial, const int32_t *skip,
+                             hipStream_t s) {
+  using S = Sh<P, DIM>;
+  int off = 0;
+  for (const auto &cr : c.colours) {
+    if (cr.count == 0) continue;
+    const int nb = (cr.count + S::CPB - 1) / S::CPB;
+    k_apply<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, G, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
+                                                       cr.count, c.nz, c.n_s, DOT ? partial + off : nullptr, skip);
+    off += nb;
+  }
+  return hipGetLastError();
+}
+
+template <int P, int DIM>
+static hipError_t apply_dispatch(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
+                                 const int32_t *skip, hipStream_t s) {
+  const bool dot = partial != nullptr;
+  if (dt == FNPF_F64) {
+    const double *xx = (const double *)x;
+    double *yy = (double *)y;
+    if (!mask) return apply_impl<P, DIM, double, false, false>(c, xx, yy, c.d_G64, nullptr, skip, s);
+    if (!dot) return apply_impl<P, DIM, double, true, false>(c, xx, yy, c.d_G64, nullptr, skip, s);
+    return apply_impl<P, DIM, double, true, true>(c, xx, yy, c.d_G64, partial, skip, s);
+  }
+  const float *xx = (const float *)x;
+  float *yy = (float *)y;
+  if (!mask) return apply_impl<P, DIM, float, false, false>(c, xx, yy, c.d_G32, nullptr, skip, s);
+  if (!dot) return apply_impl<P, DIM, float, true, false>(c, xx, yy, c.d_G32, nullptr, skip, s);
+  return apply_impl<P, DIM, float, true, true>(c, xx, yy, c.d_G32, partial, skip, s);
+}
+
+hipError_t launch_apply(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
+                        const int32_t *skip, hipStream_t s) {
+  if (c.dim == 3) {
+    FNPF_DISPATCH(3, c.p, return (apply_dispatch<P_, 3>(c, dt, x, y, mask, partial, skip, s)));
+  } else {
+    FNPF_DISPATCH(2, c.p, return (apply_dispatch<P_, 2>(c, dt, x, y, mask, partial, skip, s)));
+  }
+  return hipSuccess;
+}
+
+template <int P, int DIM>
+static hipError_t neumann_impl(Ctx &c, const double *q, double *f, hipStream_t s) {
+  using S = Sh<P, DIM>;
+  const int64_t hs = (int64_t)c.n_eh * c.nh;
+  for (const auto &cr : c.colours) {
+    if (cr.count == 0) continue;
+    const int nb = (cr.count + S::CPB - 1) / S::CPB;
+    k_neumann<P, DIM><<<nb, S::NT, 0, s>>>(q, f, c.d_geoH, c.d_geoh, c.d_hm, hs, c.d_eh_nodes, c.d_flags,
+                                           c.d_face_tag, c.d_cols + cr.offset, cr.count, c.nz, c.n_s, c.n_v,
+                                           c.d_sigma, c.d_layer_s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_neumann(Ctx &c, const double *q, double *f, hipStream_t s) {
+  if (c.dim == 3) {
+    FNPF_DISPATCH(3, c.p, return (neumann_impl<P_, 3>(c, q, f, s)));
+  } else {
+    FNPF_DISPATCH(2, c.p, return (neumann_impl<P_, 2>(c, q, f, s)));
+  }
+  return hipSuccess;
+}
+
+template <int P, int DIM>
+static hipError_t wsurf_impl(Ctx &c, const double *phi, double *w, hipStream_t s) {
+  using S = Sh<P, DIM>;
+  const int64_t hs = (int64_t)c.n_eh * c.nh;
+  const double half_ds = 0.5 * (c.h_layer_s[c.nz] - c.h_layer_s[c.nz - 1]);
+  for (const auto &cr : c.colours) {
+    if (cr.count == 0) continue;
+    const int nb = (cr.count + S::CPB - 1) / S::CPB;
+    k_wsurf<P, DIM><<<nb, S::NT, 0, s>>>(phi, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
+                                         c.d_hm, hs, c.d_geoH, c.d_mlump_w, half_ds, c.d_wnum, w);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wsurf(Ctx &c, const double *phi, double *w, hipStream_t s) {
+  if (c.dim == 3) {
+    FNPF_DISPATCH(3, c.p, return (wsurf_impl<P_, 3>(c, phi, w, s)));
+  } else {
+    FNPF_DISPATCH(2, c.p, return (wsurf_impl<P_, 2>(c, phi, w, s)));
+  }
+  return hipSuccess;
+}
+
+template <int P, int DIM>
+static hipError_t rhs_impl(Ctx &c, const double *eta, const double *phs, const double *w, const RkStageArgs &a,
+                           hipStream_t s) {
+  using S = Sh<P, DIM>;
+  const int64_t hs = (int64_t)c.n_eh * c.nh;
+  for (const auto &cr : c.colours) {
+    if (cr.count == 0) continue;
+    const int nb = (cr.count + S::CPB - 1) / S::CPB;
+    k_rhs<P, DIM><<<nb, S::NT, 0, s>>>(eta, phs, w, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.d_hm,
+                                       hs, c.d_mlump_s, c.g, c.d_nk, c.d_nd, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(Ctx &c, const double *eta, const double *phi_s, const double *w, const RkStageArgs &a,
+                      hipStream_t s) {
+  if (c.dim == 3) {
+    FNPF_DISPATCH(3, c.p, return (rhs_impl<P_, 3>(c, eta, phi_s, w, a, s)));
+  } else {
+    FNPF_DISPATCH(2, c.p, return (rhs_impl<P_, 2>(c, eta, phi_s, w, a, s)));
+  }
+  return hipSuccess;
+}
+
+}  // namespace fnpf

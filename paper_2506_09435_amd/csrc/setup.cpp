@@ -1,0 +1,317 @@
+// Host-side set-up: GLL data, horizontal geometry, mesh validation, column colouring.
+//
+// GLL nodes (nodal Lagrange P^p spectral elements, paper Sec. 3.1; GLL as the
+// node family is the adopted reading): the interior nodes are the roots of
+// P_p', found by Newton iteration with the second derivative taken from
+// Legendre's differential equation (1-x^2) P'' = 2x P' - p(p+1) P.  Weights
+// are 2 / (p(p+1) P_p(x_i)^2).  The derivative matrix uses barycentric
+// weights lambda_j = 1 / prod_{m != j}(x_j - x_m):
+//   D_ij = (lambda_j / lambda_i) / (x_i - x_j) (i != j), D_ii = -sum_{j != i} D_ij.
+//
+// Horizontal element coordinates follow the Gordon-Hall transfinite map of
+// the element's four (straight or circular) edges; the horizontal Jacobian
+// J_h is obtained by applying D to the nodal coordinates (isoparametric).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "fnpf_internal.h"
+
+namespace fnpf {
+
+static void legendre_pair(int p, double x, double &pp, double &pm) {
+  double a = 1.0, b = x;
+  if (p == 0) {
+    pp = 1.0;
+    pm = 0.0;
+    return;
+  }
+  for (int n = 1; n < p; ++n) {
+    double c = ((2.0 * n + 1.0) * x * b - n * a) / (n + 1.0);
+    a = b;
+    b = c;
+  }
+  pp = b;
+  pm = a;
+}
+
+void gll_host(int p, double *x, double *w, double *D) {
+  const int n1 = p + 1;
+  std::vector<double> xs(n1);
+  xs[0] = -1.0;
+  xs[p] = 1.0;
+  for (int i = 1; i < p; ++i) {
+    double t = -std::cos(M_PI * i / p);
+    for (int it = 0; it < 100; ++it) {
+      double P, Pm;
+      legendre_pair(p, t, P, Pm);
+      double d1 = p * (Pm - t * P) / (1.0 - t * t);
+      double d2 = (2.0 * t * d1 - p * (p + 1.0) * P) / (1.0 - t * t);
+      double dt = d1 / d2;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    xs[i] = t;
+  }
+  std::sort(xs.begin(), xs.end());
+  std::vector<double> lam(n1, 1.0);
+  for (int j = 0; j < n1; ++j) {
+    double prod = 1.0;
+    for (int m = 0; m < n1; ++m)
+      if (m != j) prod *= (xs[j] - xs[m]);
+    lam[j] = 1.0 / prod;
+  }
+  for (int i = 0; i < n1; ++i) {
+    if (x) x[i] = xs[i];
+    if (w) {
+      double P, Pm;
+      legendre_pair(p, xs[i], P, Pm);
+      w[i] = 2.0 / (p * (p + 1.0) * P * P);
+    }
+  }
+  if (D) {
+    for (int i = 0; i < n1; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < n1; ++j) {
+        if (i == j) continue;
+        double v = (lam[j] / lam[i]) / (xs[i] - xs[j]);
+        D[i * n1 + j] = v;
+        s += v;
+      }
+      D[i * n1 + i] = -s;
+    }
+  }
+}
+
+namespace {
+
+struct Pt {
+  double x, y;
+};
+
+// point on an edge from a to b at reference parameter t in [-1, 1]
+Pt edge_point(Pt a, Pt b, const double *arc, double t) {
+  double s = 0.5 * (t + 1.0);
+  if (arc == nullptr || arc[2] == 0.0) return {a.x + s * (b.x - a.x), a.y + s * (b.y - a.y)};
+  double cx = arc[0], cy = arc[1], r = arc[2];
+  double ta = std::atan2(a.y - cy, a.x - cx);
+  double tb = std::atan2(b.y - cy, b.x - cx);
+  double d = tb - ta;
+  while (d > M_PI) d -= 2.0 * M_PI;
+  while (d <= -M_PI) d += 2.0 * M_PI;
+  double th = ta + d * s;
+  return {cx + r * std::cos(th), cy + r * std::sin(th)};
+}
+
+}  // namespace
+
+std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double> &hm, std::vector<uint8_t> &flags,
+                            std::vector<int32_t> &cols, std::vector<double> &mlump_w, std::vector<double> &mlump_s) {
+  char buf[256];
+  const int dim = m.dim, p = m.p, n1 = p + 1;
+  const int nh = dim == 3 ? n1 * n1 : n1;
+  const int64_t n_eh = m.n_eh, n_s = m.n_s;
+  c.dim = dim;
+  c.p = p;
+  c.nz = m.nz;
+  c.n_eh = m.n_eh;
+  c.n_s = n_s;
+  c.nh = nh;
+  c.np = nh * n1;
+  c.ng = dim == 3 ? 6 : 3;
+  c.n_v = n_s * (int64_t)(p * m.nz + 1);
+  c.n_e = n_eh * m.nz;
+  c.g = m.g;
+
+  // node ids
+  c.h_eh_nodes.assign(m.eh_nodes, m.eh_nodes + n_eh * nh);
+  std::vector<int32_t> count(n_s, 0);
+  for (int64_t e = 0; e < n_eh; ++e) {
+    for (int t = 0; t < nh; ++t) {
+      int32_t id = m.eh_nodes[e * nh + t];
+      if (id < 0 || id >= n_s) {
+        std::snprintf(buf, sizeof buf, "eh_nodes[%lld][%d] = %d out of range [0, %lld)", (long long)e, t, id,
+                      (long long)n_s);
+        return buf;
+      }
+      for (int u = 0; u < t; ++u)
+        if (m.eh_nodes[e * nh + u] == id) {
+          std::snprintf(buf, sizeof buf, "element %lld repeats horizontal node %d", (long long)e, id);
+          return buf;
+        }
+      count[id]++;
+    }
+  }
+  for (int64_t n = 0; n < n_s; ++n)
+    if (count[n] == 0) {
+      std::snprintf(buf, sizeof buf, "horizontal node %lld is not used by any element", (long long)n);
+      return buf;
+    }
+
+  // layer fractions and node-level sigma
+  c.h_layer_s.resize(m.nz + 1);
+  for (int l = 0; l <= m.nz; ++l) c.h_layer_s[l] = m.layer_s ? m.layer_s[l] : (double)l / m.nz;
+  if (c.h_layer_s[0] != 0.0 || c.h_layer_s[m.nz] != 1.0) return "layer_s must start at 0 and end at 1";
+  for (int l = 0; l < m.nz; ++l)
+    if (!(c.h_layer_s[l + 1] > c.h_layer_s[l])) return "layer_s must be strictly increasing";
+  std::vector<double> x(n1), w(n1), D(n1 * n1);
+  gll_host(p, x.data(), w.data(), D.data());
+  c.h_sigma.resize(p * m.nz + 1);
+  for (int l = 0; l < m.nz; ++l)
+    for (int k = 0; k <= p; ++k)
+      c.h_sigma[l * p + k] = c.h_layer_s[l] + (c.h_layer_s[l + 1] - c.h_layer_s[l]) * 0.5 * (x[k] + 1.0);
+
+  // horizontal coordinates at the element GLL nodes
+  const int ncomp = dim == 3 ? kHm3 : kHm2;
+  std::vector<double> xh(n_eh * nh * (dim - 1));
+  for (int64_t e = 0; e < n_eh; ++e) {
+    if (dim == 2) {
+      double xa = m.eh_corner[e * 2 + 0], xb = m.eh_corner[e * 2 + 1];
+      for (int i = 0; i < n1; ++i) xh[e * nh + i] = xa + (xb - xa) * 0.5 * (x[i] + 1.0);
+      continue;
+    }
+    const double *cc = m.eh_corner + e * 8;
+    Pt c0{cc[0], cc[1]}, c1{cc[2], cc[3]}, c2{cc[4], cc[5]}, c3{cc[6], cc[7]};
+    const double *arc = m.eh_arc ? m.eh_arc + e * 12 : nullptr;
+    for (int j = 0; j < n1; ++j) {
+      for (int i = 0; i < n1; ++i) {
+        double xi = x[i], et = x[j];
+        Pt e0 = edge_point(c0, c1, arc ? arc + 0 : nullptr, xi);
+        Pt e1 = edge_point(c1, c2, arc ? arc + 3 : nullptr, et);
+        Pt e2 = edge_point(c3, c2, arc ? arc + 6 : nullptr, xi);
+        Pt e3 = edge_point(c0, c3, arc ? arc + 9 : nullptr, et);
+        double bx = 0.25 * ((1 - xi) * (1 - et) * c0.x + (1 + xi) * (1 - et) * c1.x + (1 + xi) * (1 + et) * c2.x +
+                            (1 - xi) * (1 + et) * c3.x);
+        double by = 0.25 * ((1 - xi) * (1 - et) * c0.y + (1 + xi) * (1 - et) * c1.y + (1 + xi) * (1 + et) * c2.y +
+                            (1 - xi) * (1 + et) * c3.y);
+        double px = 0.5 * (1 - et) * e0.x + 0.5 * (1 + et) * e2.x + 0.5 * (1 - xi) * e3.x + 0.5 * (1 + xi) * e1.x - bx;
+        double py = 0.5 * (1 - et) * e0.y + 0.5 * (1 + et) * e2.y + 0.5 * (1 - xi) * e3.y + 0.5 * (1 + xi) * e1.y - by;
+        int64_t o = (e * nh + j * n1 + i) * 2;
+        xh[o] = px;
+        xh[o + 1] = py;
+      }
+    }
+  }
+  // node coordinates (first image)
+  c.h_node_xy.assign(n_s * (dim - 1), 0.0);
+  {
+    std::vector<char> seen(n_s, 0);
+    for (int64_t e = 0; e < n_eh; ++e)
+      for (int t = 0; t < nh; ++t) {
+        int32_t id = m.eh_nodes[e * nh + t];
+        if (seen[id]) continue;
+        seen[id] = 1;
+        for (int a = 0; a < dim - 1; ++a) c.h_node_xy[id * (dim - 1) + a] = xh[(e * nh + t) * (dim - 1) + a];
+      }
+  }
+  // horizontal metrics and lumped masses
+  hm.assign((size_t)ncomp * n_eh * nh, 0.0);
+  mlump_w.assign(n_s, 0.0);
+  mlump_s.assign(n_s, 0.0);
+  const int64_t stride = n_eh * nh;
+  for (int64_t e = 0; e < n_eh; ++e) {
+    for (int t = 0; t < nh; ++t) {
+      const int i = t % n1, j = t / n1;
+      const int64_t o = e * nh + t;
+      double det, ws;
+      if (dim == 2) {
+        double xx = 0.0;
+        for (int mm = 0; mm < n1; ++mm) xx += D[i * n1 + mm] * xh[e * nh + mm];
+        if (!(xx > 0.0)) {
+          std::snprintf(buf, sizeof buf, "element %lld: non-positive horizontal Jacobian (corners reversed?)",
+                        (long long)e);
+          return buf;
+        }
+        hm[0 * stride + o] = 1.0 / xx;
+        hm[1 * stride + o] = xx;
+        det = xx;
+        ws = w[i];
+      } else {
+        double xxi = 0, xet = 0, yxi = 0, yet = 0;
+        for (int mm = 0; mm < n1; ++mm) {
+          xxi += D[i * n1 + mm] * xh[(e * nh + j * n1 + mm) * 2];
+          yxi += D[i * n1 + mm] * xh[(e * nh + j * n1 + mm) * 2 + 1];
+          xet += D[j * n1 + mm] * xh[(e * nh + mm * n1 + i) * 2];
+          yet += D[j * n1 + mm] * xh[(e * nh + mm * n1 + i) * 2 + 1];
+        }
+        det = xxi * yet - xet * yxi;
+        if (!(det > 0.0)) {
+          std::snprintf(buf, sizeof buf,
+                        "element %lld: non-positive horizontal Jacobian at node %d (clockwise or tangled corners)",
+                        (long long)e, t);
+          return buf;
+        }
+        hm[0 * stride + o] = yet / det;    // (J_h^{-1})_00
+        hm[1 * stride + o] = -xet / det;   // (J_h^{-1})_01
+        hm[2 * stride + o] = -yxi / det;   // (J_h^{-1})_10
+        hm[3 * stride + o] = xxi / det;    // (J_h^{-1})_11
+        hm[4 * stride + o] = det;
+        hm[5 * stride + o] = xxi;
+        hm[6 * stride + o] = xet;
+        hm[7 * stride + o] = yxi;
+        hm[8 * stride + o] = yet;
+        ws = w[i] * w[j];
+      }
+      int32_t id = m.eh_nodes[o];
+      mlump_s[id] += ws * det;
+      mlump_w[id] += ws * w[p] * det;
+    }
+  }
+
+  // greedy colouring of columns: columns sharing a horizontal node get different colours
+  std::vector<int64_t> off(n_s + 1, 0);
+  for (int64_t n = 0; n < n_s; ++n) off[n + 1] = off[n] + count[n];
+  std::vector<int32_t> adj(off[n_s]);
+  {
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int64_t e = 0; e < n_eh; ++e)
+      for (int t = 0; t < nh; ++t) adj[pos[m.eh_nodes[e * nh + t]]++] = (int32_t)e;
+  }
+  std::vector<int32_t> colour(n_eh, -1);
+  int ncol = 0;
+  for (int64_t e = 0; e < n_eh; ++e) {
+    uint64_t used = 0;
+    for (int t = 0; t < nh; ++t) {
+      int32_t id = m.eh_nodes[e * nh + t];
+      for (int64_t q = off[id]; q < off[id + 1]; ++q) {
+        int32_t o = adj[q];
+        if (colour[o] >= 0) used |= (1ull << colour[o]);
+      }
+    }
+    int cc = 0;
+    while (cc < 64 && (used >> cc & 1ull)) ++cc;
+    if (cc >= 64) return "column colouring needs more than 64 colours";
+    colour[e] = cc;
+    ncol = std::max(ncol, cc + 1);
+  }
+  c.colours.assign(ncol, ColourRange{0, 0});
+  for (int64_t e = 0; e < n_eh; ++e) c.colours[colour[e]].count++;
+  for (int k = 1; k < ncol; ++k) c.colours[k].offset = c.colours[k - 1].offset + c.colours[k - 1].count;
+  cols.assign(n_eh, 0);
+  {
+    std::vector<int32_t> fill(ncol, 0);
+    for (int64_t e = 0; e < n_eh; ++e) cols[c.colours[colour[e]].offset + fill[colour[e]]++] = (int32_t)e;
+  }
+  // first / last writer flags per (column, local node), in colour launch order
+  flags.assign(n_eh * nh, 0);
+  for (int64_t e = 0; e < n_eh; ++e) {
+    for (int t = 0; t < nh; ++t) {
+      int32_t id = m.eh_nodes[e * nh + t];
+      int cmin = 1 << 30, cmax = -1;
+      for (int64_t q = off[id]; q < off[id + 1]; ++q) {
+        cmin = std::min(cmin, colour[adj[q]]);
+        cmax = std::max(cmax, colour[adj[q]]);
+      }
+      uint8_t f = 0;
+      if (colour[e] == cmin) f |= kFirst;
+      if (colour[e] == cmax) f |= kLast;
+      flags[e * nh + t] = f;
+    }
+  }
+  return "";
+}
+
+}  // namespace fnpf

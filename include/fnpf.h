@@ -157,6 +157,18 @@ fnpf_status fnpf_gll(int32_t p, double *nodes, double *weights, double *D);
  * xy[n_s][dim-1] (periodic nodes: the first element's image). */
 fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy);
 
+/* Stiffness-apply variant (both compute the same operator):
+ *   0 (default) fused geometry: the per-point factors are re-evaluated in
+ *     registers from five numbers per column node (eta+h, h and their
+ *     horizontal derivatives) and the static horizontal metrics, so an apply
+ *     reads x and writes y only;
+ *   1 stored factors: fnpf_geom stores G (6 or 3 per point, FP64 and FP32)
+ *     and the apply streams it from HBM;
+ *   2 fused geometry with a fully unrolled schedule (more registers, fewer
+ *     LDS accesses; kept for comparison).
+ * Switching to 1 invalidates the current geometry (call fnpf_geom again). */
+fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant);
+
 /* Enable the FP32 path: allocates FP32 factors and the inner-PCG vectors;
  * every later fnpf_geom also produces the FP32 factors.  fnpf_rk4_step with
  * precision 1 enables it by itself. */

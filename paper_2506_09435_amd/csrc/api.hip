@@ -66,6 +66,12 @@ void free_all(Ctx &c) {
   dfree(c.d_mlump_s);
   dfree(c.d_G64);
   dfree(c.d_G32);
+  dfree(c.d_cg64);
+  dfree(c.d_cg32);
+  dfree(c.d_hm32);
+  dfree(c.d_half_ds);
+  dfree(c.d_half_ds32);
+  dfree(c.d_sigma32);
   dfree(c.d_diag);
   dfree(c.d_dinv);
   dfree(c.d_dinv32);
@@ -109,9 +115,25 @@ hipError_t upload(T **d, const T *h, size_t n) {
 }
 
 // Enable the FP32 path (allocates FP32 factors and inner PCG vectors on first use).
+fnpf_status ensure_G(Ctx &c) {
+  if (!c.d_G64) HIPCHK(dalloc(&c.d_G64, (size_t)c.n_e * c.ng * c.np));
+  if (c.want32 && !c.d_G32) HIPCHK(dalloc(&c.d_G32, (size_t)c.n_e * c.ng * c.np));
+  return FNPF_OK;
+}
+
+template <typename T>
+hipError_t upload_cast(float **d, const std::vector<T> &h) {
+  std::vector<float> f(h.begin(), h.end());
+  return upload(d, f.data(), f.size());
+}
+
 fnpf_status ensure32(Ctx &c) {
   if (c.want32) return FNPF_OK;
-  HIPCHK(dalloc(&c.d_G32, (size_t)c.n_e * c.ng * c.np));
+  HIPCHK(dalloc(&c.d_cg32, (size_t)c.ncg * c.n_eh * c.nh));
+  HIPCHK(upload_cast(&c.d_hm32, c.h_hm));
+  HIPCHK(upload_cast(&c.d_sigma32, c.h_sigma));
+  HIPCHK(upload_cast(&c.d_half_ds32, c.h_half_ds));
+  if (c.apply_variant == 1) HIPCHK(dalloc(&c.d_G32, (size_t)c.n_e * c.ng * c.np));
   HIPCHK(dalloc(&c.d_dinv32, c.n_v));
   HIPCHK(dalloc(&c.d_r32, c.n_v));
   HIPCHK(dalloc(&c.d_p32, c.n_v));
@@ -235,9 +257,15 @@ fnpf_status solve_impl(Ctx &c, const double *phis, const double *f, double *phi,
 }
 
 fnpf_status geom_impl(Ctx &c, const double *eta, const double *h, hipStream_t s) {
-  HIPCHK(launch_geom(c, eta, h, s));
+  const bool store = c.apply_variant == 1;
+  if (store) {
+    fnpf_status st = ensure_G(c);
+    if (st != FNPF_OK) return st;
+  }
+  HIPCHK(launch_geom(c, eta, h, store, false, s));
   c.have_geom = true;
   c.have_geom32 = c.want32;
+  c.have_G = store;
   return FNPF_OK;
 }
 
@@ -308,6 +336,10 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   std::vector<uint8_t> flags;
   std::vector<int32_t> cols;
   std::string e = build_host_mesh(*m, c, hm, flags, cols, mw, ms);
+  c.h_hm = hm;
+  c.ncg = c.dim == 3 ? 5 : 3;
+  c.h_half_ds.resize(c.nz);
+  for (int l = 0; l < c.nz; ++l) c.h_half_ds[l] = 0.5 * (c.h_layer_s[l + 1] - c.h_layer_s[l]);
   if (!e.empty()) {
     g_create_error = e;
     delete h;
@@ -357,7 +389,8 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   UP(c.d_layer_s, c.h_layer_s.data(), c.h_layer_s.size());
   UP(c.d_mlump_w, mw.data(), mw.size());
   UP(c.d_mlump_s, ms.data(), ms.size());
-  AL(c.d_G64, (size_t)c.n_e * c.ng * c.np);
+  AL(c.d_cg64, (size_t)c.ncg * c.n_eh * c.nh);
+  UP(c.d_half_ds, c.h_half_ds.data(), c.h_half_ds.size());
   AL(c.d_diag, c.n_v);
   AL(c.d_dinv, c.n_v);
   AL(c.d_err, 1);
@@ -416,6 +449,20 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy) {
   return FNPF_OK;
 }
 
+fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (variant < 0 || variant > 2) return fail(&c, FNPF_ERR_ARG, "apply variant must be 0, 1 or 2");
+  if (variant == c.apply_variant) return FNPF_OK;
+  c.apply_variant = variant;
+  if (variant == 1) {
+    fnpf_status st = ensure_G(c);
+    if (st != FNPF_OK) return st;
+    c.have_geom = c.have_geom32 = false;   // factors must be (re)computed by fnpf_geom
+  }
+  return FNPF_OK;
+}
+
 fnpf_status fnpf_enable_fp32(fnpf_ctx ctx) {
   if (!ctx) return FNPF_ERR_ARG;
   return ensure32(ctx->c);
@@ -435,6 +482,13 @@ fnpf_status fnpf_export_geometry(fnpf_ctx ctx, fnpf_dtype dtype, void *G, double
   if (dtype != FNPF_F64 && dtype != FNPF_F32) return fail(&c, FNPF_ERR_ARG, "bad dtype");
   if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_export_geometry before fnpf_geom");
   if (dtype == FNPF_F32 && !c.have_geom32) return fail(&c, FNPF_ERR_STATE, "no FP32 factors (enable the mixed path)");
+  if (!c.have_G) {
+    // factors are not stored by the fused-geometry variant: evaluate them from the saved column data
+    fnpf_status st = ensure_G(c);
+    if (st != FNPF_OK) return st;
+    HIPCHK(launch_geom(c, c.d_geoH, c.d_geoh, true, true, s));
+    c.have_G = true;
+  }
   const size_t ng = (size_t)c.n_e * c.ng * c.np;
   if (G) {
     if (dtype == FNPF_F64)

@@ -55,7 +55,8 @@ struct Ctx;
 
 // Kernel launchers (kernels_*.hip). All return hipSuccess or the launch error.
 hipError_t upload_constants(int device);
-hipError_t launch_geom(Ctx &c, const double *eta, const double *h, hipStream_t s);
+hipError_t launch_geom(Ctx &c, const double *eta, const double *h, bool store_G, bool h_is_total,
+                       hipStream_t s);
 hipError_t launch_apply(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
                         const int32_t *skip, hipStream_t s);
 hipError_t launch_neumann(Ctx &c, const double *q, double *f, hipStream_t s);
@@ -114,6 +115,9 @@ struct Ctx {
   std::vector<double> h_layer_s;          // [nz+1]
   std::vector<double> h_sigma;            // [p nz + 1]
   std::vector<ColourRange> colours;
+  std::vector<double> h_hm;               // horizontal metrics (host copy)
+  std::vector<double> h_half_ds;          // [nz]
+  int ncg = 5;                            // column-data components (5 in 3D, 3 in 2D)
   int max_colour_blocks = 0;              // sum over colours of apply blocks
   // device mesh data
   int32_t *d_eh_nodes = nullptr;
@@ -125,6 +129,15 @@ struct Ctx {
   double *d_layer_s = nullptr;            // [nz + 1]
   double *d_mlump_w = nullptr;            // [n_s] sum_e w_i w_j w_p det J_h (w recovery denominator)
   double *d_mlump_s = nullptr;            // [n_s] sum_e w_i w_j det J_h (surface mass)
+  // apply variant: 0 fused geometry (factors recomputed in registers), 1 stored factors
+  int apply_variant = 0;
+  double *d_cg64 = nullptr;               // [5|3][n_eh*nh] H, H_xi, h_xi, (H_eta, h_eta) per column node
+  float *d_cg32 = nullptr;
+  float *d_hm32 = nullptr;                // FP32 copy of d_hm
+  double *d_half_ds = nullptr;            // [nz] (s_{l+1} - s_l) / 2
+  float *d_half_ds32 = nullptr;
+  float *d_sigma32 = nullptr;
+  bool have_G = false;                    // stored factors are current
   // geometry state
   double *d_G64 = nullptr;
   float *d_G32 = nullptr;

@@ -233,6 +233,341 @@ __global__ __launch_bounds__(256) void k_apply(const T *__restrict__ x, T *__res
 }
 
 // ---------------------------------------------------------------------------------------------
+// Stiffness apply with the geometric factors recomputed in registers (fused geometry).
+// For the extruded sigma-mesh, J = [[J_h, 0], [z_xi, z_eta, z_zeta]] with
+//   z_xi = sigma_v H_xi - h_xi,  z_eta = sigma_v H_eta - h_eta,  z_zeta = (ds_l / 2) H,
+// H = eta + h, so every factor of G = w det(J) B B^T (B = J^-1) follows from five numbers per
+// column node (H, H_xi, h_xi, H_eta, h_eta) and the static horizontal metrics A = J_h^-1,
+// det J_h.  G r is evaluated as f B (B^T r), f = w_q det J_h z_zeta.  Same operator as the
+// stored-factor kernel; HBM traffic drops to the vectors x and y.
+// ---------------------------------------------------------------------------------------------
+template <int P, int DIM, typename T, bool MASK, bool DOT>
+__global__ __launch_bounds__(256) void k_apply_fused(const T *__restrict__ x, T *__restrict__ y,
+                                                     const T *__restrict__ cg, const T *__restrict__ hmT,
+                                                     int64_t hstride, const T *__restrict__ sig,
+                                                     const T *__restrict__ half_ds,
+                                                     const int32_t *__restrict__ eh_nodes,
+                                                     const uint8_t *__restrict__ flags,
+                                                     const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
+                                                     double *__restrict__ partial, const int32_t *__restrict__ skip) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
+  __shared__ T su[CPB * NP];
+  __shared__ T sx[CPB * NP];
+  __shared__ T sy[DIM == 3 ? CPB * NP : 1];
+  if (skip != nullptr && *skip) return;
+
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? cols[ci] : 0;
+  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
+  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
+  const int64_t ho = (int64_t)col * NH + t;
+
+  // column-node geometry
+  T H = T(1), Hx = T(0), hx = T(0), Hy = T(0), hy = T(0);
+  T A00 = T(1), A01 = T(0), A10 = T(0), A11 = T(1), dJ = T(1);
+  if (active) {
+    H = cg[0 * hstride + ho];
+    Hx = cg[1 * hstride + ho];
+    hx = cg[2 * hstride + ho];
+    if constexpr (DIM == 3) {
+      Hy = cg[3 * hstride + ho];
+      hy = cg[4 * hstride + ho];
+      A00 = hmT[0 * hstride + ho];
+      A01 = hmT[1 * hstride + ho];
+      A10 = hmT[2 * hstride + ho];
+      A11 = hmT[3 * hstride + ho];
+      dJ = hmT[4 * hstride + ho];
+    } else {
+      A00 = hmT[0 * hstride + ho];
+      dJ = hmT[1 * hstride + ho];
+    }
+  }
+  const T wh = (T)(DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i));
+  const T wdJ = wh * dJ;
+
+  T Dri[N1], Drj[N1], Dci[N1], Dcj[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    Dri[m] = dmat<T>(P, i, m);
+    Dci[m] = dmat<T>(P, m, i);
+    if constexpr (DIM == 3) {
+      Drj[m] = dmat<T>(P, j, m);
+      Dcj[m] = dmat<T>(P, m, j);
+    }
+  }
+  T *u_c = su + lc * NP;
+  T *x_c = sx + lc * NP;
+  T *y_c = sy + (DIM == 3 ? lc * NP : 0);
+
+  T ucol[N1];
+  T carry = T(0);
+  double dot = 0.0;
+  ucol[0] = active ? x[hn] : T(0);
+  const int vtop = P * nz;
+
+  for (int l = 0; l < nz; ++l) {
+#pragma unroll
+    for (int k = 1; k < N1; ++k) ucol[k] = active ? x[(int64_t)(l * P + k) * n_s + hn] : T(0);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) u_c[k * NH + t] = ucol[k];
+    __syncthreads();
+
+    const T zz = half_ds[l] * H;
+    const T izz = T(1) / zz;
+    const T fl0 = wdJ * zz;
+    T vz[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      T ux = T(0), uy = T(0), uz = T(0);
+#pragma unroll
+      for (int m = 0; m < N1; ++m) ux += Dri[m] * u_c[k * NH + j * N1 + m];
+      if constexpr (DIM == 3) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) uy += Drj[m] * u_c[k * NH + m * N1 + i];
+      }
+#pragma unroll
+      for (int m = 0; m < N1; ++m) uz += dmat<T>(P, k, m) * ucol[m];
+      const T sg = sig[l * P + k];
+      const T f = (T)wgt(P, k) * fl0;
+      const T zx = sg * Hx - hx;
+      const int q = k * NH + t;
+      if constexpr (DIM == 3) {
+        const T zy = sg * Hy - hy;
+        const T b2x = -(zx * A00 + zy * A10) * izz;
+        const T b2y = -(zx * A01 + zy * A11) * izz;
+        const T gx = A00 * ux + A10 * uy + b2x * uz;
+        const T gy = A01 * ux + A11 * uy + b2y * uz;
+        const T gz = izz * uz;
+        x_c[q] = f * (A00 * gx + A01 * gy);
+        y_c[q] = f * (A10 * gx + A11 * gy);
+        vz[k] = f * (b2x * gx + b2y * gy + izz * gz);
+      } else {
+        const T b1x = -zx * A00 * izz;
+        const T g0 = A00 * ux + b1x * uz;
+        const T g1 = izz * uz;
+        x_c[q] = f * (A00 * g0);
+        vz[k] = f * (b1x * g0 + izz * g1);
+      }
+    }
+    __syncthreads();
+
+    T yk[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int m = 0; m < N1; ++m) acc += Dci[m] * x_c[k * NH + j * N1 + m];
+      if constexpr (DIM == 3) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) acc += Dcj[m] * y_c[k * NH + m * N1 + i];
+      }
+#pragma unroll
+      for (int m = 0; m < N1; ++m) acc += dmat<T>(P, m, k) * vz[m];
+      yk[k] = acc;
+    }
+    yk[0] += carry;
+    if (active) {
+      const int kend = (l == nz - 1) ? N1 : P;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        if (k < kend) {
+          const int v = l * P + k;
+          const int64_t idx = (int64_t)v * n_s + hn;
+          T val;
+          if (MASK && v == vtop) {
+            y[idx] = T(0);
+            val = T(0);
+          } else {
+            val = scatter(y, idx, yk[k], fl);
+          }
+          if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
+        }
+      }
+    }
+    carry = yk[P];
+    ucol[0] = ucol[P];
+  }
+  if constexpr (DOT) {
+    double s = block_sum<S::NT>(dot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// Same operator, register-lean schedule: the forward (gradient) loop over the zeta index k
+// runs at run time, reading the uniform row D[k][.] through the scalar cache, and scatters the
+// zeta part of the transposed contraction, y_zeta[k'] += D[k][k'] v_zeta[k], straight into a
+// register line; the backward loop is unrolled.  Live registers: the thread's D rows, its
+// vertical line, the y_zeta line and the column geometry.
+template <int P, int DIM, typename T, bool MASK, bool DOT>
+__global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T *__restrict__ y,
+                                                      const T *__restrict__ cg, const T *__restrict__ hmT,
+                                                      int64_t hstride, const T *__restrict__ sig,
+                                                      const T *__restrict__ half_ds,
+                                                      const int32_t *__restrict__ eh_nodes,
+                                                      const uint8_t *__restrict__ flags,
+                                                      const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
+                                                      double *__restrict__ partial, const int32_t *__restrict__ skip) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
+  __shared__ T su[CPB * NP];
+  __shared__ T sx[CPB * NP];
+  __shared__ T sy[DIM == 3 ? CPB * NP : 1];
+  if (skip != nullptr && *skip) return;
+
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? cols[ci] : 0;
+  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
+  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
+  const int64_t ho = (int64_t)col * NH + t;
+
+  T H = T(1), Hx = T(0), hx = T(0), Hy = T(0), hy = T(0);
+  T A00 = T(1), A01 = T(0), A10 = T(0), A11 = T(1), dJ = T(1);
+  if (active) {
+    H = cg[0 * hstride + ho];
+    Hx = cg[1 * hstride + ho];
+    hx = cg[2 * hstride + ho];
+    if constexpr (DIM == 3) {
+      Hy = cg[3 * hstride + ho];
+      hy = cg[4 * hstride + ho];
+      A00 = hmT[0 * hstride + ho];
+      A01 = hmT[1 * hstride + ho];
+      A10 = hmT[2 * hstride + ho];
+      A11 = hmT[3 * hstride + ho];
+      dJ = hmT[4 * hstride + ho];
+    } else {
+      A00 = hmT[0 * hstride + ho];
+      dJ = hmT[1 * hstride + ho];
+    }
+  }
+  const T wdJ = (T)(DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i)) * dJ;
+
+  T Dri[N1], Drj[N1], Dci[N1], Dcj[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    Dri[m] = dmat<T>(P, i, m);
+    Dci[m] = dmat<T>(P, m, i);
+    if constexpr (DIM == 3) {
+      Drj[m] = dmat<T>(P, j, m);
+      Dcj[m] = dmat<T>(P, m, j);
+    }
+  }
+  T *u_c = su + lc * NP;
+  T *x_c = sx + lc * NP;
+  T *y_c = sy + (DIM == 3 ? lc * NP : 0);
+
+  T ucol[N1];
+  T carry = T(0);
+  double dot = 0.0;
+  ucol[0] = active ? x[hn] : T(0);
+  const int vtop = P * nz;
+
+  for (int l = 0; l < nz; ++l) {
+#pragma unroll
+    for (int k = 1; k < N1; ++k) ucol[k] = active ? x[(int64_t)(l * P + k) * n_s + hn] : T(0);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) u_c[k * NH + t] = ucol[k];
+    __syncthreads();
+
+    const T zz = half_ds[l] * H;
+    const T izz = T(1) / zz;
+    const T fl0 = wdJ * zz;
+    T yz[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) yz[k] = T(0);
+#pragma unroll 1
+    for (int k = 0; k < N1; ++k) {
+      T ux = T(0), uy = T(0), uz = T(0);
+      const T *row = u_c + k * NH;
+#pragma unroll
+      for (int m = 0; m < N1; ++m) ux += Dri[m] * row[j * N1 + m];
+      if constexpr (DIM == 3) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) uy += Drj[m] * row[m * N1 + i];
+      }
+#pragma unroll
+      for (int m = 0; m < N1; ++m) uz += dmat<T>(P, k, m) * ucol[m];
+      const T sg = sig[l * P + k];
+      const T f = (T)wgt(P, k) * fl0;
+      const T zx = sg * Hx - hx;
+      const int q = k * NH + t;
+      T vz;
+      if constexpr (DIM == 3) {
+        const T zy = sg * Hy - hy;
+        const T b2x = -(zx * A00 + zy * A10) * izz;
+        const T b2y = -(zx * A01 + zy * A11) * izz;
+        const T gx = A00 * ux + A10 * uy + b2x * uz;
+        const T gy = A01 * ux + A11 * uy + b2y * uz;
+        const T gz = izz * uz;
+        x_c[q] = f * (A00 * gx + A01 * gy);
+        y_c[q] = f * (A10 * gx + A11 * gy);
+        vz = f * (b2x * gx + b2y * gy + izz * gz);
+      } else {
+        const T b1x = -zx * A00 * izz;
+        const T g0 = A00 * ux + b1x * uz;
+        const T g1 = izz * uz;
+        x_c[q] = f * (A00 * g0);
+        vz = f * (b1x * g0 + izz * g1);
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < N1; ++k2) yz[k2] += dmat<T>(P, k, k2) * vz;
+    }
+    __syncthreads();
+
+    // own u entries are no longer read by other threads: reuse them for the output line
+#pragma unroll
+    for (int k = 0; k < N1; ++k) u_c[k * NH + t] = yz[k];
+#pragma unroll 1
+    for (int k = 0; k < N1; ++k) {
+      T acc = u_c[k * NH + t];
+      const T *rx = x_c + k * NH;
+#pragma unroll
+      for (int m = 0; m < N1; ++m) acc += Dci[m] * rx[j * N1 + m];
+      if constexpr (DIM == 3) {
+        const T *ry = y_c + k * NH;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) acc += Dcj[m] * ry[m * N1 + i];
+      }
+      u_c[k * NH + t] = acc;
+    }
+    if (active) {
+      const int kend = (l == nz - 1) ? N1 : P;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        if (k < kend) {
+          const int v = l * P + k;
+          const int64_t idx = (int64_t)v * n_s + hn;
+          T yv = u_c[k * NH + t];
+          if (k == 0) yv += carry;
+          T val;
+          if (MASK && v == vtop) {
+            y[idx] = T(0);
+            val = T(0);
+          } else {
+            val = scatter(y, idx, yv, fl);
+          }
+          if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
+        }
+      }
+    }
+    carry = u_c[P * NH + t];
+    ucol[0] = ucol[P];
+  }
+  if constexpr (DOT) {
+    double s = block_sum<S::NT>(dot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Geometry (paper Sec. 3.1.2, Step 4.1): z = -h + sigma_v (eta + h) per node level; per point
 // G = w det(J) J^-1 J^-T with J = [[J_h, 0], [z_xi, z_eta, z_zeta]]; assembled Jacobi diagonal.
 // ---------------------------------------------------------------------------------------------
@@ -245,7 +580,8 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
                                               double *__restrict__ G64, float *__restrict__ G32,
                                               double *__restrict__ diag, double *__restrict__ dinv,
                                               float *__restrict__ dinv32, double *__restrict__ Hout,
-                                              double *__restrict__ hout, int32_t *__restrict__ err) {
+                                              double *__restrict__ hout, double *__restrict__ cg64,
+                                              float *__restrict__ cg32, int h_is_total, int32_t *__restrict__ err) {
   using S = Sh<P, DIM>;
   constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, NG = S::NG, CPB = S::CPB;
   __shared__ double sH[CPB * NH];
@@ -263,7 +599,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
   const int64_t ho = (int64_t)col * NH + t;
 
-  const double Hn = active ? eta[hn] + hb[hn] : 1.0;
+  const double Hn = active ? (h_is_total ? eta[hn] : eta[hn] + hb[hn]) : 1.0;
   const double hnv = active ? hb[hn] : 0.0;
   if (active && !(Hn > 0.0)) *err = 1;
   if (active && (fl & kFirst)) {
@@ -284,6 +620,25 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
     for (int m = 0; m < N1; ++m) {
       Hy += dmat<double>(P, j, m) * sH[lc * NH + m * N1 + i];
       hy += dmat<double>(P, j, m) * sh[lc * NH + m * N1 + i];
+    }
+  }
+  // per (column, node) vertical data used by the fused-geometry apply
+  if (active) {
+    cg64[0 * hstride + ho] = Hn;
+    cg64[1 * hstride + ho] = Hx;
+    cg64[2 * hstride + ho] = hx;
+    if (cg32) {
+      cg32[0 * hstride + ho] = (float)Hn;
+      cg32[1 * hstride + ho] = (float)Hx;
+      cg32[2 * hstride + ho] = (float)hx;
+    }
+    if constexpr (DIM == 3) {
+      cg64[3 * hstride + ho] = Hy;
+      cg64[4 * hstride + ho] = hy;
+      if (cg32) {
+        cg32[3 * hstride + ho] = (float)Hy;
+        cg32[4 * hstride + ho] = (float)hy;
+      }
     }
   }
   double A00, A01 = 0.0, A10 = 0.0, A11 = 0.0, detJh;
@@ -312,7 +667,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   for (int l = 0; l < nz; ++l) {
     const double zz = 0.5 * (layer_s[l + 1] - layer_s[l]) * Hn;   // z_zeta (sigma-linear per layer)
     double gz[N1], c01[N1], c02[N1], c12[N1];
-    double *Ge64 = G64 + (e0 + l) * (int64_t)(NG * NP);
+    double *Ge64 = G64 ? G64 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
     float *Ge32 = G32 ? G32 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
@@ -331,7 +686,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
         const double g11 = f * (A10 * A10 + A11 * A11);
         const double g12 = f * (A10 * b2x + A11 * b2y);
         const double g22 = f * (b2x * b2x + b2y * b2y + b2z * b2z);
-        if (active) {
+        if (active && Ge64) {
           Ge64[0 * NP + q] = g00;
           Ge64[1 * NP + q] = g01;
           Ge64[2 * NP + q] = g02;
@@ -359,7 +714,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
         const double g00 = f * A00 * A00;
         const double g01 = f * A00 * b1x;
         const double g11 = f * (b1x * b1x + b1z * b1z);
-        if (active) {
+        if (active && Ge64) {
           Ge64[0 * NP + q] = g00;
           Ge64[1 * NP + q] = g01;
           Ge64[2 * NP + q] = g11;
@@ -671,25 +1026,27 @@ __global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ eta, con
   }
 
 template <int P, int DIM>
-static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, hipStream_t s) {
+static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, bool store_G, bool h_is_total,
+                            hipStream_t s) {
   using S = Sh<P, DIM>;
   const int64_t hs = (int64_t)c.n_eh * c.nh;
   for (const auto &cr : c.colours) {
     if (cr.count == 0) continue;
     const int nb = (cr.count + S::CPB - 1) / S::CPB;
     k_geom<P, DIM><<<nb, S::NT, 0, s>>>(eta, h, c.d_hm, hs, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count,
-                                        c.nz, c.n_s, c.d_sigma, c.d_layer_s, c.d_G64, c.want32 ? c.d_G32 : nullptr,
-                                        c.d_diag, c.d_dinv, c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh,
-                                        c.d_err);
+                                        c.nz, c.n_s, c.d_sigma, c.d_layer_s, store_G ? c.d_G64 : nullptr,
+                                        (store_G && c.want32) ? c.d_G32 : nullptr, c.d_diag, c.d_dinv,
+                                        c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh, c.d_cg64,
+                                        c.want32 ? c.d_cg32 : nullptr, h_is_total ? 1 : 0, c.d_err);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_geom(Ctx &c, const double *eta, const double *h, hipStream_t s) {
+hipError_t launch_geom(Ctx &c, const double *eta, const double *h, bool store_G, bool h_is_total, hipStream_t s) {
   if (c.dim == 3) {
-    FNPF_DISPATCH(3, c.p, return (geom_impl<P_, 3>(c, eta, h, s)));
+    FNPF_DISPATCH(3, c.p, return (geom_impl<P_, 3>(c, eta, h, store_G, h_is_total, s)));
   } else {
-    FNPF_DISPATCH(2, c.p, return (geom_impl<P_, 2>(c, eta, h, s)));
+    FNPF_DISPATCH(2, c.p, return (geom_impl<P_, 2>(c, eta, h, store_G, h_is_total, s)));
   }
   return hipSuccess;
 }
@@ -698,12 +1055,35 @@ template <int P, int DIM, typename T, bool MASK, bool DOT>
 static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *partial, const int32_t *skip,
                              hipStream_t s) {
   using S = Sh<P, DIM>;
+  const int64_t hs = (int64_t)c.n_eh * c.nh;
+  const bool fused = c.apply_variant == 0;
+  const T *cg = nullptr, *hmT = nullptr, *sig = nullptr, *hds = nullptr;
+  if constexpr (sizeof(T) == 8) {
+    cg = (const T *)c.d_cg64;
+    hmT = (const T *)c.d_hm;
+    sig = (const T *)c.d_sigma;
+    hds = (const T *)c.d_half_ds;
+  } else {
+    cg = (const T *)c.d_cg32;
+    hmT = (const T *)c.d_hm32;
+    sig = (const T *)c.d_sigma32;
+    hds = (const T *)c.d_half_ds32;
+  }
   int off = 0;
   for (const auto &cr : c.colours) {
     if (cr.count == 0) continue;
     const int nb = (cr.count + S::CPB - 1) / S::CPB;
-    k_apply<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, G, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
-                                                       cr.count, c.nz, c.n_s, DOT ? partial + off : nullptr, skip);
+    if (fused)
+      k_apply_fused2<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags,
+                                                                c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
+                                                                DOT ? partial + off : nullptr, skip);
+    else if (c.apply_variant == 2)
+      k_apply_fused<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags,
+                                                               c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
+                                                               DOT ? partial + off : nullptr, skip);
+    else
+      k_apply<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, G, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
+                                                         cr.count, c.nz, c.n_s, DOT ? partial + off : nullptr, skip);
     off += nb;
   }
   return hipGetLastError();

@@ -63,6 +63,7 @@ SIGNATURES = {
     "fnpf_sizes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_node_coords": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fnpf_enable_fp32": (C.c_int, [C.c_void_p]),
+    "fnpf_set_apply_variant": (C.c_int, [C.c_void_p, C.c_int32]),
     "fnpf_geom": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_export_geometry": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_laplace_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
@@ -192,6 +193,10 @@ class Context:
         return xy[:, 0], xy[:, 1]
 
     # -- path ---------------------------------------------------------------------
+    def set_apply_variant(self, variant: int):
+        """0: fused geometry (default), 1: stored per-point factors."""
+        self._check(lib().fnpf_set_apply_variant(self._h, int(variant)), "fnpf_set_apply_variant")
+
     def enable_fp32(self):
         self._check(lib().fnpf_enable_fp32(self._h), "fnpf_enable_fp32")
 

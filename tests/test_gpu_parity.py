@@ -63,7 +63,7 @@ CASES = ["slice_periodic", "slice_walls", "box_periodic", "box_mixed", "box_wall
 class Pair:
     """The same workload on both sides: oracle arrays and a library context."""
 
-    def __init__(self, wl, fp32=False):
+    def __init__(self, wl, fp32=False, variant=0):
         self.wl = wl
         self.m = wl.mesh
         self.xh = geo.horizontal_coords(self.m)
@@ -72,6 +72,8 @@ class Pair:
         self.eta = np.asarray(wl.eta0(self.x, self.y), dtype=np.float64)
         self.phis = np.asarray(wl.phi0(self.x, self.y), dtype=np.float64)
         self.ctx = fnpf.Context(self.m, g=wl.g)
+        if variant:
+            self.ctx.set_apply_variant(variant)
         if fp32:
             self.ctx.enable_fp32()
         self.d_h, self.d_eta, self.d_phis = dev(self.h), dev(self.eta), dev(self.phis)
@@ -88,9 +90,10 @@ def test_node_coords(name):
     assert np.abs(xy - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("name", CASES)
-def test_geometry_parity(name):
-    pr = Pair(_case(name), fp32=True)
+def test_geometry_parity(name, variant):
+    pr = Pair(_case(name), fp32=True, variant=variant)
     pr.ctx.geom(pr.d_eta, pr.d_h)
     G, diag = pr.ctx.export_geometry(fnpf.F64)
     G32, _ = pr.ctx.export_geometry(fnpf.F32)
@@ -119,9 +122,10 @@ def test_apply_equals_dense_matrix(name):
     assert np.abs(Ag @ np.ones(n)).max() <= 1e-12 * np.abs(A).max()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("name", CASES)
-def test_apply_random_fp64_fp32(name):
-    pr = Pair(_case(name), fp32=True)
+def test_apply_random_fp64_fp32(name, variant):
+    pr = Pair(_case(name), fp32=True, variant=variant)
     pr.ctx.geom(pr.d_eta, pr.d_h)
     Go, _, _ = pr.oracle_factors()
     rng = np.random.default_rng(11)
@@ -238,6 +242,10 @@ def test_c2_full_size_apply_and_solve():
     yo = op.apply(pr.m, Go, xv)
     assert rel(host(pr.ctx.laplace_apply(dev(xv))), yo) < 1e-13
     assert rel(host(pr.ctx.laplace_apply(dev(xv).float())), yo) < 2e-6
+    stored = Pair(wl, fp32=True, variant=1)
+    stored.ctx.geom(stored.d_eta, stored.d_h)
+    assert rel(host(stored.ctx.laplace_apply(dev(xv))), yo) < 1e-13
+    del stored
     for precision, rtol in ((0, 1e-10), (1, 1e-10)):
         phi, info = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precision=precision, rtol=rtol))
         assert info["status"] == "OK"

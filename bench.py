@@ -128,6 +128,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-steps", action="store_true")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only the apply loops (FP64, FP32) and a calibration copy of n_v doubles (for counters)")
+    ap.add_argument("--variant", type=int, default=0, help="apply variant: 0 fused geometry, 1 stored factors")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -149,6 +152,7 @@ def main():
           f"setup {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     # -- apply throughput (FP64 and FP32) at the initial geometry -----------------------
+    ctx.set_apply_variant(args.variant)
     ctx.geom(s.eta0, s.h)
     torch.cuda.synchronize()
     g = torch.Generator(device="cuda").manual_seed(0)
@@ -158,6 +162,17 @@ def main():
     n_q = m.n_e * (m.p + 1) ** m.dim
     print(f"[bench] apply f64 {t64 * 1e3:.3f} ms ({m.n_v / t64 / 1e9:.1f} GDOF/s), "
           f"f32 {t32 * 1e3:.3f} ms ({m.n_v / t32 / 1e9:.1f} GDOF/s)", file=sys.stderr, flush=True)
+    if args.apply_only:
+        # calibration copy: a plain device-to-device copy of n_v doubles (8 n_v bytes read and written)
+        ycopy = torch.empty_like(x64)
+        for _ in range(5):
+            ycopy.copy_(x64)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(mode="apply-only", workload=wl.name, variant=args.variant, apply_ms_f64=t64 * 1e3,
+                              apply_ms_f32=t32 * 1e3, copy_bytes_each_way=8 * m.n_v,
+                              algorithmic_bytes_f64=apply_bytes(m.n_v, n_q, 8) if args.variant == 1 else
+                              16 * m.n_v)), flush=True)
+        return
 
     # -- ERK4 steps --------------------------------------------------------------------
     o_mixed = fnpf.default_opts(precision=1, rtol=args.rtol, inner_rtol=1e-4, check_every=25, max_outer=30)

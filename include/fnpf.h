@@ -229,10 +229,49 @@ fnpf_status fnpf_set_relaxation(fnpf_ctx ctx, const double *cr, const double *et
  * in place on eta[n_s] and phi_s[n_s] (device FP64), depth h[n_s] (device),
  * followed by relaxation at t + dt.  The volume potential of the previous
  * stage is the PCG warm start (kept in the context).  tape (device, may be
- * NULL) receives the four stage potentials [4][n_v]; info (host, may be NULL)
- * receives one record per stage. */
+ * NULL) receives, per stage s = 0..3, a record of n_v + 2 n_s doubles:
+ * the stage's volume potential, then its surface elevation and surface
+ * potential (tape[s*(n_v+2 n_s) ...]); it is the input of fnpf_rk4_step_vjp.
+ * info (host, may be NULL) receives one record per stage. */
 fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phi_s, const double *h, double t, double dt,
                           const fnpf_solve_opts *opts, double *tape, fnpf_solve_info *info, void *stream);
+
+/* ---- Adjoint (vector-Jacobian products).  The paper has no adjoint; these
+ * differentiate the discrete path above exactly (up to the solver tolerance).
+ * "(+=)" marks device arrays that are accumulated into, never overwritten. */
+
+/* VJP of fnpf_rhs: given deta_bar, dphi_bar [n_s], adds the contributions to
+ * eta_bar (+=), phis_bar (+=) and w_bar (+=) [n_s]. */
+fnpf_status fnpf_rhs_vjp(fnpf_ctx ctx, const double *eta, const double *phi_s, const double *w_s,
+                         const double *deta_bar, const double *dphi_bar, double *eta_bar, double *phis_bar,
+                         double *w_bar, void *stream);
+
+/* VJP of fnpf_w_surface for the geometry of the last fnpf_geom: from w_s and
+ * w_bar [n_s], adds to phi_bar (+=) [n_v] (top element layer only) and to
+ * eta_bar (+=), h_bar (+=) [n_s] (the recovery divides by eta + h). */
+fnpf_status fnpf_w_surface_vjp(fnpf_ctx ctx, const double *w_s, const double *w_bar, double *phi_bar,
+                               double *eta_bar, double *h_bar, void *stream);
+
+/* Adjoint Laplace solve (the operator is symmetric): A_II lambda_I = phi_bar_I,
+ * lambda_S = 0, same options and stopping rule as fnpf_solve; lambda [n_v]
+ * holds the initial guess on entry.  Synchronises the stream. */
+fnpf_status fnpf_solve_adjoint(fnpf_ctx ctx, const double *phi_bar, double *lambda, const fnpf_solve_opts *opts,
+                               fnpf_solve_info *info, void *stream);
+
+/* VJP of the geometry dependence of the solve: adds d(-lambda^T A(eta, h) phi)
+ * to eta_bar (+=) and h_bar (+=) [n_s], for the geometry of the last
+ * fnpf_geom (lambda, phi [n_v]). */
+fnpf_status fnpf_geom_vjp(fnpf_ctx ctx, const double *lambda, const double *phi, double *eta_bar, double *h_bar,
+                          void *stream);
+
+/* VJP of one fnpf_rk4_step taken from its tape: on entry eta_bar, phis_bar
+ * [n_s] hold the adjoint of the step's output state; on exit, of its input
+ * state; h_bar (+=) accumulates the adjoint of the depth.  Runs 4 adjoint
+ * solves (opts) and recomputes the stage geometry; info (host, may be NULL)
+ * gets one record per stage (index = stage). */
+fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt, const double *tape,
+                              double *eta_bar, double *phis_bar, double *h_bar, const fnpf_solve_opts *opts,
+                              fnpf_solve_info *info, void *stream);
 
 /* Copy the context's warm-start potential to/from phi[n_v] (device FP64);
  * phi == NULL in set_ resets it to zero. */

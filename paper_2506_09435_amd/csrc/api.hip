@@ -100,6 +100,16 @@ void free_all(Ctx &c) {
   dfree(c.d_sc);
   if (c.h_sc) (void)hipHostFree(c.h_sc);
   c.h_sc = nullptr;
+  dfree(c.d_lam);
+  dfree(c.d_phibar);
+  dfree(c.d_kbe);
+  dfree(c.d_kbp);
+  dfree(c.d_ybe);
+  dfree(c.d_ybp);
+  dfree(c.d_acce);
+  dfree(c.d_accp);
+  dfree(c.d_wbar);
+  dfree(c.d_zero_s);
   dfree(c.d_cr);
   dfree(c.d_rec);
   dfree(c.d_res);
@@ -141,6 +151,18 @@ fnpf_status ensure32(Ctx &c) {
   HIPCHK(dalloc(&c.d_d32, c.n_v));
   c.want32 = true;
   c.have_geom32 = false;
+  return FNPF_OK;
+}
+
+fnpf_status ensure_adjoint(Ctx &c, hipStream_t s) {
+  if (c.have_adjoint) return FNPF_OK;
+  HIPCHK(dalloc(&c.d_lam, c.n_v));
+  HIPCHK(dalloc(&c.d_phibar, c.n_v));
+  double **surf[8] = {&c.d_kbe, &c.d_kbp, &c.d_ybe, &c.d_ybp, &c.d_acce, &c.d_accp, &c.d_wbar, &c.d_zero_s};
+  for (auto p : surf) HIPCHK(dalloc(p, c.n_s));
+  HIPCHK(launch_fill(c.d_lam, 0.0, c.n_v, s));
+  HIPCHK(launch_fill(c.d_zero_s, 0.0, c.n_s, s));
+  c.have_adjoint = true;
   return FNPF_OK;
 }
 
@@ -336,15 +358,15 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   std::vector<uint8_t> flags;
   std::vector<int32_t> cols;
   std::string e = build_host_mesh(*m, c, hm, flags, cols, mw, ms);
-  c.h_hm = hm;
-  c.ncg = c.dim == 3 ? 5 : 3;
-  c.h_half_ds.resize(c.nz);
-  for (int l = 0; l < c.nz; ++l) c.h_half_ds[l] = 0.5 * (c.h_layer_s[l + 1] - c.h_layer_s[l]);
   if (!e.empty()) {
     g_create_error = e;
     delete h;
     return FNPF_ERR_ARG;
   }
+  c.h_hm = hm;
+  c.ncg = c.dim == 3 ? 5 : 3;
+  c.h_half_ds.resize(c.nz);
+  for (int l = 0; l < c.nz; ++l) c.h_half_ds[l] = 0.5 * (c.h_layer_s[l + 1] - c.h_layer_s[l]);
   // total apply blocks over colours (partials of the fused dot product)
   {
     const int cpb = 256 / c.nh;
@@ -603,13 +625,18 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
   }
   if (info) std::memset(info, 0, 4 * sizeof(fnpf_solve_info));
   const double *ein = eta, *pin = phis;
+  const size_t rec = (size_t)c.n_v + 2 * (size_t)c.n_s;
   for (int stg = 0; stg < 4; ++stg) {
+    if (tape) {
+      HIPCHK(hipMemcpyAsync(tape + stg * rec + c.n_v, ein, c.n_s * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(tape + stg * rec + c.n_v + c.n_s, pin, c.n_s * sizeof(double), hipMemcpyDeviceToDevice,
+                            s));
+    }
     st = geom_impl(c, ein, h, s);
     if (st != FNPF_OK) return st;
     st = solve_impl(c, pin, nullptr, c.d_phi, o, info ? info + stg : nullptr, s);
     if (st != FNPF_OK) return st;
-    if (tape) HIPCHK(hipMemcpyAsync(tape + (size_t)stg * c.n_v, c.d_phi, c.n_v * sizeof(double),
-                                    hipMemcpyDeviceToDevice, s));
+    if (tape) HIPCHK(hipMemcpyAsync(tape + stg * rec, c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_wsurf(c, c.d_phi, c.d_w, s));
     RkStageArgs a{};
     a.eta0 = eta;
@@ -642,6 +669,124 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
     ein = a.out_e;
     pin = a.out_p;
   }
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_rhs_vjp(fnpf_ctx ctx, const double *eta, const double *phis, const double *w, const double *deta_bar,
+                         const double *dphi_bar, double *eta_bar, double *phis_bar, double *w_bar, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!eta || !phis || !w || !deta_bar || !dphi_bar || !eta_bar || !phis_bar || !w_bar)
+    return fail(&c, FNPF_ERR_ARG, "fnpf_rhs_vjp: null device pointer");
+  HIPCHK(launch_rhs_vjp(c, eta, phis, w, deta_bar, dphi_bar, eta_bar, phis_bar, w_bar, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_w_surface_vjp(fnpf_ctx ctx, const double *w, const double *w_bar, double *phi_bar, double *eta_bar,
+                               double *h_bar, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!w || !w_bar || !phi_bar || !eta_bar || !h_bar)
+    return fail(&c, FNPF_ERR_ARG, "fnpf_w_surface_vjp: null device pointer");
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_w_surface_vjp before fnpf_geom");
+  HIPCHK(launch_wsurf_vjp(c, w_bar, w, phi_bar, eta_bar, h_bar, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_solve_adjoint(fnpf_ctx ctx, const double *phi_bar, double *lambda, const fnpf_solve_opts *opts,
+                               fnpf_solve_info *info, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  hipStream_t s = (hipStream_t)stream;
+  if (!phi_bar || !lambda) return fail(&c, FNPF_ERR_ARG, "fnpf_solve_adjoint: null device pointer");
+  fnpf_solve_opts o;
+  fnpf_default_opts(&o);
+  if (opts) o = *opts;
+  fnpf_status st = validate_opts(c, o);
+  if (st != FNPF_OK) return st;
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_solve_adjoint before fnpf_geom");
+  if (o.precision == 1 && !c.have_geom32)
+    return fail(&c, FNPF_ERR_STATE, "mixed adjoint solve needs FP32 factors: fnpf_enable_fp32, then fnpf_geom");
+  st = ensure_adjoint(c, s);
+  if (st != FNPF_OK) return st;
+  // the operator is symmetric: A_II lambda_I = phi_bar_I with lambda_S = 0
+  return solve_impl(c, c.d_zero_s, phi_bar, lambda, o, info, s);
+}
+
+fnpf_status fnpf_geom_vjp(fnpf_ctx ctx, const double *lambda, const double *phi, double *eta_bar, double *h_bar,
+                          void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!lambda || !phi || !eta_bar || !h_bar) return fail(&c, FNPF_ERR_ARG, "fnpf_geom_vjp: null device pointer");
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_geom_vjp before fnpf_geom");
+  HIPCHK(launch_geom_vjp(c, lambda, phi, eta_bar, h_bar, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt, const double *tape,
+                              double *eta_bar, double *phis_bar, double *h_bar, const fnpf_solve_opts *opts,
+                              fnpf_solve_info *info, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  hipStream_t s = (hipStream_t)stream;
+  if (!h || !tape || !eta_bar || !phis_bar || !h_bar)
+    return fail(&c, FNPF_ERR_ARG, "fnpf_rk4_step_vjp: null device pointer");
+  if (!(dt > 0.0)) return fail(&c, FNPF_ERR_ARG, "fnpf_rk4_step_vjp: dt must be > 0");
+  fnpf_solve_opts o;
+  fnpf_default_opts(&o);
+  if (opts) o = *opts;
+  fnpf_status st = validate_opts(c, o);
+  if (st != FNPF_OK) return st;
+  if (o.precision == 1) {
+    st = ensure32(c);
+    if (st != FNPF_OK) return st;
+  }
+  st = ensure_adjoint(c, s);
+  if (st != FNPF_OK) return st;
+  if (info) std::memset(info, 0, 4 * sizeof(fnpf_solve_info));
+  const size_t rec = (size_t)c.n_v + 2 * (size_t)c.n_s;
+  const int64_t ns = c.n_s;
+  // relaxation acted last: y_{n+1} = (1 - C_r) (y_n + sum b dt k) + C_r f_true(t + dt)
+  if (c.have_relax) {
+    HIPCHK(launch_relax_vjp(eta_bar, c.d_cr, ns, s));
+    HIPCHK(launch_relax_vjp(phis_bar, c.d_cr, ns, s));
+  }
+  // accumulators of y_n bar start with the direct path
+  HIPCHK(hipMemcpyAsync(c.d_acce, eta_bar, ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(c.d_accp, phis_bar, ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int stg = 3; stg >= 0; --stg) {
+    const double *phi_s = tape + stg * rec;
+    const double *eta_s = phi_s + c.n_v;
+    const double *pin_s = eta_s + ns;
+    // k bar of this stage: b_s dt ybar' + c_{s+1} dt Ybar_{s+1}
+    if (stg == 3) {
+      HIPCHK(launch_lincomb(c.d_kbe, kRkB[stg] * dt, eta_bar, 0.0, nullptr, ns, s));
+      HIPCHK(launch_lincomb(c.d_kbp, kRkB[stg] * dt, phis_bar, 0.0, nullptr, ns, s));
+    } else {
+      HIPCHK(launch_lincomb(c.d_kbe, kRkB[stg] * dt, eta_bar, kRkC[stg + 1] * dt, c.d_ybe, ns, s));
+      HIPCHK(launch_lincomb(c.d_kbp, kRkB[stg] * dt, phis_bar, kRkC[stg + 1] * dt, c.d_ybp, ns, s));
+    }
+    // stage VJP at Y_s
+    st = geom_impl(c, eta_s, h, s);
+    if (st != FNPF_OK) return st;
+    HIPCHK(launch_wsurf(c, phi_s, c.d_w, s));
+    HIPCHK(launch_fill(c.d_ybe, 0.0, ns, s));
+    HIPCHK(launch_fill(c.d_ybp, 0.0, ns, s));
+    HIPCHK(launch_fill(c.d_wbar, 0.0, ns, s));
+    HIPCHK(launch_rhs_vjp(c, eta_s, pin_s, c.d_w, c.d_kbe, c.d_kbp, c.d_ybe, c.d_ybp, c.d_wbar, s));
+    HIPCHK(launch_fill(c.d_phibar, 0.0, c.n_v, s));
+    HIPCHK(launch_wsurf_vjp(c, c.d_wbar, c.d_w, c.d_phibar, c.d_ybe, h_bar, s));
+    st = solve_impl(c, c.d_zero_s, c.d_phibar, c.d_lam, o, info ? info + stg : nullptr, s);
+    if (st != FNPF_OK) return st;
+    HIPCHK(launch_apply(c, FNPF_F64, c.d_lam, c.d_q, false, nullptr, nullptr, s));
+    HIPCHK(launch_surface_adj(c.d_ybp, c.d_phibar, c.d_q, c.n_v, ns, s));
+    HIPCHK(launch_geom_vjp(c, c.d_lam, phi_s, c.d_ybe, h_bar, s));
+    HIPCHK(launch_lincomb(c.d_acce, 1.0, c.d_acce, 1.0, c.d_ybe, ns, s));
+    HIPCHK(launch_lincomb(c.d_accp, 1.0, c.d_accp, 1.0, c.d_ybp, ns, s));
+  }
+  HIPCHK(hipMemcpyAsync(eta_bar, c.d_acce, ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(phis_bar, c.d_accp, ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+  (void)t;
   return FNPF_OK;
 }
 

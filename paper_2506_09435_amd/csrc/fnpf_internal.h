@@ -78,7 +78,20 @@ struct RkStageArgs {
 hipError_t launch_rhs(Ctx &c, const double *eta, const double *phi_s, const double *w, const RkStageArgs &a,
                       hipStream_t s);
 
+// adjoint kernels (adjoint_kernels.inc); outputs are accumulated
+hipError_t launch_rhs_vjp(Ctx &c, const double *eta, const double *phs, const double *w, const double *kbe,
+                          const double *kbp, double *eta_bar, double *phs_bar, double *w_bar, hipStream_t s);
+hipError_t launch_wsurf_vjp(Ctx &c, const double *wbar, const double *w, double *phi_bar, double *eta_bar,
+                            double *h_bar, hipStream_t s);
+hipError_t launch_geom_vjp(Ctx &c, const double *lam, const double *phi, double *eta_bar, double *h_bar,
+                           hipStream_t s);
+
 // vector kernels (kernels_vec.hip)
+hipError_t launch_lincomb(double *out, double a, const double *x, double b, const double *y, int64_t n,
+                          hipStream_t s);
+hipError_t launch_relax_vjp(double *v, const double *cr, int64_t n, hipStream_t s);
+hipError_t launch_surface_adj(double *phis_bar, const double *phibar, const double *Alam, int64_t n_v, int64_t n_s,
+                              hipStream_t s);
 hipError_t launch_set_lift(double *v, const double *phis, int64_t n_v, int64_t n_s, hipStream_t s);
 hipError_t launch_copy_top(double *x, const double *phis, int64_t n_v, int64_t n_s, hipStream_t s);
 hipError_t launch_bnorm(const double *f, const double *y, int64_t n_v, int64_t n_s, double *partial,
@@ -163,6 +176,11 @@ struct Ctx {
   int n_partial = 0;
   PcgScalars *d_sc = nullptr;             // [2]: outer/plain, inner
   PcgScalars *h_sc = nullptr;             // pinned host mirror
+  // adjoint workspaces (allocated on first use)
+  double *d_lam = nullptr, *d_phibar = nullptr;
+  double *d_kbe = nullptr, *d_kbp = nullptr, *d_ybe = nullptr, *d_ybp = nullptr;
+  double *d_acce = nullptr, *d_accp = nullptr, *d_wbar = nullptr, *d_zero_s = nullptr;
+  bool have_adjoint = false;
   // relaxation
   double *d_cr = nullptr, *d_rec = nullptr, *d_res = nullptr, *d_rpc = nullptr, *d_rps = nullptr;
   double relax_omega = 0.0, relax_tramp = 0.0;

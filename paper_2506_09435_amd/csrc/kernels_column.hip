@@ -1187,4 +1187,6 @@ hipError_t launch_rhs(Ctx &c, const double *eta, const double *phi_s, const doub
   return hipSuccess;
 }
 
+#include "adjoint_kernels.inc"
+
 }  // namespace fnpf

@@ -255,7 +255,41 @@ __global__ void k_add_f32(double *x, const float *d, int64_t n) {
     x[i] += (double)d[i];
 }
 
+__global__ void k_lincomb(double *out, double a, const double *x, double b, const double *y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (x ? a * x[i] : 0.0) + (y ? b * y[i] : 0.0);
+}
+
+__global__ void k_relax_vjp(double *v, const double *cr, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] *= (1.0 - cr[i]);
+}
+
+// phi_s bar += phi_bar(surface level) - (A lambda)(surface level)
+__global__ void k_surface_adj(double *phis_bar, const double *phibar, const double *Alam, int64_t n_s,
+                              int64_t top0) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_s; i += (int64_t)gridDim.x * blockDim.x)
+    phis_bar[i] += phibar[top0 + i] - Alam[top0 + i];
+}
+
 }  // namespace
+
+hipError_t launch_lincomb(double *out, double a, const double *x, double b, const double *y, int64_t n,
+                          hipStream_t s) {
+  k_lincomb<<<kVecBlocks, kVecThreads, 0, s>>>(out, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_relax_vjp(double *v, const double *cr, int64_t n, hipStream_t s) {
+  k_relax_vjp<<<kVecBlocks, kVecThreads, 0, s>>>(v, cr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_surface_adj(double *phis_bar, const double *phibar, const double *Alam, int64_t n_v, int64_t n_s,
+                              hipStream_t s) {
+  k_surface_adj<<<kVecBlocks, kVecThreads, 0, s>>>(phis_bar, phibar, Alam, n_s, n_v - n_s);
+  return hipGetLastError();
+}
 
 hipError_t launch_set_lift(double *v, const double *phis, int64_t n_v, int64_t n_s, hipStream_t s) {
   k_set_lift<<<kVecBlocks, kVecThreads, 0, s>>>(v, phis, n_v, n_v - n_s);

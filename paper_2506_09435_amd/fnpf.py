@@ -75,6 +75,12 @@ SIGNATURES = {
                                       C.c_double, C.c_double]),
     "fnpf_rk4_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fnpf_rhs_vjp": (C.c_int, [C.c_void_p] + [C.c_void_p] * 8 + [C.c_void_p]),
+    "fnpf_w_surface_vjp": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5 + [C.c_void_p]),
+    "fnpf_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fnpf_geom_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fnpf_rk4_step_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_get_warm_start": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_set_warm_start": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_sync": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -279,6 +285,57 @@ class Context:
                                  _ptr(h, torch.float64), float(t), float(dt), C.byref(o),
                                  _ptr(tape, torch.float64), infos, _stream(stream))
         self._check(st, "fnpf_rk4_step")
+        return [infos[k].as_dict() for k in range(4)]
+
+    # -- adjoint --------------------------------------------------------------------
+    @property
+    def tape_record(self):
+        """Doubles per stage in an fnpf_rk4_step tape: n_v + 2 n_s."""
+        return self.n_v + 2 * self.n_s
+
+    def new_tape(self):
+        import torch
+        return torch.empty(4 * self.tape_record, dtype=torch.float64, device=self.device)
+
+    def rhs_vjp(self, eta, phi_s, w, deta_bar, dphi_bar, eta_bar, phis_bar, w_bar, stream=None):
+        import torch
+        f = torch.float64
+        self._check(lib().fnpf_rhs_vjp(self._h, _ptr(eta, f), _ptr(phi_s, f), _ptr(w, f), _ptr(deta_bar, f),
+                                       _ptr(dphi_bar, f), _ptr(eta_bar, f), _ptr(phis_bar, f), _ptr(w_bar, f),
+                                       _stream(stream)), "fnpf_rhs_vjp")
+
+    def w_surface_vjp(self, w, w_bar, phi_bar, eta_bar, h_bar, stream=None):
+        import torch
+        f = torch.float64
+        self._check(lib().fnpf_w_surface_vjp(self._h, _ptr(w, f), _ptr(w_bar, f), _ptr(phi_bar, f),
+                                             _ptr(eta_bar, f), _ptr(h_bar, f), _stream(stream)),
+                    "fnpf_w_surface_vjp")
+
+    def solve_adjoint(self, phi_bar, lam=None, opts=None, stream=None):
+        import torch
+        if lam is None:
+            lam = torch.zeros(self.n_v, dtype=torch.float64, device=self.device)
+        info = SolveInfo()
+        o = opts if opts is not None else default_opts()
+        self._check(lib().fnpf_solve_adjoint(self._h, _ptr(phi_bar, torch.float64), _ptr(lam, torch.float64),
+                                             C.byref(o), C.byref(info), _stream(stream)), "fnpf_solve_adjoint")
+        return lam, info.as_dict()
+
+    def geom_vjp(self, lam, phi, eta_bar, h_bar, stream=None):
+        import torch
+        f = torch.float64
+        self._check(lib().fnpf_geom_vjp(self._h, _ptr(lam, f), _ptr(phi, f), _ptr(eta_bar, f), _ptr(h_bar, f),
+                                        _stream(stream)), "fnpf_geom_vjp")
+
+    def rk4_step_vjp(self, h, t, dt, tape, eta_bar, phis_bar, h_bar, opts=None, stream=None):
+        """In place: (eta_bar, phis_bar) of the step output -> of its input; h_bar accumulated."""
+        import torch
+        f = torch.float64
+        infos = (SolveInfo * 4)()
+        o = opts if opts is not None else default_opts()
+        self._check(lib().fnpf_rk4_step_vjp(self._h, _ptr(h, f), float(t), float(dt), _ptr(tape, f),
+                                            _ptr(eta_bar, f), _ptr(phis_bar, f), _ptr(h_bar, f), C.byref(o),
+                                            infos, _stream(stream)), "fnpf_rk4_step_vjp")
         return [infos[k].as_dict() for k in range(4)]
 
     def get_warm_start(self, stream=None):

@@ -1,0 +1,137 @@
+"""Adjoint (VJP) of the HIP path against complex-step directional derivatives of the oracle.
+
+For a map y = F(x) the check is the dot-product identity <ybar, dF[v]> = <F^T ybar, v>, with
+dF[v] from the oracle run in complex arithmetic (x + i e v, e = 1e-30; no cancellation) and
+F^T ybar from the library's VJP kernels, on the same seeded inputs.  Tolerances follow the
+solver tolerances used (rtol 1e-13 for both the forward and the adjoint solves).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import geometry as geo
+from oracle import operator as op
+from oracle import solve as sv
+from oracle import surface as sf
+from oracle import timestep as ts
+from paper_2506_09435_amd import fnpf
+from workloads import configs
+
+EPS = 1e-30
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _case(name):
+    if name == "slice":
+        return configs.small_slice(nx=5, nz=2, p=4, periodic=True)
+    if name == "box":
+        return configs.small_box(nx=4, ny=3, nz=2, p=3, periodic=(True, False))
+    if name == "bar":
+        wl = configs.c4(nx=8, ny=2, nz=2, p=3, nsteps=1)
+        return wl
+    raise KeyError(name)
+
+
+def _setup(wl):
+    m = wl.mesh
+    xh = geo.horizontal_coords(m)
+    x, y = geo.node_xy(m)
+    h = np.asarray(wl.depth(x, y), dtype=np.float64)
+    rng = np.random.default_rng(17)
+    if wl.name == "C4":
+        eta = 0.01 * np.cos(2 * np.pi * x / 9.5) + 0.002 * rng.standard_normal(m.n_s)
+        phis = 0.02 * np.sin(2 * np.pi * x / 9.5)
+    else:
+        eta = np.asarray(wl.eta0(x, y), dtype=np.float64)
+        phis = np.asarray(wl.phi0(x, y), dtype=np.float64)
+    ctx = fnpf.Context(m, g=wl.g)
+    ra = wl.relaxation_arrays(x, y)
+    if ra is not None:
+        ctx.set_relaxation(*ra, omega=wl.relax_wave.omega, t_ramp=wl.t_ramp)
+    return m, xh, x, y, h, eta, phis, ctx, rng
+
+
+OPTS = dict(rtol=1e-13, check_every=10)
+
+
+@pytest.mark.parametrize("name", ["slice", "box"])
+def test_rhs_vjp(name):
+    wl = _case(name)
+    m, xh, x, y, h, eta, phis, ctx, rng = _setup(wl)
+    w = 0.3 * np.cos(x + 0.2) + 0.05 * rng.standard_normal(m.n_s)
+    ve, vp, vw = (rng.standard_normal(m.n_s) for _ in range(3))
+    kbe, kbp = rng.standard_normal(m.n_s), rng.standard_normal(m.n_s)
+    de, dp = sf.free_surface_rhs(m, eta + 1j * EPS * ve, phis + 1j * EPS * vp, w + 1j * EPS * vw, wl.g, xh=xh)
+    lhs = kbe @ (de.imag / EPS) + kbp @ (dp.imag / EPS)
+    eb, pb, wb = (torch.zeros(m.n_s, dtype=torch.float64, device="cuda") for _ in range(3))
+    ctx.rhs_vjp(dev(eta), dev(phis), dev(w), dev(kbe), dev(kbp), eb, pb, wb)
+    rhs = host(eb) @ ve + host(pb) @ vp + host(wb) @ vw
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+def _w_of(m, xh, eta, phis, h):
+    G, _, _ = geo.factors(m, eta, h, xh)
+    phi = sv.solve_dense(m, op.assemble_dense(m, G), phis)
+    return sf.w_surface(m, phi, eta, h, xh), phi
+
+
+@pytest.mark.parametrize("name", ["slice", "box", "bar"])
+def test_solve_and_geometry_vjp(name):
+    """(eta, phi_s, h) -> w through geometry, the Dirichlet-lifted solve and w recovery."""
+    wl = _case(name)
+    m, xh, x, y, h, eta, phis, ctx, rng = _setup(wl)
+    ve, vp, vh = (rng.standard_normal(m.n_s) * s for s in (0.01, 1.0, 0.01))
+    wbar = rng.standard_normal(m.n_s)
+    wc, _ = _w_of(m, xh, eta + 1j * EPS * ve, phis + 1j * EPS * vp, h + 1j * EPS * vh)
+    lhs = wbar @ (wc.imag / EPS)
+    # library chain
+    d_eta, d_h = dev(eta), dev(h)
+    ctx.geom(d_eta, d_h)
+    phi, info = ctx.solve(dev(phis), opts=fnpf.default_opts(**OPTS))
+    w = ctx.w_surface(phi)
+    w_ref, phi_ref = _w_of(m, xh, eta, phis, h)
+    assert np.abs(host(w) - w_ref).max() < 1e-10 * np.abs(w_ref).max()
+    phibar = torch.zeros(m.n_v, dtype=torch.float64, device="cuda")
+    eb = torch.zeros(m.n_s, dtype=torch.float64, device="cuda")
+    hb = torch.zeros_like(eb)
+    ctx.w_surface_vjp(w, dev(wbar), phibar, eb, hb)
+    lam, _ = ctx.solve_adjoint(phibar, opts=fnpf.default_opts(**OPTS))
+    Alam = ctx.laplace_apply(lam)
+    top = sv.surface_slice(m)
+    pb = host(phibar)[top] - host(Alam)[top]
+    ctx.geom_vjp(lam, phi, eb, hb)
+    rhs = host(eb) @ ve + pb @ vp + host(hb) @ vh
+    assert abs(lhs - rhs) <= 1e-9 * abs(lhs)
+
+
+@pytest.mark.parametrize("name", ["slice", "box", "bar"])
+def test_rk4_step_vjp(name):
+    """One ERK4 step (with relaxation for the bar case): adjoint vs complex step."""
+    wl = _case(name)
+    m, xh, x, y, h, eta, phis, ctx, rng = _setup(wl)
+    md = ts.Model(wl, solver="dense")
+    t, dt = 0.37, 0.03
+    ve, vp, vh = (rng.standard_normal(m.n_s) * s for s in (0.01, 0.1, 0.01))
+    ybe, ybp = rng.standard_normal(m.n_s), rng.standard_normal(m.n_s)
+    e1, p1 = md.rk4_step(eta + 1j * EPS * ve, phis + 1j * EPS * vp, t, dt, h=h + 1j * EPS * vh)
+    lhs = ybe @ (e1.imag / EPS) + ybp @ (p1.imag / EPS)
+    e, p = dev(eta), dev(phis)
+    tape = ctx.new_tape()
+    o = fnpf.default_opts(**OPTS)
+    ctx.rk4_step(e, p, dev(h), t, dt, opts=o, tape=tape)
+    assert np.abs(host(e) - e1.real).max() < 1e-10 * np.abs(e1.real).max()
+    eb, pb = dev(ybe), dev(ybp)
+    hb = torch.zeros(m.n_s, dtype=torch.float64, device="cuda")
+    ctx.rk4_step_vjp(dev(h), t, dt, tape, eb, pb, hb, opts=o)
+    rhs = host(eb) @ ve + host(pb) @ vp + host(hb) @ vh
+    assert abs(lhs - rhs) <= 1e-9 * abs(lhs)

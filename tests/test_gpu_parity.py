@@ -186,7 +186,7 @@ def test_rk4_step_parity(name, precision):
     dt = 0.02
     e1, p1 = md.rk4_step(pr.eta, pr.phis, 0.0, dt)
     e, p = pr.d_eta.clone(), pr.d_phis.clone()
-    tape = torch.zeros(4 * pr.m.n_v, dtype=torch.float64, device="cuda")
+    tape = pr.ctx.new_tape()
     opts = fnpf.default_opts(precision=precision, rtol=1e-13 if precision == 0 else 1e-12, inner_rtol=1e-3)
     infos = pr.ctx.rk4_step(e, p, pr.d_h, 0.0, dt, opts=opts, tape=tape)
     tol = 1e-10 if precision == 0 else 1e-8

@@ -118,6 +118,92 @@ def cpu_baseline(wl, target_s=10.0):
                        f"{reps} reps in {el:.1f} s; DoF counted as columns x n_v/n_eh")
 
 
+def adjoint_leg(nsteps, rtol, fd_dirs):
+    """C4 bar: gauge misfit over nsteps ERK4 steps, gradient w.r.t. 64 bathymetry controls and eta0.
+
+    Returns the forward and backward (checkpoint recomputation + adjoint) times, their ratio
+    and, when fd_dirs > 0, central-difference checks of the adjoint gradient (FP64, rtol 1e-12).
+    """
+    import numpy as np
+    import torch
+    from paper_2506_09435_amd import fnpf
+    from paper_2506_09435_amd.autograd import gauge_matrix, rollout
+    from workloads import configs, waves
+
+    wl = configs.c4(nsteps=nsteps)
+    m = wl.mesh
+    fctx = fnpf.Context(m, g=wl.g)
+    x, y = fctx.node_xy()
+    ra = wl.relaxation_arrays(x, y)
+    fctx.set_relaxation(*ra, omega=wl.relax_wave.omega, t_ramp=wl.t_ramp)
+    xc, c0 = wl.meta["xc"], wl.meta["c0"]
+    B = torch.tensor(waves.piecewise_linear_matrix(x, xc), device="cuda")
+    P = gauge_matrix(fctx, wl.meta["gauges"])
+    rng = np.random.default_rng(1)
+    # twin experiment: observations from the perturbed bathymetry c_true
+    c_true = torch.tensor(wl.meta["c_true"], device="cuda")
+    zeros = torch.zeros(m.n_s, dtype=torch.float64, device="cuda")
+    # a short window starts from the incident linear wave over the whole flume (instead of
+    # rest), so that the gauges see the bathymetry within the differentiated steps
+    eta_in = torch.tensor(wl.relax_wave.eta(x, y, 0.0), device="cuda")
+    phi_in = torch.tensor(wl.relax_wave.phi(x, y, 0.0), device="cuda")
+    o = fnpf.default_opts(rtol=rtol, check_every=25)
+    with torch.no_grad():
+        obs = rollout(fctx, eta_in, phi_in, B @ c_true, 0.0, wl.dt, nsteps, opts=o) @ P.T
+
+    def loss(c, e0, opts):
+        traj = rollout(fctx, e0, phi_in, B @ c, 0.0, wl.dt, nsteps, opts=opts)
+        return 0.5 * ((traj @ P.T - obs) ** 2).sum()
+
+    c = torch.tensor(c0, device="cuda", requires_grad=True)
+    e0 = eta_in.clone().requires_grad_(True)
+    fctx.set_warm_start(None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        loss(c, e0, o)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    fctx.set_warm_start(None)
+    J = loss(c, e0, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    out = dict(workload=f"C4 bar 64x16x4 p=5 (n_v={m.n_v}), {nsteps} steps, 8 gauges, 64 controls + eta0, "
+                        f"FP64 forward and adjoint",
+               rtol=rtol, t_forward_s=t_fwd, t_backward_s=t_bwd, ratio=t_bwd / t_fwd,
+               grad_norm_c=float(c.grad.norm()), loss=float(J.detach()))
+    if fd_dirs > 0:
+        o12 = fnpf.default_opts(rtol=1e-12, check_every=25)
+        c = torch.tensor(c0, device="cuda", requires_grad=True)
+        e0 = eta_in.clone().requires_grad_(True)
+        loss(c, e0, o12).backward()
+        checks = []
+        for k in range(fd_dirs):
+            g = np.random.default_rng(wl.meta["fd_seed"] + k)
+            vc = torch.tensor(g.standard_normal(len(c0)) * 0.01, device="cuda")
+            if k == 0:
+                # smooth initial-elevation direction: a few seeded long-wave modes along the flume
+                kx = 2 * np.pi * np.arange(1, 5) / 38.0
+                amp, ph = g.standard_normal(4), g.uniform(0, 2 * np.pi, 4)
+                ve = torch.tensor(1e-3 * (amp[None, :] * np.cos(kx[None, :] * x[:, None] + ph[None, :])).sum(1),
+                                  device="cuda")
+            else:
+                ve = zeros
+            d_adj = float(c.grad @ vc + e0.grad @ ve)
+            eps = 1e-4
+            with torch.no_grad():
+                jp = float(loss(c.detach() + eps * vc, e0.detach() + eps * ve, o12))
+                jm = float(loss(c.detach() - eps * vc, e0.detach() - eps * ve, o12))
+            d_fd = (jp - jm) / (2 * eps)
+            checks.append(dict(adjoint=d_adj, fd=d_fd, rel=abs(d_adj - d_fd) / abs(d_fd)))
+            print(f"[bench] adjoint vs FD dir {k}: {checks[-1]}", file=sys.stderr, flush=True)
+        out["fd_checks"] = checks
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +217,8 @@ def main():
     ap.add_argument("--apply-only", action="store_true",
                     help="only the apply loops (FP64, FP32) and a calibration copy of n_v doubles (for counters)")
     ap.add_argument("--variant", type=int, default=0, help="apply variant: 0 fused geometry, 1 stored factors")
+    ap.add_argument("--adjoint-steps", type=int, default=40, help="C4 steps of the adjoint leg (0: skip)")
+    ap.add_argument("--adjoint-fd", type=int, default=0, help="finite-difference directions checked in the adjoint leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -197,6 +285,11 @@ def main():
         t_f64 = (time.perf_counter() - t0) / args.steps
         print(f"[bench] fp64 step {t_f64:.3f} s, iters {it_f64}", file=sys.stderr, flush=True)
 
+    adj = None
+    if args.adjoint_steps > 0:
+        adj = adjoint_leg(args.adjoint_steps, args.rtol, args.adjoint_fd)
+        print(f"[bench] adjoint leg {adj}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl)
@@ -215,7 +308,8 @@ def main():
         apply_ms=dict(f64=t64 * 1e3, f32=t32 * 1e3),
         s_per_rk4_step=dict(f64=t_f64, mixed=t_mixed),
         pcg_iters_per_stage=dict(f64=it_f64, mixed=it_mixed),
-        adjoint_forward_ratio=None,
+        adjoint_forward_ratio=None if adj is None else adj["ratio"],
+        adjoint=adj,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                       traffic=None, kernel="k_apply<6,3,double> (4 colour launches = one apply)",
                       algorithmic_bytes_per_apply=bytes64),

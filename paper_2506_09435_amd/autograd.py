@@ -1,0 +1,113 @@
+"""torch.autograd.Function over N ERK4 steps of the library, with sqrt(N) step checkpointing.
+
+Forward: N calls of fnpf_rk4_step from (eta0, phi0) with depth h; returns the surface
+elevation after every step, traj[n] = eta^{n+1} (shape [N, n_s]), and keeps only the state
+at every S-th step (S = ceil(sqrt(N)) by default).
+
+Backward: for each segment in reverse, the steps are recomputed from the segment's
+checkpoint with tapes (fnpf_rk4_step tape: stage potentials and stage states), then
+fnpf_rk4_step_vjp runs the stages in reverse (adjoint solves with the same SPD operator,
+geometry VJP).  The adjoint of the trajectory enters as ybar_eta += dL/d eta^{n}.
+Gradients are returned for eta0, phi0 and h.
+
+All numerical work is in the HIP library; this module orders the calls.
+"""
+
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import fnpf
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(actx, eta0, phi0, h, fctx, t0, dt, nsteps, opts, adj_opts, every):
+        every = every or max(1, int(math.ceil(math.sqrt(nsteps))))
+        e = eta0.detach().clone().contiguous()
+        p = phi0.detach().clone().contiguous()
+        hd = h.detach().contiguous()
+        traj = torch.empty((nsteps, fctx.n_s), dtype=torch.float64, device=e.device)
+        checkpoints = {}
+        t = t0
+        for n in range(nsteps):
+            if n % every == 0:
+                checkpoints[n] = (e.clone(), p.clone(), t)
+            fctx.rk4_step(e, p, hd, t, dt, opts=opts)
+            traj[n] = e
+            t = t0 + (n + 1) * dt
+        actx.fctx, actx.dt, actx.nsteps, actx.opts, actx.adj_opts, actx.every = fctx, dt, nsteps, opts, adj_opts, every
+        actx.checkpoints = checkpoints
+        actx.save_for_backward(hd)
+        return traj
+
+    @staticmethod
+    def backward(actx, gtraj):
+        (hd,) = actx.saved_tensors
+        fctx, dt, N, every = actx.fctx, actx.dt, actx.nsteps, actx.every
+        gtraj = gtraj.contiguous()
+        eb = torch.zeros(fctx.n_s, dtype=torch.float64, device=hd.device)
+        pb = torch.zeros_like(eb)
+        hb = torch.zeros_like(eb)
+        starts = sorted(actx.checkpoints)
+        for s0 in reversed(starts):
+            s1 = min(s0 + every, N)
+            e, p, t = actx.checkpoints[s0]
+            e, p = e.clone(), p.clone()
+            tapes, times = [], []
+            for n in range(s0, s1):
+                tape = fctx.new_tape()
+                times.append(t)
+                fctx.rk4_step(e, p, hd, t, dt, opts=actx.opts, tape=tape)
+                tapes.append(tape)
+                t = t + dt
+            for k in range(s1 - 1, s0 - 1, -1):
+                eb += gtraj[k]
+                fctx.rk4_step_vjp(hd, times[k - s0], dt, tapes[k - s0], eb, pb, hb, opts=actx.adj_opts)
+            del tapes
+        return eb, pb, hb, None, None, None, None, None, None, None
+
+
+def rollout(fctx, eta0, phi0, h, t0, dt, nsteps, opts=None, adj_opts=None, checkpoint_every=None):
+    """Differentiable trajectory eta^1..eta^N ([N, n_s]) of N ERK4 steps."""
+    opts = opts if opts is not None else fnpf.default_opts()
+    adj_opts = adj_opts if adj_opts is not None else opts
+    return _Rollout.apply(eta0, phi0, h, fctx, float(t0), float(dt), int(nsteps), opts, adj_opts, checkpoint_every)
+
+
+def gauge_matrix(fctx, points):
+    """Dense [n_gauges, n_s] surface Lagrange interpolation for axis-aligned quads/intervals.
+
+    Uses the library's GLL nodes (fnpf_gll) and the mesh corners; a helper for losses.
+    """
+    import numpy as np
+    mesh = fctx.mesh
+    p = mesh.p
+    x, _, _ = fnpf.gll(p)
+
+    def lag(t):
+        L = np.ones(p + 1)
+        for j in range(p + 1):
+            for m in range(p + 1):
+                if m != j:
+                    L[j] *= (t - x[m]) / (x[j] - x[m])
+        return L
+
+    P = np.zeros((len(points), mesh.n_s))
+    for g, pt in enumerate(points):
+        pt = np.atleast_1d(np.asarray(pt, dtype=np.float64))
+        for e in range(mesh.n_eh):
+            c = mesh.eh_corner[e]
+            lo, hi = c.min(0), c.max(0)
+            if np.all(pt >= lo - 1e-12) and np.all(pt <= hi + 1e-12):
+                ref = 2.0 * (pt - lo) / (hi - lo) - 1.0
+                w = lag(ref[0])
+                if mesh.dim == 3:
+                    w = (lag(ref[1])[:, None] * w[None, :]).ravel()
+                np.add.at(P[g], mesh.eh_nodes[e], w)
+                break
+        else:
+            raise ValueError(f"gauge {pt} outside the mesh")
+    return torch.tensor(P, dtype=torch.float64, device=fctx.device)

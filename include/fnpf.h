@@ -109,7 +109,12 @@ typedef struct {
  *   check_every is the number of iterations between host convergence checks
  *   (the iterations after convergence are skipped on the device, so results
  *   do not depend on it).  inner_rtol: relative reduction of each inner FP32
- *   solve; max_outer bounds the defect-correction sweeps.                  */
+ *   solve; max_outer bounds the defect-correction sweeps.
+ *   extrapolate (fnpf_rk4_step only): 1 starts stage s of a step from
+ *   2 phi_s(n-1) - phi_s(n-2), the same stage of the two previous steps,
+ *   once the context has seen two consecutive steps with the same dt; 0
+ *   always starts from the previous stage's potential.  Only the initial
+ *   guess changes; the converged solution does not.                         */
 typedef struct {
   int32_t precision;
   int32_t precond;
@@ -119,6 +124,7 @@ typedef struct {
   int32_t check_every;
   double inner_rtol;
   int32_t max_outer;
+  int32_t extrapolate;
 } fnpf_solve_opts;
 
 typedef struct {
@@ -129,7 +135,7 @@ typedef struct {
 } fnpf_solve_info;
 
 /* Defaults: FP64, Jacobi, rtol 1e-8, atol 0, max_iter 20000, check_every 25,
- * inner_rtol 1e-4, max_outer 30. */
+ * inner_rtol 1e-4, max_outer 30, extrapolate 1. */
 void fnpf_default_opts(fnpf_solve_opts *opts);
 
 /* Create a context on the current HIP device: validates and copies the mesh,
@@ -165,7 +171,10 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy);
  *   1 stored factors: fnpf_geom stores G (6 or 3 per point, FP64 and FP32)
  *     and the apply streams it from HBM;
  *   2 fused geometry with a fully unrolled schedule (more registers, fewer
- *     LDS accesses; kept for comparison).
+ *     LDS accesses; kept for comparison);
+ *   3, 4, 5 fused geometry with alternative schedules for p = 6 in 3D (3 one
+ *     column per workgroup, 4 without the next-layer prefetch, 5 zeta loops
+ *     unrolled by two; other degrees use the default schedule).
  * Switching to 1 invalidates the current geometry (call fnpf_geom again). */
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant);
 
@@ -274,7 +283,8 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
                               fnpf_solve_info *info, void *stream);
 
 /* Copy the context's warm-start potential to/from phi[n_v] (device FP64);
- * phi == NULL in set_ resets it to zero. */
+ * phi == NULL in set_ resets it to zero.  Both also clear the step history
+ * used by opts.extrapolate. */
 fnpf_status fnpf_get_warm_start(fnpf_ctx ctx, double *phi, void *stream);
 fnpf_status fnpf_set_warm_start(fnpf_ctx ctx, const double *phi, void *stream);
 

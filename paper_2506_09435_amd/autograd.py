@@ -31,6 +31,7 @@ class _Rollout(torch.autograd.Function):
         hd = h.detach().contiguous()
         traj = torch.empty((nsteps, fctx.n_s), dtype=torch.float64, device=e.device)
         checkpoints = {}
+        fctx.set_warm_start(None)
         t = t0
         for n in range(nsteps):
             if n % every == 0:
@@ -56,6 +57,7 @@ class _Rollout(torch.autograd.Function):
             s1 = min(s0 + every, N)
             e, p, t = actx.checkpoints[s0]
             e, p = e.clone(), p.clone()
+            fctx.set_warm_start(None)
             tapes, times = [], []
             for n in range(s0, s1):
                 tape = fctx.new_tape()

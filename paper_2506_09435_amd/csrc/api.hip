@@ -100,6 +100,8 @@ void free_all(Ctx &c) {
   dfree(c.d_sc);
   if (c.h_sc) (void)hipHostFree(c.h_sc);
   c.h_sc = nullptr;
+  for (int s = 0; s < 4; ++s)
+    for (int k = 0; k < 2; ++k) dfree(c.d_hist[s][k]);
   dfree(c.d_lam);
   dfree(c.d_phibar);
   dfree(c.d_kbe);
@@ -166,6 +168,13 @@ fnpf_status ensure_adjoint(Ctx &c, hipStream_t s) {
   return FNPF_OK;
 }
 
+fnpf_status ensure_history(Ctx &c) {
+  if (c.d_hist[0][0]) return FNPF_OK;
+  for (int s = 0; s < 4; ++s)
+    for (int k = 0; k < 2; ++k) HIPCHK(dalloc(&c.d_hist[s][k], c.n_v));
+  return FNPF_OK;
+}
+
 fnpf_status check_err_flag(Ctx &c, hipStream_t s) {
   int32_t flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, c.d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -177,7 +186,11 @@ fnpf_status check_err_flag(Ctx &c, hipStream_t s) {
   return FNPF_OK;
 }
 
-int apply_blocks(const Ctx &c) { return c.max_colour_blocks; }
+int apply_blocks(const Ctx &c) {
+  // the one-column-per-workgroup schedules (p = 6, 3D) launch one block per column
+  if (c.apply_variant == 0 && c.apply_tune == 1 && c.p == 6 && c.dim == 3) return c.n_eh;
+  return c.max_colour_blocks;
+}
 
 // PCG on A_II (FP64), x = phi holds the guess with its surface level set.
 fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, int &iters, hipStream_t s) {
@@ -248,6 +261,7 @@ fnpf_status validate_opts(Ctx &c, const fnpf_solve_opts &o) {
   if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || (o.rtol == 0.0 && o.atol == 0.0))
     return fail(&c, FNPF_ERR_ARG, "opts.rtol/atol must be >= 0 and not both 0");
   if (o.max_iter < 1 || o.check_every < 1) return fail(&c, FNPF_ERR_ARG, "opts.max_iter and check_every must be >= 1");
+  if (o.extrapolate != 0 && o.extrapolate != 1) return fail(&c, FNPF_ERR_ARG, "opts.extrapolate must be 0 or 1");
   if (o.precision == 1 && (!(o.inner_rtol > 0.0) || !(o.inner_rtol < 1.0) || o.max_outer < 1))
     return fail(&c, FNPF_ERR_ARG, "opts.inner_rtol must be in (0,1) and max_outer >= 1 for the mixed path");
   return FNPF_OK;
@@ -305,6 +319,7 @@ void fnpf_default_opts(fnpf_solve_opts *o) {
   o->check_every = 25;
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
+  o->extrapolate = 1;
 }
 
 const char *fnpf_status_string(fnpf_status s) {
@@ -432,7 +447,7 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   AL(c.d_wnum, c.n_s);
   AL(c.d_nk, c.n_s);
   AL(c.d_nd, c.n_s);
-  c.n_partial = std::max(3 * kVecBlocks, c.max_colour_blocks) + 16;
+  c.n_partial = std::max(std::max(3 * kVecBlocks, c.max_colour_blocks), c.n_eh) + 16;
   AL(c.d_partial, c.n_partial);
   AL(c.d_sc, 2);
 #undef UP
@@ -474,7 +489,9 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy) {
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
-  if (variant < 0 || variant > 2) return fail(&c, FNPF_ERR_ARG, "apply variant must be 0, 1 or 2");
+  if (variant < 0 || variant > 5) return fail(&c, FNPF_ERR_ARG, "apply variant must be in 0..5");
+  c.apply_tune = variant >= 3 ? variant - 2 : 0;
+  if (variant >= 3) variant = 0;
   if (variant == c.apply_variant) return FNPF_OK;
   c.apply_variant = variant;
   if (variant == 1) {
@@ -634,8 +651,20 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
     }
     st = geom_impl(c, ein, h, s);
     if (st != FNPF_OK) return st;
+    const bool extrap = o.extrapolate && c.hist_count >= 2 && c.hist_dt == dt;
+    if (extrap) {
+      // linear extrapolation in time from the same stage of the two previous steps
+      const int i1 = c.hist_head, i2 = 1 - c.hist_head;
+      HIPCHK(launch_lincomb(c.d_phi, 2.0, c.d_hist[stg][i1], -1.0, c.d_hist[stg][i2], c.n_v, s));
+    }
     st = solve_impl(c, pin, nullptr, c.d_phi, o, info ? info + stg : nullptr, s);
     if (st != FNPF_OK) return st;
+    if (o.extrapolate) {
+      st = ensure_history(c);
+      if (st != FNPF_OK) return st;
+      HIPCHK(hipMemcpyAsync(c.d_hist[stg][1 - c.hist_head], c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice,
+                            s));
+    }
     if (tape) HIPCHK(hipMemcpyAsync(tape + stg * rec, c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_wsurf(c, c.d_phi, c.d_w, s));
     RkStageArgs a{};
@@ -668,6 +697,14 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
     HIPCHK(launch_rhs(c, ein, pin, c.d_w, a, s));
     ein = a.out_e;
     pin = a.out_p;
+  }
+  if (o.extrapolate) {
+    // the slot written this step becomes the newest
+    c.hist_head = 1 - c.hist_head;
+    c.hist_count = (c.hist_dt == dt) ? std::min(c.hist_count + 1, 2) : 1;
+    c.hist_dt = dt;
+  } else {
+    c.hist_count = 0;  // a step taken without recording breaks the sequence
   }
   return FNPF_OK;
 }
@@ -793,6 +830,7 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
 fnpf_status fnpf_get_warm_start(fnpf_ctx ctx, double *phi, void *stream) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
+  c.hist_count = 0;
   if (!phi) return fail(&c, FNPF_ERR_ARG, "phi is NULL");
   HIPCHK(hipMemcpyAsync(phi, c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return FNPF_OK;
@@ -801,6 +839,7 @@ fnpf_status fnpf_get_warm_start(fnpf_ctx ctx, double *phi, void *stream) {
 fnpf_status fnpf_set_warm_start(fnpf_ctx ctx, const double *phi, void *stream) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
+  c.hist_count = 0;
   if (phi)
     HIPCHK(hipMemcpyAsync(c.d_phi, phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   else

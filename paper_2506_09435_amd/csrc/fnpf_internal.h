@@ -144,6 +144,7 @@ struct Ctx {
   double *d_mlump_s = nullptr;            // [n_s] sum_e w_i w_j det J_h (surface mass)
   // apply variant: 0 fused geometry (factors recomputed in registers), 1 stored factors
   int apply_variant = 0;
+  int apply_tune = 0;                     // schedule option of the fused apply (p = 6, 3D)
   double *d_cg64 = nullptr;               // [5|3][n_eh*nh] H, H_xi, h_xi, (H_eta, h_eta) per column node
   float *d_cg32 = nullptr;
   float *d_hm32 = nullptr;                // FP32 copy of d_hm
@@ -176,6 +177,11 @@ struct Ctx {
   int n_partial = 0;
   PcgScalars *d_sc = nullptr;             // [2]: outer/plain, inner
   PcgScalars *h_sc = nullptr;             // pinned host mirror
+  // same-stage solutions of the two previous steps (initial-guess extrapolation)
+  double *d_hist[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int hist_head = 0;                      // slot of the newest step
+  int hist_count = 0;
+  double hist_dt = 0.0;
   // adjoint workspaces (allocated on first use)
   double *d_lam = nullptr, *d_phibar = nullptr;
   double *d_kbe = nullptr, *d_kbp = nullptr, *d_ybe = nullptr, *d_ybp = nullptr;

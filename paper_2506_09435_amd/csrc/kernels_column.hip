@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void k_apply_fused(const T *__restrict__ x, T 
 // zeta part of the transposed contraction, y_zeta[k'] += D[k][k'] v_zeta[k], straight into a
 // register line; the backward loop is unrolled.  Live registers: the thread's D rows, its
 // vertical line, the y_zeta line and the column geometry.
-template <int P, int DIM, typename T, bool MASK, bool DOT>
+template <int P, int DIM, typename T, bool MASK, bool DOT, int CPBv = Sh<P, DIM>::CPB, bool PF = true, int UF = 1>
 __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T *__restrict__ y,
                                                       const T *__restrict__ cg, const T *__restrict__ hmT,
                                                       int64_t hstride, const T *__restrict__ sig,
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
                                                       const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
                                                       double *__restrict__ partial, const int32_t *__restrict__ skip) {
   using S = Sh<P, DIM>;
-  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
+  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = CPBv;
   __shared__ T su[CPB * NP];
   __shared__ T sx[CPB * NP];
   __shared__ T sy[DIM == 3 ? CPB * NP : 1];
@@ -470,12 +470,29 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
   ucol[0] = active ? x[hn] : T(0);
   const int vtop = P * nz;
 
-  for (int l = 0; l < nz; ++l) {
+  T nxt[N1];
+  if constexpr (PF) {
 #pragma unroll
-    for (int k = 1; k < N1; ++k) ucol[k] = active ? x[(int64_t)(l * P + k) * n_s + hn] : T(0);
+    for (int k = 1; k < N1; ++k) nxt[k] = active ? x[(int64_t)k * n_s + hn] : T(0);
+  }
+  for (int l = 0; l < nz; ++l) {
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 1; k < N1; ++k) ucol[k] = nxt[k];
+    } else {
+#pragma unroll
+      for (int k = 1; k < N1; ++k) ucol[k] = active ? x[(int64_t)(l * P + k) * n_s + hn] : T(0);
+    }
 #pragma unroll
     for (int k = 0; k < N1; ++k) u_c[k * NH + t] = ucol[k];
     __syncthreads();
+    if constexpr (PF) {
+      // issue the next layer's loads now; they complete behind this layer's arithmetic
+      if (l + 1 < nz) {
+#pragma unroll
+        for (int k = 1; k < N1; ++k) nxt[k] = active ? x[(int64_t)((l + 1) * P + k) * n_s + hn] : T(0);
+      }
+    }
 
     const T zz = half_ds[l] * H;
     const T izz = T(1) / zz;
@@ -483,7 +500,7 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
     T yz[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) yz[k] = T(0);
-#pragma unroll 1
+#pragma unroll UF
     for (int k = 0; k < N1; ++k) {
       T ux = T(0), uy = T(0), uz = T(0);
       const T *row = u_c + k * NH;
@@ -525,35 +542,49 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
     // own u entries are no longer read by other threads: reuse them for the output line
 #pragma unroll
     for (int k = 0; k < N1; ++k) u_c[k * NH + t] = yz[k];
-#pragma unroll 1
+#pragma unroll UF
     for (int k = 0; k < N1; ++k) {
-      T acc = u_c[k * NH + t];
+      // independent partial sums keep the FP64 FMA chains short
+      T a0 = u_c[k * NH + t], a1 = T(0), a2 = T(0), a3 = T(0);
       const T *rx = x_c + k * NH;
 #pragma unroll
-      for (int m = 0; m < N1; ++m) acc += Dci[m] * rx[j * N1 + m];
+      for (int m = 0; m < N1; m += 2) {
+        a1 += Dci[m] * rx[j * N1 + m];
+        if (m + 1 < N1) a2 += Dci[m + 1] * rx[j * N1 + m + 1];
+      }
       if constexpr (DIM == 3) {
         const T *ry = y_c + k * NH;
+        T b1 = T(0);
 #pragma unroll
-        for (int m = 0; m < N1; ++m) acc += Dcj[m] * ry[m * N1 + i];
+        for (int m = 0; m < N1; m += 2) {
+          a3 += Dcj[m] * ry[m * N1 + i];
+          if (m + 1 < N1) b1 += Dcj[m + 1] * ry[(m + 1) * N1 + i];
+        }
+        a3 += b1;
       }
-      u_c[k * NH + t] = acc;
+      u_c[k * NH + t] = (a0 + a1) + (a2 + a3);
     }
     if (active) {
       const int kend = (l == nz - 1) ? N1 : P;
+      T yv[N1], old[N1];
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        yv[k] = u_c[k * NH + t];
+        old[k] = T(0);
+      }
+      yv[0] += carry;
+      // colour schedule: all read-add-write loads of the line in flight together
+      if (!(fl & kFirst)) {
+#pragma unroll
+        for (int k = 0; k < N1; ++k)
+          if (k < kend) old[k] = y[(int64_t)(l * P + k) * n_s + hn];
+      }
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
         if (k < kend) {
           const int v = l * P + k;
-          const int64_t idx = (int64_t)v * n_s + hn;
-          T yv = u_c[k * NH + t];
-          if (k == 0) yv += carry;
-          T val;
-          if (MASK && v == vtop) {
-            y[idx] = T(0);
-            val = T(0);
-          } else {
-            val = scatter(y, idx, yv, fl);
-          }
+          const T val = (MASK && v == vtop) ? T(0) : yv[k] + old[k];
+          y[(int64_t)v * n_s + hn] = val;
           if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
         }
       }
@@ -562,7 +593,7 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
     ucol[0] = ucol[P];
   }
   if constexpr (DOT) {
-    double s = block_sum<S::NT>(dot);
+    double s = block_sum<CPB * NH>(dot);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
 }
@@ -1073,10 +1104,37 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
   for (const auto &cr : c.colours) {
     if (cr.count == 0) continue;
     const int nb = (cr.count + S::CPB - 1) / S::CPB;
-    if (fused)
+    if (fused) {
+      bool done = false;
+      if constexpr (P == 6 && DIM == 3) {
+        // alternative schedules kept for measurement: 1 one column per workgroup, 2 no
+        // next-layer prefetch, 3 k loops unrolled by two
+        const int tune = c.apply_tune;
+        if (tune == 1) {
+          k_apply_fused2<P, DIM, T, MASK, DOT, 1, true><<<cr.count, S::NH, 0, s>>>(
+              x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
+              DOT ? partial + off : nullptr, skip);
+          off += cr.count;
+          done = true;
+        } else if (tune == 2) {
+          k_apply_fused2<P, DIM, T, MASK, DOT, S::CPB, false><<<nb, S::NT, 0, s>>>(
+              x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
+              DOT ? partial + off : nullptr, skip);
+          off += nb;
+          done = true;
+        } else if (tune == 3) {
+          k_apply_fused2<P, DIM, T, MASK, DOT, S::CPB, true, 2><<<nb, S::NT, 0, s>>>(
+              x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
+              DOT ? partial + off : nullptr, skip);
+          off += nb;
+          done = true;
+        }
+      }
+      if (done) continue;
       k_apply_fused2<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags,
                                                                 c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
                                                                 DOT ? partial + off : nullptr, skip);
+    }
     else if (c.apply_variant == 2)
       k_apply_fused<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags,
                                                                c.d_cols + cr.offset, cr.count, c.nz, c.n_s,

@@ -205,20 +205,80 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_pq(const double *partial, i
 }
 
 // x += alpha p ; r -= alpha q ; partial sums (r.z, r.r) with z = dinv r.
-template <typename T, typename TX>
-__global__ __launch_bounds__(kVecThreads) void k_pcg_update(TX *x, T *r, const T *p, const T *q, const T *dinv,
-                                                            int64_t n_v, double *partial, const PcgScalars *sc) {
+// Vectorised over 16-byte chunks (VW elements); the tail is handled element-wise.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int W = 2;
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int W = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ void upd_one(T *x, T *r, const T *p, const T *q, const T *dinv, int64_t i, T a,
+                                        double (&v)[2]) {
+  x[i] = x[i] + a * p[i];
+  T ri = r[i] - a * q[i];
+  r[i] = ri;
+  T zi = dinv[i] * ri;
+  v[0] += (double)ri * (double)zi;
+  v[1] += (double)ri * (double)ri;
+}
+
+// element-wise fallback (operands not 16-byte aligned)
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_pcg_update_scalar(T *x, T *r, const T *p, const T *q, const T *dinv,
+                                                                   int64_t n_v, double *partial,
+                                                                   const PcgScalars *sc) {
   if (sc->done) return;
   const T a = (T)sc->alpha;
   double v[2] = {0.0, 0.0};
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_v; i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] = x[i] + (TX)(a * p[i]);
-    T ri = r[i] - a * q[i];
-    r[i] = ri;
-    T zi = dinv[i] * ri;
-    v[0] += (double)ri * (double)zi;
-    v[1] += (double)ri * (double)ri;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_v; i += (int64_t)gridDim.x * blockDim.x)
+    upd_one(x, r, p, q, dinv, i, a, v);
+  block_partials<2>(v, partial);
+}
+
+template <typename T, typename TX>
+__global__ __launch_bounds__(kVecThreads) void k_pcg_update(TX *x, T *r, const T *p, const T *q, const T *dinv,
+                                                            int64_t n_v, double *partial, const PcgScalars *sc) {
+  static_assert(sizeof(T) == sizeof(TX), "the solution and the residual share the precision");
+  if (sc->done) return;
+  const T a = (T)sc->alpha;
+  double v[2] = {0.0, 0.0};
+  using V = typename Vec16<T>::type;
+  constexpr int W = Vec16<T>::W;
+  const int64_t nvec = n_v / W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nvec; c += stride) {
+    V xv = reinterpret_cast<V *>(x)[c];
+    V rv = reinterpret_cast<V *>(r)[c];
+    const V pv = reinterpret_cast<const V *>(p)[c];
+    const V qv = reinterpret_cast<const V *>(q)[c];
+    const V dv = reinterpret_cast<const V *>(dinv)[c];
+    T *xs = reinterpret_cast<T *>(&xv);
+    T *rs = reinterpret_cast<T *>(&rv);
+    const T *ps = reinterpret_cast<const T *>(&pv);
+    const T *qs = reinterpret_cast<const T *>(&qv);
+    const T *ds = reinterpret_cast<const T *>(&dv);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      xs[w] = xs[w] + a * ps[w];
+      const T ri = rs[w] - a * qs[w];
+      rs[w] = ri;
+      const T zi = ds[w] * ri;
+      v[0] += (double)ri * (double)zi;
+      v[1] += (double)ri * (double)ri;
+    }
+    reinterpret_cast<V *>(x)[c] = xv;
+    reinterpret_cast<V *>(r)[c] = rv;
   }
+  if (blockIdx.x == 0)
+    for (int64_t i = nvec * W + threadIdx.x; i < n_v; i += blockDim.x) upd_one(x, r, p, q, dinv, i, a, v);
   block_partials<2>(v, partial);
 }
 
@@ -246,8 +306,23 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_dir(T *p, const T *r, const
                                                          const PcgScalars *sc) {
   if (sc->done) return;
   const T b = (T)sc->beta;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_v; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = dinv[i] * r[i] + b * p[i];
+  using V = typename Vec16<T>::type;
+  constexpr int W = Vec16<T>::W;
+  const int64_t nvec = n_v / W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nvec; c += stride) {
+    V pv = reinterpret_cast<V *>(p)[c];
+    const V rv = reinterpret_cast<const V *>(r)[c];
+    const V dv = reinterpret_cast<const V *>(dinv)[c];
+    T *ps = reinterpret_cast<T *>(&pv);
+    const T *rs = reinterpret_cast<const T *>(&rv);
+    const T *ds = reinterpret_cast<const T *>(&dv);
+#pragma unroll
+    for (int w = 0; w < W; ++w) ps[w] = ds[w] * rs[w] + b * ps[w];
+    reinterpret_cast<V *>(p)[c] = pv;
+  }
+  if (blockIdx.x == 0)
+    for (int64_t i = nvec * W + threadIdx.x; i < n_v; i += blockDim.x) p[i] = dinv[i] * r[i] + b * p[i];
 }
 
 __global__ void k_add_f32(double *x, const float *d, int64_t n) {
@@ -349,7 +424,12 @@ hipError_t launch_finalize_pq(const double *partial, int np, PcgScalars *sc, hip
 template <typename T, typename TX>
 hipError_t launch_pcg_update(TX *x, T *r, const T *p, const T *q, const T *dinv, int64_t n_v, double *partial,
                              PcgScalars *sc, hipStream_t s) {
-  k_pcg_update<T, TX><<<kVecBlocks, kVecThreads, 0, s>>>(x, r, p, q, dinv, n_v, partial, sc);
+  // every vector here is a device allocation (256-byte aligned) except x, which may be a caller
+  // tensor: the vectorised kernel requires 16-byte alignment of all operands
+  if ((reinterpret_cast<uintptr_t>(x) & 15) != 0)
+    k_pcg_update_scalar<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, r, p, q, dinv, n_v, partial, sc);
+  else
+    k_pcg_update<T, TX><<<kVecBlocks, kVecThreads, 0, s>>>(x, r, p, q, dinv, n_v, partial, sc);
   k_fin_rz<<<1, kVecThreads, 0, s>>>(partial, kVecBlocks, sc);
   return hipGetLastError();
 }

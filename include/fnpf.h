@@ -174,7 +174,10 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy);
  *     LDS accesses; kept for comparison);
  *   3, 4, 5 fused geometry with alternative schedules for p = 6 in 3D (3 one
  *     column per workgroup, 4 without the next-layer prefetch, 5 zeta loops
- *     unrolled by two; other degrees use the default schedule).
+ *     unrolled by two; other degrees use the default schedule);
+ *   6 fused geometry, line schedule (3D): in the horizontal contraction
+ *     phases each thread owns one xi-line and one eta-line of the element,
+ *     so derivative coefficients are uniform scalars (2D: same as 0).
  * Switching to 1 invalidates the current geometry (call fnpf_geom again). */
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant);
 

@@ -489,8 +489,9 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy) {
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
-  if (variant < 0 || variant > 5) return fail(&c, FNPF_ERR_ARG, "apply variant must be in 0..5");
-  c.apply_tune = variant >= 3 ? variant - 2 : 0;
+  if (variant < 0 || variant > 6) return fail(&c, FNPF_ERR_ARG, "apply variant must be in 0..6");
+  c.apply_tune = (variant >= 3 && variant <= 5) ? variant - 2 : 0;
+  c.apply_lines = variant == 6;
   if (variant >= 3) variant = 0;
   if (variant == c.apply_variant) return FNPF_OK;
   c.apply_variant = variant;

@@ -145,6 +145,7 @@ struct Ctx {
   // apply variant: 0 fused geometry (factors recomputed in registers), 1 stored factors
   int apply_variant = 0;
   int apply_tune = 0;                     // schedule option of the fused apply (p = 6, 3D)
+  bool apply_lines = false;               // 3D fused apply with the xi/eta line schedule
   double *d_cg64 = nullptr;               // [5|3][n_eh*nh] H, H_xi, h_xi, (H_eta, h_eta) per column node
   float *d_cg32 = nullptr;
   float *d_hm32 = nullptr;                // FP32 copy of d_hm

@@ -29,10 +29,23 @@ __constant__ double c_D64[kMaxN1 * kDStride];
 __constant__ float c_D32[kMaxN1 * kDStride];
 __constant__ double c_W[kMaxN1 * kMaxN1];
 
+// Even-odd coefficient tables of the line contractions with D (tr = 0) and D^T (tr = 1), per
+// degree p, with H = (p+1)/2 pairs (r, p-r) and, for even p, the middle index c = p/2.  Both
+// matrices are centro-antisymmetric, M[p-r][p-m] = -M[r][m]; the table stores
+//   A[r][m] = (M[r][m] - M[r][p-m]) / 2,  B[r][m] = (M[r][m] + M[r][p-m]) / 2   (r, m < H),
+//   Bc[r] = M[r][c],  Cc[m] = M[c][m]                                            (even p),
+// taken from the antisymmetrised M~[r][m] = (M[r][m] - M[p-r][p-m]) / 2.
+constexpr int kMaxH = kMaxN1 / 2;
+constexpr int kEOStride = 2 * kMaxH * kMaxH + 2 * kMaxH;
+__constant__ double c_EO64[(kMaxP + 1) * 2 * kEOStride];
+__constant__ float c_EO32[(kMaxP + 1) * 2 * kEOStride];
+
 hipError_t upload_constants(int /*device*/) {
   static double D64[kMaxN1 * kDStride];
   static float D32[kMaxN1 * kDStride];
   static double W[kMaxN1 * kMaxN1];
+  static double EO64[(kMaxP + 1) * 2 * kEOStride];
+  static float EO32[(kMaxP + 1) * 2 * kEOStride];
   for (int p = 1; p <= kMaxP; ++p) {
     double x[kMaxN1], w[kMaxN1], D[kMaxN1 * kMaxN1];
     gll_host(p, x, w, D);
@@ -42,10 +55,34 @@ hipError_t upload_constants(int /*device*/) {
       D32[p * kDStride + i] = (float)D[i];
     }
     for (int i = 0; i < n1; ++i) W[p * kMaxN1 + i] = w[i];
+    const int H = n1 / 2, c = p / 2;
+    for (int tr = 0; tr < 2; ++tr) {
+      auto M = [&](int r, int m) {
+        const double a = tr ? D[m * n1 + r] : D[r * n1 + m];
+        const double b = tr ? D[(p - m) * n1 + (p - r)] : D[(p - r) * n1 + (p - m)];
+        return 0.5 * (a - b);
+      };
+      double *E = EO64 + (p * 2 + tr) * kEOStride;
+      for (int r = 0; r < H; ++r)
+        for (int m = 0; m < H; ++m) {
+          E[r * H + m] = 0.5 * (M(r, m) - M(r, p - m));
+          E[H * H + r * H + m] = 0.5 * (M(r, m) + M(r, p - m));
+        }
+      if (n1 & 1)
+        for (int r = 0; r < H; ++r) {
+          E[2 * H * H + r] = M(r, c);
+          E[2 * H * H + H + r] = M(c, r);
+        }
+      for (int k = 0; k < kEOStride; ++k) EO32[(p * 2 + tr) * kEOStride + k] = (float)E[k];
+    }
   }
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_D64), D64, sizeof(D64));
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_D32), D32, sizeof(D32));
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_EO64), EO64, sizeof(EO64));
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_EO32), EO32, sizeof(EO32));
   if (e != hipSuccess) return e;
   return hipMemcpyToSymbol(HIP_SYMBOL(c_W), W, sizeof(W));
 }
@@ -71,6 +108,77 @@ __device__ __forceinline__ float dmat<float>(int P, int r, int c) {
   return c_D32[P * kDStride + r * (P + 1) + c];
 }
 __device__ __forceinline__ double wgt(int P, int i) { return c_W[P * kMaxN1 + i]; }
+
+// Raw buffer access: a per-thread 32-bit byte offset plus a wave-uniform row offset, so the
+// vertical walk needs one address register per thread.  The descriptor's record count is the
+// vector's size: accesses beyond it read 0 and drop writes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  using V1 = unsigned long long __attribute__((ext_vector_type(1)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V1, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ const T *eo_table();
+template <>
+__device__ __forceinline__ const double *eo_table<double>() { return c_EO64; }
+template <>
+__device__ __forceinline__ const float *eo_table<float>() { return c_EO32; }
+
+// out = M in along one line of N1 = P+1 nodes, M = D (TR = 0) or D^T (TR = 1), in even-odd
+// form: e_m = in_m + in_{P-m}, o_m = in_m - in_{P-m} for m < H, then
+//   out_r = sum_m A_rm o_m + S_r,  out_{P-r} = sum_m A_rm o_m - S_r,
+//   S_r = sum_m B_rm e_m (+ Bc_r in_c for even P),  out_c = sum_m Cc_m o_m,
+// about half the multiply-adds of the dense product.  The coefficients are read through the
+// scalar cache at every call (the zero offset is opaque to the compiler), so they occupy
+// scalar registers only while the line is computed.
+template <int P, typename T, int TR>
+__device__ __forceinline__ void line_eo(const T (&in)[P + 1], T (&out)[P + 1]) {
+  constexpr int N1 = P + 1, H = N1 / 2, C = P / 2;
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  const T *E = eo_table<T>() + (P * 2 + TR) * kEOStride + z;
+  T e[H], o[H];
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    e[m] = in[m] + in[P - m];
+    o[m] = in[m] - in[P - m];
+  }
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    T so = E[r * H] * o[0];
+    T se = E[H * H + r * H] * e[0];
+#pragma unroll
+    for (int m = 1; m < H; ++m) {
+      so += E[r * H + m] * o[m];
+      se += E[H * H + r * H + m] * e[m];
+    }
+    if constexpr ((N1 & 1) != 0) se += E[2 * H * H + r] * in[C];
+    out[r] = so + se;
+    out[P - r] = so - se;
+  }
+  if constexpr ((N1 & 1) != 0) {
+    T sc = E[2 * H * H + H] * o[0];
+#pragma unroll
+    for (int m = 1; m < H; ++m) sc += E[2 * H * H + H + m] * o[m];
+    out[C] = sc;
+  }
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -590,6 +698,188 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
       }
     }
     carry = u_c[P * NH + t];
+    ucol[0] = ucol[P];
+  }
+  if constexpr (DOT) {
+    double s = block_sum<CPB * NH>(dot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// Same operator (3D), line schedule.  Between barriers a thread owns either its vertical line
+// (i, j) or, in the two horizontal phases, the xi-line (j = a, k = b) and the eta-line
+// (i = a, k = b) with t = b N1 + a.  Every contraction then runs over compile-time indices, so
+// its D entries are wave-uniform scalar operands, and each LDS word read feeds N1 FMAs.
+// Phases per layer element (4 barriers):
+//   0  line (i,j): store u to LDS; u_zeta in registers
+//   1  xi/eta lines: u_xi -> sA, u_eta -> sB
+//   2  line (i,j): per point g = J^-T grad u, v = w detJ J^-1 g; v_xi, v_eta back into sA, sB
+//      in place; zeta part of the transposed contraction into registers
+//   3  xi/eta lines: transposed contractions in place in sA, sB
+//   4  line (i,j): y = sA + sB + zeta part, assembled into global y under the colour schedule
+template <int P, typename T, bool MASK, bool DOT>
+__global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T *__restrict__ y,
+                                                     const T *__restrict__ cg, const T *__restrict__ hmT,
+                                                     int64_t hstride, const T *__restrict__ sig,
+                                                     const T *__restrict__ half_ds,
+                                                     const int32_t *__restrict__ eh_nodes,
+                                                     const uint8_t *__restrict__ flags,
+                                                     const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
+                                                     double *__restrict__ partial, const int32_t *__restrict__ skip) {
+  using S = Sh<P, 3>;
+  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
+  __shared__ T sU[CPB * NP];
+  __shared__ T sA[CPB * NP];
+  __shared__ T sB[CPB * NP];
+  if (skip != nullptr && *skip) return;
+
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? cols[ci] : 0;
+  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
+  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
+  const int64_t ho = (int64_t)col * NH + t;
+
+  T H = T(1), Hx = T(0), hx = T(0), Hy = T(0), hy = T(0);
+  T A00 = T(1), A01 = T(0), A10 = T(0), A11 = T(1), dJ = T(1);
+  if (active) {
+    H = cg[0 * hstride + ho];
+    Hx = cg[1 * hstride + ho];
+    hx = cg[2 * hstride + ho];
+    Hy = cg[3 * hstride + ho];
+    hy = cg[4 * hstride + ho];
+    A00 = hmT[0 * hstride + ho];
+    A01 = hmT[1 * hstride + ho];
+    A10 = hmT[2 * hstride + ho];
+    A11 = hmT[3 * hstride + ho];
+    dJ = hmT[4 * hstride + ho];
+  }
+  const T wdJ = (T)(wgt(P, i) * wgt(P, j)) * dJ;
+
+  T *U = sU + lc * NP;
+  T *Ab = sA + lc * NP;
+  T *Bb = sB + lc * NP;
+  // the thread's lines in the horizontal phases: xi-line (j = a, k = b), eta-line (i = a, k = b)
+  const int xi_base = t * N1;                       // b NH + a N1
+  const int eta_base = (t / N1) * NH + (t % N1);    // b NH + a, stride N1
+  // node (v, hn) at byte offset v n_s sizeof(T) (uniform) + hn sizeof(T) (per thread); the
+  // launcher guarantees that n_v sizeof(T) fits in 32 bits
+  const uint32_t nbytes = (uint32_t)((int64_t)(P * nz + 1) * n_s * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t rx = vec_rsrc(x, nbytes), ry = vec_rsrc(y, nbytes);
+  const uint32_t hb = (uint32_t)hn * (uint32_t)sizeof(T);
+  const uint32_t rowb = (uint32_t)n_s * (uint32_t)sizeof(T);
+
+  T ucol[N1];
+  T carry = T(0);
+  double dot = 0.0;
+  ucol[0] = active ? buf_ld<T>(rx, hb, 0) : T(0);
+  const int vtop = P * nz;
+  T nxt[N1];
+#pragma unroll
+  for (int k = 1; k < N1; ++k) nxt[k] = active ? buf_ld<T>(rx, hb, (uint32_t)k * rowb) : T(0);
+
+  for (int l = 0; l < nz; ++l) {
+    // phase 0
+#pragma unroll
+    for (int k = 1; k < N1; ++k) ucol[k] = nxt[k];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) U[k * NH + t] = ucol[k];
+    T uz[N1];
+    line_eo<P, T, 0>(ucol, uz);
+    __syncthreads();
+    // next layer's x loads complete behind this layer's arithmetic
+    if (l + 1 < nz) {
+#pragma unroll
+      for (int k = 1; k < N1; ++k) nxt[k] = active ? buf_ld<T>(rx, hb, (uint32_t)((l + 1) * P + k) * rowb) : T(0);
+    }
+
+    // phase 1
+    {
+      T in[N1], out[N1];
+#pragma unroll
+      for (int m = 0; m < N1; ++m) in[m] = U[xi_base + m];
+      line_eo<P, T, 0>(in, out);
+#pragma unroll
+      for (int r = 0; r < N1; ++r) Ab[xi_base + r] = out[r];
+#pragma unroll
+      for (int m = 0; m < N1; ++m) in[m] = U[eta_base + m * N1];
+      line_eo<P, T, 0>(in, out);
+#pragma unroll
+      for (int r = 0; r < N1; ++r) Bb[eta_base + r * N1] = out[r];
+    }
+    __syncthreads();
+
+    // phase 2
+    const T zz = half_ds[l] * H;
+    const T izz = T(1) / zz;
+    const T fl0 = wdJ * zz;
+    T vz[N1], yz[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const int q = k * NH + t;
+      const T ux = Ab[q], uy = Bb[q];
+      const T sg = sig[l * P + k];
+      const T f = (T)wgt(P, k) * fl0;
+      const T zx = sg * Hx - hx;
+      const T zy = sg * Hy - hy;
+      const T b2x = -(zx * A00 + zy * A10) * izz;
+      const T b2y = -(zx * A01 + zy * A11) * izz;
+      const T gx = A00 * ux + A10 * uy + b2x * uz[k];
+      const T gy = A01 * ux + A11 * uy + b2y * uz[k];
+      const T gz = izz * uz[k];
+      Ab[q] = f * (A00 * gx + A01 * gy);
+      Bb[q] = f * (A10 * gx + A11 * gy);
+      vz[k] = f * (b2x * gx + b2y * gy + izz * gz);
+    }
+    line_eo<P, T, 1>(vz, yz);
+    __syncthreads();
+
+    // phase 3 (in place: only this thread touches these lines now)
+    {
+      T in[N1], out[N1];
+#pragma unroll
+      for (int m = 0; m < N1; ++m) in[m] = Ab[xi_base + m];
+      line_eo<P, T, 1>(in, out);
+#pragma unroll
+      for (int r = 0; r < N1; ++r) Ab[xi_base + r] = out[r];
+#pragma unroll
+      for (int m = 0; m < N1; ++m) in[m] = Bb[eta_base + m * N1];
+      line_eo<P, T, 1>(in, out);
+#pragma unroll
+      for (int r = 0; r < N1; ++r) Bb[eta_base + r * N1] = out[r];
+    }
+    // read-add-write loads of the colour schedule, in flight across the barrier
+    const int kend = (l == nz - 1) ? N1 : P;
+    T old[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) old[k] = T(0);
+    if (active && !(fl & kFirst)) {
+#pragma unroll
+      for (int k = 0; k < N1; ++k)
+        if (k < kend) old[k] = buf_ld<T>(ry, hb, (uint32_t)(l * P + k) * rowb);
+    }
+    __syncthreads();
+
+    // phase 4
+    T yv[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) yv[k] = yz[k] + (Ab[k * NH + t] + Bb[k * NH + t]);
+    yv[0] += carry;
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        if (k < kend) {
+          const int v = l * P + k;
+          const T val = (MASK && v == vtop) ? T(0) : yv[k] + old[k];
+          buf_st(val, ry, hb, (uint32_t)v * rowb);
+          if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
+        }
+      }
+    }
+    carry = yv[P];
     ucol[0] = ucol[P];
   }
   if constexpr (DOT) {
@@ -1131,6 +1421,15 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
         }
       }
       if (done) continue;
+      if constexpr (DIM == 3) {
+        if (c.apply_lines && (int64_t)c.n_v * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+          k_apply_lines<P, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags,
+                                                               c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
+                                                               DOT ? partial + off : nullptr, skip);
+          off += nb;
+          continue;
+        }
+      }
       k_apply_fused2<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags,
                                                                 c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
                                                                 DOT ? partial + off : nullptr, skip);

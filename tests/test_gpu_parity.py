@@ -108,9 +108,10 @@ def test_geometry_parity(name, variant):
     assert np.abs(host(diag) - dref).max() < 1e-13 * np.abs(dref).max()
 
 
+@pytest.mark.parametrize("variant", [0, 6])
 @pytest.mark.parametrize("name", ["slice_periodic", "box_periodic", "cylinder"])
-def test_apply_equals_dense_matrix(name):
-    pr = Pair(_case(name))
+def test_apply_equals_dense_matrix(name, variant):
+    pr = Pair(_case(name), variant=variant)
     pr.ctx.geom(pr.d_eta, pr.d_h)
     Go, _, _ = pr.oracle_factors()
     A = op.assemble_dense(pr.m, Go)
@@ -122,7 +123,7 @@ def test_apply_equals_dense_matrix(name):
     assert np.abs(Ag @ np.ones(n)).max() <= 1e-12 * np.abs(A).max()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 6])
 @pytest.mark.parametrize("name", CASES)
 def test_apply_random_fp64_fp32(name, variant):
     pr = Pair(_case(name), fp32=True, variant=variant)
@@ -154,9 +155,10 @@ def test_neumann_load_parity(name):
     assert np.abs(f - fo).max() < 1e-13 * np.abs(fo).max()
 
 
+@pytest.mark.parametrize("variant", [0, 6])
 @pytest.mark.parametrize("name", CASES)
-def test_solve_w_rhs_parity(name):
-    pr = Pair(_case(name), fp32=True)
+def test_solve_w_rhs_parity(name, variant):
+    pr = Pair(_case(name), fp32=True, variant=variant)
     pr.ctx.geom(pr.d_eta, pr.d_h)
     Go, _, _ = pr.oracle_factors()
     A = op.assemble_dense(pr.m, Go)
@@ -242,10 +244,12 @@ def test_c2_full_size_apply_and_solve():
     yo = op.apply(pr.m, Go, xv)
     assert rel(host(pr.ctx.laplace_apply(dev(xv))), yo) < 1e-13
     assert rel(host(pr.ctx.laplace_apply(dev(xv).float())), yo) < 2e-6
-    stored = Pair(wl, fp32=True, variant=1)
-    stored.ctx.geom(stored.d_eta, stored.d_h)
-    assert rel(host(stored.ctx.laplace_apply(dev(xv))), yo) < 1e-13
-    del stored
+    for v in (1, 6):
+        other = Pair(wl, fp32=True, variant=v)
+        other.ctx.geom(other.d_eta, other.d_h)
+        assert rel(host(other.ctx.laplace_apply(dev(xv))), yo) < 1e-13
+        assert rel(host(other.ctx.laplace_apply(dev(xv).float())), yo) < 2e-6
+        del other
     for precision, rtol in ((0, 1e-10), (1, 1e-10)):
         phi, info = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precision=precision, rtol=rtol))
         assert info["status"] == "OK"
@@ -261,11 +265,13 @@ def test_c2_full_size_apply_and_solve():
         assert rel(host(pr.ctx.w_surface(phi)), wo) < 1e-12
 
 
-def test_c5_sampled_apply():
+@pytest.mark.parametrize("variant", [0, 6])
+def test_c5_sampled_apply(variant):
     """C5 (43,675,392 DoF): apply parity at the nodes of sampled columns (oracle on their neighbourhood)."""
     wl = configs.c5()
     m = wl.mesh
     ctx = fnpf.Context(m, g=wl.g)
+    ctx.set_apply_variant(variant)
     x, y = ctx.node_xy()
     h = np.asarray(wl.depth(x, y))
     eta = np.asarray(wl.eta0(x, y))

@@ -7,11 +7,13 @@ w recovery, free-surface RHS + stage update], relaxation) on the synthetic C5 wo
 bathymetry and a JONSWAP irregular sea.  Inputs are resident in HBM before timing.
 
 Printed JSON line:
-  value            GDOF/s of the FP64 matrix-free Laplace apply (n_v / mean apply time,
-                   HIP events around a loop of applies on the launch stream)
+  value            GDOF/s of the FP64 matrix-free Laplace apply: n_v / median apply time
+                   (HIP events around each of >= 100 applies on the launch stream)
   ms_per_step      mean wall time of one mixed-precision ERK4 step at rtol 1e-8
   s_per_rk4_step   FP64 and mixed step times at rtol 1e-8
-  roofline         the FP64 apply against the 8 TB/s HBM peak (algorithmic bytes)
+  roofline         the FP64 apply (both launches of the owner-computes schedule) against the
+                   8 TB/s HBM peak with its algorithmic bytes; roofline_alu: the same apply's
+                   executed flops against the FP64 vector peak
   cpu_baseline     the oracle's apply on a bounded sample of the same mesh, host cores
 """
 
@@ -28,28 +30,70 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFS = 78.6
 METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/forward ratio"
 
+# HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by the
+# plain-copy calibration), valid only for the kernel source they were taken from.
+MEASURED_TRAFFIC = {
+    "kernel_source_sha256": "f80db3d9be88f697861f96e51cd05896e3f62947c76772095f63560ca64dbe96",
+    "fetch_bytes_per_apply": 1151667132,
+    "write_bytes_per_apply": 615177572,
+}
 
-def apply_bytes(n_v, n_q, word):
-    """Algorithmic bytes of one apply: x read once, y written once, 6 factors per point read once."""
+
+def apply_bytes_stored(n_v, n_q, word):
+    """Algorithmic bytes of a stored-factor apply: x read once, y written once, 6 factors per point."""
     return word * (2 * n_v + 6 * n_q)
 
 
+def apply_bytes_fused(n_v, n_eh, nh, word, dim=3):
+    """Algorithmic bytes of the fused-geometry apply: x read once, y written once, and per column
+    node the five column numbers and five horizontal metric entries (3D) read once."""
+    per_node = 10 if dim == 3 else 5
+    return word * (2 * n_v + per_node * n_eh * nh)
+
+
+def line_flops(n1):
+    """Flops of one even-odd line contraction over n1 nodes (as executed)."""
+    h, odd = n1 // 2, n1 % 2
+    return 2 * h + h * (4 * h + 2 * odd) + odd * (2 * h - 1)
+
+
+def apply_flops(n_q, p):
+    """Executed flops of the 3D fused-geometry apply: six line contractions per point plus 38
+    flops of per-point geometry and factor multiply and 2 of the final sum."""
+    n1 = p + 1
+    return n_q * (6 * line_flops(n1) / n1 + 40)
+
+
+def kernel_source_sha256():
+    """sha256 of the apply-kernel region of kernels_column.hip (buffer helpers to the last apply kernel)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2506_09435_amd", "csrc", "kernels_column.hip")
+    with open(src, encoding="utf-8") as f:
+        text = f.read()
+    i0 = text.index("// Raw buffer access")
+    i1 = text.index("bool owner_apply_active(const Ctx &c) {")
+    return hashlib.sha256(text[i0:i1].encode()).hexdigest()
+
+
 def time_applies(ctx, x, reps, warm=3):
+    """Median and mean seconds of one apply, HIP events around each apply on the launch stream."""
     import torch
     y = torch.empty_like(x)
     for _ in range(warm):
         ctx.laplace_apply(x, y)
     s = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(s)
+    for k in range(reps):
         ctx.laplace_apply(x, y)
-    e1.record(s)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / reps
+        ev[k + 1].record(s)
+    ev[-1].synchronize()
+    t = sorted(ev[k].elapsed_time(ev[k + 1]) / 1e3 for k in range(reps))
+    mean = ev[0].elapsed_time(ev[-1]) / 1e3 / reps
+    return t[reps // 2], mean
 
 
 def run_steps(s, wl, opts, nsteps, t0=0.0, eta=None, phi=None):
@@ -210,14 +254,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C5")
-    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--apply-reps", type=int, default=100)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-steps", action="store_true")
     ap.add_argument("--apply-only", action="store_true",
                     help="only the apply loops (FP64, FP32) and a calibration copy of n_v doubles (for counters)")
-    ap.add_argument("--variant", type=int, default=0, help="apply variant: 0 fused geometry, 1 stored factors")
-    ap.add_argument("--adjoint-steps", type=int, default=40, help="C4 steps of the adjoint leg (0: skip)")
+    ap.add_argument("--variant", type=int, default=0, help="apply variant (fnpf_set_apply_variant)")
+    ap.add_argument("--adjoint-steps", type=int, default=200, help="C4 steps of the adjoint leg (0: skip)")
     ap.add_argument("--adjoint-fd", type=int, default=0, help="finite-difference directions checked in the adjoint leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -245,8 +289,8 @@ def main():
     torch.cuda.synchronize()
     g = torch.Generator(device="cuda").manual_seed(0)
     x64 = torch.randn(m.n_v, dtype=torch.float64, device="cuda", generator=g)
-    t64 = time_applies(ctx, x64, args.apply_reps)
-    t32 = time_applies(ctx, x64.float(), args.apply_reps)
+    t64, t64_mean = time_applies(ctx, x64, args.apply_reps)
+    t32, t32_mean = time_applies(ctx, x64.float(), args.apply_reps)
     n_q = m.n_e * (m.p + 1) ** m.dim
     print(f"[bench] apply f64 {t64 * 1e3:.3f} ms ({m.n_v / t64 / 1e9:.1f} GDOF/s), "
           f"f32 {t32 * 1e3:.3f} ms ({m.n_v / t32 / 1e9:.1f} GDOF/s)", file=sys.stderr, flush=True)
@@ -258,8 +302,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(mode="apply-only", workload=wl.name, variant=args.variant, apply_ms_f64=t64 * 1e3,
                               apply_ms_f32=t32 * 1e3, copy_bytes_each_way=8 * m.n_v,
-                              algorithmic_bytes_f64=apply_bytes(m.n_v, n_q, 8) if args.variant == 1 else
-                              16 * m.n_v)), flush=True)
+                              algorithmic_bytes_f64=apply_bytes_stored(m.n_v, n_q, 8) if args.variant == 1 else
+                              apply_bytes_fused(m.n_v, m.n_eh, m.nh, 8, m.dim),
+                              source_sha256=kernel_source_sha256())), flush=True)
         return
 
     # -- ERK4 steps --------------------------------------------------------------------
@@ -295,8 +340,12 @@ def main():
         cpu = cpu_baseline(wl)
         print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
 
-    bytes64 = apply_bytes(m.n_v, n_q, 8)
+    bytes64 = apply_bytes_fused(m.n_v, m.n_eh, m.nh, 8, m.dim)
     achieved = bytes64 / t64 / 1e9
+    flops64 = apply_flops(n_q, m.p)
+    traffic = None
+    if MEASURED_TRAFFIC["kernel_source_sha256"] == kernel_source_sha256() and args.variant == 0:
+        traffic = MEASURED_TRAFFIC["fetch_bytes_per_apply"] + MEASURED_TRAFFIC["write_bytes_per_apply"]
     out = dict(
         metric=METRIC, value=m.n_v / t64 / 1e9, unit="GDOF/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=t_mixed * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
@@ -305,14 +354,18 @@ def main():
                              f"JONSWAP sea (128 components)", n_v=m.n_v, n_e=m.n_e, p=m.p, rtol=args.rtol,
                     parallelism="single GPU"),
         apply_gdofs=dict(f64=m.n_v / t64 / 1e9, f32=m.n_v / t32 / 1e9),
-        apply_ms=dict(f64=t64 * 1e3, f32=t32 * 1e3),
+        apply_ms=dict(f64=t64 * 1e3, f32=t32 * 1e3, f64_mean=t64_mean * 1e3, f32_mean=t32_mean * 1e3),
         s_per_rk4_step=dict(f64=t_f64, mixed=t_mixed),
         pcg_iters_per_stage=dict(f64=it_f64, mixed=it_mixed),
         adjoint_forward_ratio=None if adj is None else adj["ratio"],
         adjoint=adj,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                      traffic=None, kernel="k_apply<6,3,double> (4 colour launches = one apply)",
-                      algorithmic_bytes_per_apply=bytes64),
+                      traffic=traffic,
+                      kernel="FP64 apply: k_apply_lines<6,double,owner> (all columns) + k_apply_faces<double> "
+                             "(shared-node sums), one launch each per apply",
+                      algorithmic_bytes_per_apply=bytes64, traffic_unit="bytes per apply"),
+        roofline_alu=dict(bound="alu", achieved=flops64 / t64 / 1e12, peak=FP64_VALU_PEAK_TFS, unit="TFLOP/s",
+                          frac=flops64 / t64 / 1e12 / FP64_VALU_PEAK_TFS, flops_per_apply=flops64),
         cpu_baseline=cpu,
     )
     print(json.dumps(out), flush=True)

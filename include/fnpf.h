@@ -163,21 +163,31 @@ fnpf_status fnpf_gll(int32_t p, double *nodes, double *weights, double *D);
  * xy[n_s][dim-1] (periodic nodes: the first element's image). */
 fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy);
 
-/* Stiffness-apply variant (both compute the same operator):
+/* Stiffness-apply variant (all compute the same operator, paper Eq. 4):
  *   0 (default) fused geometry: the per-point factors are re-evaluated in
  *     registers from five numbers per column node (eta+h, h and their
  *     horizontal derivatives) and the static horizontal metrics, so an apply
- *     reads x and writes y only;
+ *     reads x and writes y only.  3D: line schedule (below) with
+ *     owner-computes assembly -- one launch over all columns stores each
+ *     column's values at the horizontal nodes it owns (each node belongs to
+ *     the lowest-numbered column that has it) and its other values into face
+ *     slots, and a second launch adds the slots to the owners.  It is fastest
+ *     when each column's own nodes are numbered consecutively (shared ones
+ *     first); any consistent numbering gives the same result.  2D: colour
+ *     schedule with read-add-write of shared nodes;
  *   1 stored factors: fnpf_geom stores G (6 or 3 per point, FP64 and FP32)
  *     and the apply streams it from HBM;
  *   2 fused geometry with a fully unrolled schedule (more registers, fewer
  *     LDS accesses; kept for comparison);
- *   3, 4, 5 fused geometry with alternative schedules for p = 6 in 3D (3 one
- *     column per workgroup, 4 without the next-layer prefetch, 5 zeta loops
- *     unrolled by two; other degrees use the default schedule);
- *   6 fused geometry, line schedule (3D): in the horizontal contraction
- *     phases each thread owns one xi-line and one eta-line of the element,
- *     so derivative coefficients are uniform scalars (2D: same as 0).
+ *   3, 4, 5 fused geometry, colour schedule, alternative schedules for p = 6
+ *     in 3D (3 one column per workgroup, 4 without the next-layer prefetch,
+ *     5 zeta loops unrolled by two; other degrees use the schedule of 7);
+ *   6 fused geometry, line schedule with colour assembly (3D): in the
+ *     horizontal contraction phases each thread owns one xi-line and one
+ *     eta-line of the element, so derivative coefficients are uniform
+ *     scalars (2D: same as 7);
+ *   7 fused geometry, colour schedule (one thread per vertical node line,
+ *     derivatives through LDS reads).
  * Switching to 1 invalidates the current geometry (call fnpf_geom again). */
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant);
 

@@ -57,6 +57,12 @@ void dfree(T *&p) {
 void free_all(Ctx &c) {
   dfree(c.d_eh_nodes);
   dfree(c.d_cols);
+  dfree(c.d_slot);
+  dfree(c.d_ps_node);
+  dfree(c.d_ps_ptr);
+  dfree(c.d_ps_slot);
+  dfree(c.d_F64);
+  dfree(c.d_F32);
   dfree(c.d_flags);
   dfree(c.d_face_tag);
   dfree(c.d_hm);
@@ -151,6 +157,7 @@ fnpf_status ensure32(Ctx &c) {
   HIPCHK(dalloc(&c.d_p32, c.n_v));
   HIPCHK(dalloc(&c.d_q32, c.n_v));
   HIPCHK(dalloc(&c.d_d32, c.n_v));
+  if (c.dim == 3) HIPCHK(dalloc(&c.d_F32, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(c.n_slots, 1)));
   c.want32 = true;
   c.have_geom32 = false;
   return FNPF_OK;
@@ -189,6 +196,7 @@ fnpf_status check_err_flag(Ctx &c, hipStream_t s) {
 int apply_blocks(const Ctx &c) {
   // the one-column-per-workgroup schedules (p = 6, 3D) launch one block per column
   if (c.apply_variant == 0 && c.apply_tune == 1 && c.p == 6 && c.dim == 3) return c.n_eh;
+  if (owner_apply_active(c)) return owner_apply_blocks(c);
   return c.max_colour_blocks;
 }
 
@@ -380,6 +388,7 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   }
   c.h_hm = hm;
   c.ncg = c.dim == 3 ? 5 : 3;
+  c.apply_lines = c.apply_owner = c.dim == 3;   // default schedule of the 3D apply
   c.h_half_ds.resize(c.nz);
   for (int l = 0; l < c.nz; ++l) c.h_half_ds[l] = 0.5 * (c.h_layer_s[l + 1] - c.h_layer_s[l]);
   // total apply blocks over colours (partials of the fused dot product)
@@ -419,6 +428,13 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   } while (0)
   UP(c.d_eh_nodes, c.h_eh_nodes.data(), c.h_eh_nodes.size());
   UP(c.d_cols, cols.data(), cols.size());
+  if (c.dim == 3) {
+    UP(c.d_slot, c.h_slot.data(), c.h_slot.size());
+    UP(c.d_ps_node, c.h_ps_node.data(), std::max<size_t>(c.h_ps_node.size(), 1));
+    UP(c.d_ps_ptr, c.h_ps_ptr.data(), c.h_ps_ptr.size());
+    UP(c.d_ps_slot, c.h_ps_slot.data(), std::max<size_t>(c.h_ps_slot.size(), 1));
+    AL(c.d_F64, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(c.n_slots, 1));
+  }
   UP(c.d_flags, flags.data(), flags.size());
   UP(c.d_face_tag, tags.data(), tags.size());
   UP(c.d_hm, hm.data(), hm.size());
@@ -448,6 +464,7 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   AL(c.d_nk, c.n_s);
   AL(c.d_nd, c.n_s);
   c.n_partial = std::max(std::max(3 * kVecBlocks, c.max_colour_blocks), c.n_eh) + 16;
+  c.n_partial = std::max(c.n_partial, owner_apply_blocks(c) + 16);
   AL(c.d_partial, c.n_partial);
   AL(c.d_sc, 2);
 #undef UP
@@ -489,9 +506,10 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy) {
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
-  if (variant < 0 || variant > 6) return fail(&c, FNPF_ERR_ARG, "apply variant must be in 0..6");
+  if (variant < 0 || variant > 7) return fail(&c, FNPF_ERR_ARG, "apply variant must be in 0..7");
   c.apply_tune = (variant >= 3 && variant <= 5) ? variant - 2 : 0;
-  c.apply_lines = variant == 6;
+  c.apply_lines = c.dim == 3 && (variant == 0 || variant == 6);
+  c.apply_owner = c.dim == 3 && variant == 0;
   if (variant >= 3) variant = 0;
   if (variant == c.apply_variant) return FNPF_OK;
   c.apply_variant = variant;

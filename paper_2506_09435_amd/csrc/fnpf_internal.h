@@ -16,6 +16,8 @@ constexpr int kMaxN1 = kMaxP + 1;
 constexpr int kDStride = kMaxN1 * kMaxN1;  // per-degree stride of the D tables
 constexpr uint8_t kFirst = 1;              // column is the first writer of this horizontal node
 constexpr uint8_t kLast = 2;               // column is the last writer (sees the final sum)
+constexpr uint8_t kOwned = 4;              // column owns this horizontal node (owner-computes apply)
+constexpr uint8_t kShared = 8;             // the node belongs to more than one column
 
 // Horizontal metric components stored per (column, local horizontal node).
 // 3D: A = J_h^{-1} (A00, A01, A10, A11), det J_h, J_h (x_xi, x_eta, y_xi, y_eta).
@@ -142,10 +144,21 @@ struct Ctx {
   double *d_layer_s = nullptr;            // [nz + 1]
   double *d_mlump_w = nullptr;            // [n_s] sum_e w_i w_j w_p det J_h (w recovery denominator)
   double *d_mlump_s = nullptr;            // [n_s] sum_e w_i w_j det J_h (surface mass)
-  // apply variant: 0 fused geometry (factors recomputed in registers), 1 stored factors
+  // apply variant: 0 fused geometry (factors recomputed in registers), 1 stored factors,
+  // 2 fused geometry, unrolled schedule; the schedule of 0 is refined by the fields below
   int apply_variant = 0;
   int apply_tune = 0;                     // schedule option of the fused apply (p = 6, 3D)
   bool apply_lines = false;               // 3D fused apply with the xi/eta line schedule
+  bool apply_owner = false;               // 3D line schedule with owner-computes assembly (two passes)
+  // owner-computes assembly: contributions of a column at nodes it does not own go to face
+  // slots (column-major numbering); the second pass adds them at the owner
+  std::vector<int32_t> h_slot;            // [n_eh][nh] slot id, -1 where owned
+  std::vector<int32_t> h_ps_node, h_ps_ptr, h_ps_slot;  // shared nodes, CSR of their slots
+  int64_t n_slots = 0;
+  int n_ps = 0;
+  int32_t *d_slot = nullptr, *d_ps_node = nullptr, *d_ps_ptr = nullptr, *d_ps_slot = nullptr;
+  double *d_F64 = nullptr;                // [p nz + 1][n_slots]
+  float *d_F32 = nullptr;
   double *d_cg64 = nullptr;               // [5|3][n_eh*nh] H, H_xi, h_xi, (H_eta, h_eta) per column node
   float *d_cg32 = nullptr;
   float *d_hm32 = nullptr;                // FP32 copy of d_hm
@@ -195,6 +208,11 @@ struct Ctx {
   std::string err;
   int device = 0;
 };
+
+// owner-computes apply (3D line schedule): active for the current settings, and its block count
+// (pass 1 + pass 2 partials of the fused dot product)
+bool owner_apply_active(const Ctx &c);
+int owner_apply_blocks(const Ctx &c);
 
 // host setup (setup.cpp)
 void gll_host(int p, double *x, double *w, double *D);

@@ -717,7 +717,14 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
 //      in place; zeta part of the transposed contraction into registers
 //   3  xi/eta lines: transposed contractions in place in sA, sB
 //   4  line (i,j): y = sA + sB + zeta part, assembled into global y under the colour schedule
-template <int P, typename T, bool MASK, bool DOT>
+//
+// OWN = false: colour schedule (cols = the colour's columns, read-add-write of shared nodes).
+// OWN = true: one launch over all columns (cols unused, column = index); a column stores its
+// contributions at the nodes it owns into y and the others into its face slots F[v][slot];
+// k_apply_faces then adds the slots to the owners.  Blocks are mapped so that each XCD (blocks
+// dispatched round-robin over 8) walks a contiguous range of columns, keeping neighbouring
+// columns' shared cache lines in the same L2.
+template <int P, typename T, bool MASK, bool DOT, bool OWN = false>
 __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T *__restrict__ y,
                                                      const T *__restrict__ cg, const T *__restrict__ hmT,
                                                      int64_t hstride, const T *__restrict__ sig,
@@ -725,7 +732,10 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
                                                      const int32_t *__restrict__ eh_nodes,
                                                      const uint8_t *__restrict__ flags,
                                                      const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
-                                                     double *__restrict__ partial, const int32_t *__restrict__ skip) {
+                                                     double *__restrict__ partial, const int32_t *__restrict__ skip,
+                                                     T *__restrict__ F = nullptr,
+                                                     const int32_t *__restrict__ slot = nullptr,
+                                                     int64_t n_slots = 0) {
   using S = Sh<P, 3>;
   constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
   __shared__ T sU[CPB * NP];
@@ -736,9 +746,14 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
   const int lc = threadIdx.x / NH;
   const int t = threadIdx.x - lc * NH;
   const int i = t % N1, j = t / N1;
-  const int ci = blockIdx.x * CPB + lc;
+  int blk = blockIdx.x;
+  if constexpr (OWN) {
+    const int nb = gridDim.x, q = nb >> 3, r = nb & 7, xc = blk & 7;
+    blk = (xc < r ? xc * (q + 1) : r * (q + 1) + (xc - r) * q) + (blk >> 3);
+  }
+  const int ci = blk * CPB + lc;
   const bool active = ci < ncols;
-  const int col = active ? cols[ci] : 0;
+  const int col = active ? (OWN ? ci : cols[ci]) : 0;
   const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
   const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
   const int64_t ho = (int64_t)col * NH + t;
@@ -771,6 +786,15 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
   const __amdgpu_buffer_rsrc_t rx = vec_rsrc(x, nbytes), ry = vec_rsrc(y, nbytes);
   const uint32_t hb = (uint32_t)hn * (uint32_t)sizeof(T);
   const uint32_t rowb = (uint32_t)n_s * (uint32_t)sizeof(T);
+  // face slots (OWN): [p nz + 1][n_slots]
+  __amdgpu_buffer_rsrc_t rf = ry;
+  uint32_t fb = 0, rowf = 0;
+  if constexpr (OWN) {
+    rf = vec_rsrc(F, (uint32_t)((int64_t)(P * nz + 1) * n_slots * (int64_t)sizeof(T)));
+    const int32_t sl = active ? slot[ho] : -1;
+    fb = (uint32_t)(sl < 0 ? 0 : sl) * (uint32_t)sizeof(T);
+    rowf = (uint32_t)n_slots * (uint32_t)sizeof(T);
+  }
 
   T ucol[N1];
   T carry = T(0);
@@ -856,7 +880,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     T old[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) old[k] = T(0);
-    if (active && !(fl & kFirst)) {
+    if (!OWN && active && !(fl & kFirst)) {
 #pragma unroll
       for (int k = 0; k < N1; ++k)
         if (k < kend) old[k] = buf_ld<T>(ry, hb, (uint32_t)(l * P + k) * rowb);
@@ -873,9 +897,19 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
       for (int k = 0; k < N1; ++k) {
         if (k < kend) {
           const int v = l * P + k;
-          const T val = (MASK && v == vtop) ? T(0) : yv[k] + old[k];
-          buf_st(val, ry, hb, (uint32_t)v * rowb);
-          if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
+          if constexpr (OWN) {
+            if (fl & kOwned) {
+              const T val = (MASK && v == vtop) ? T(0) : yv[k];
+              buf_st(val, ry, hb, (uint32_t)v * rowb);
+              if (DOT && !(fl & kShared)) dot += (double)ucol[k] * (double)val;
+            } else if (!(MASK && v == vtop)) {
+              buf_st(yv[k], rf, fb, (uint32_t)v * rowf);
+            }
+          } else {
+            const T val = (MASK && v == vtop) ? T(0) : yv[k] + old[k];
+            buf_st(val, ry, hb, (uint32_t)v * rowb);
+            if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
+          }
         }
       }
     }
@@ -886,6 +920,83 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     double s = block_sum<CPB * NH>(dot);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
+}
+
+// Second pass of the owner-computes apply: y[v][n] += sum of the face slots of the other
+// columns at shared node n (slots in increasing column order), for every node level v; the
+// dot-product contribution x.y of the shared nodes is taken here.  A thread takes one shared
+// node and a chunk of kFaceLevels levels, with all its loads issued before the sums.  Blocks
+// are remapped so that each XCD walks a contiguous range of nodes of one level chunk (the slots
+// of neighbouring columns then meet in the same L2).
+constexpr int kFaceLevels = 8;
+
+template <typename T, bool MASK, bool DOT>
+__global__ __launch_bounds__(256) void k_apply_faces(const T *__restrict__ x, T *__restrict__ y,
+                                                     const T *__restrict__ F, const int32_t *__restrict__ ps_node,
+                                                     const int32_t *__restrict__ ps_ptr,
+                                                     const int32_t *__restrict__ ps_slot, int n_ps, int nlev,
+                                                     int64_t n_s, int64_t n_slots, double *__restrict__ partial,
+                                                     const int32_t *__restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  constexpr int LC = kFaceLevels;
+  int blk = blockIdx.x;
+  {
+    const int nb = gridDim.x, q = nb >> 3, r = nb & 7, xc = blk & 7;
+    blk = (xc < r ? xc * (q + 1) : r * (q + 1) + (xc - r) * q) + (blk >> 3);
+  }
+  const int nbx = (n_ps + 255) >> 8;
+  const int chunk = blk / nbx;
+  const int k = (blk - chunk * nbx) * 256 + threadIdx.x;
+  const int v0 = chunk * LC;
+  const int vend = MASK ? nlev - 1 : nlev;   // the masked top level stays 0
+  double dot = 0.0;
+  if (k < n_ps) {
+    const int64_t n = ps_node[k];
+    const int a = ps_ptr[k], b = ps_ptr[k + 1];
+    T acc[LC];
+#pragma unroll
+    for (int u = 0; u < LC; ++u) acc[u] = (v0 + u < vend) ? y[(v0 + u) * n_s + n] : T(0);
+    for (int q = a; q < b; ++q) {
+      const int64_t sl = ps_slot[q];
+      T f[LC];
+#pragma unroll
+      for (int u = 0; u < LC; ++u) f[u] = (v0 + u < vend) ? F[(v0 + u) * n_slots + sl] : T(0);
+#pragma unroll
+      for (int u = 0; u < LC; ++u) acc[u] += f[u];
+    }
+    T xv[LC];
+    if constexpr (DOT) {
+#pragma unroll
+      for (int u = 0; u < LC; ++u) xv[u] = (v0 + u < vend) ? x[(v0 + u) * n_s + n] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < LC; ++u) {
+      if (v0 + u < vend) {
+        y[(v0 + u) * n_s + n] = acc[u];
+        if (DOT) dot += (double)xv[u] * (double)acc[u];
+      }
+    }
+  }
+  if constexpr (DOT) {
+    double s = block_sum<256>(dot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+bool owner_apply_active(const Ctx &c) {
+  if (c.dim != 3 || c.apply_variant != 0 || !c.apply_owner) return false;
+  const int64_t lim = int64_t(1) << 32;
+  return c.n_v * 8 < lim && (int64_t)(c.p * c.nz + 1) * c.n_slots * 8 < lim;
+}
+
+static int face_blocks(const Ctx &c) {
+  return ((c.n_ps + 255) / 256) * ((c.p * c.nz + 1 + kFaceLevels - 1) / kFaceLevels);
+}
+
+int owner_apply_blocks(const Ctx &c) {
+  if (c.dim != 3) return 0;
+  const int cpb = 256 / c.nh;
+  return (c.n_eh + cpb - 1) / cpb + face_blocks(c);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1422,6 +1533,19 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
       }
       if (done) continue;
       if constexpr (DIM == 3) {
+        if (owner_apply_active(c)) {
+          T *F = nullptr;
+          if constexpr (sizeof(T) == 8) F = (T *)c.d_F64; else F = (T *)c.d_F32;
+          const int nb1 = (c.n_eh + S::CPB - 1) / S::CPB;
+          k_apply_lines<P, T, MASK, DOT, true><<<nb1, S::NT, 0, s>>>(
+              x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s,
+              DOT ? partial : nullptr, skip, F, c.d_slot, c.n_slots);
+          if (c.n_ps > 0)
+            k_apply_faces<T, MASK, DOT><<<face_blocks(c), 256, 0, s>>>(
+                x, y, F, c.d_ps_node, c.d_ps_ptr, c.d_ps_slot, c.n_ps, c.p * c.nz + 1, c.n_s, c.n_slots,
+                DOT ? partial + nb1 : nullptr, skip);
+          return hipGetLastError();
+        }
         if (c.apply_lines && (int64_t)c.n_v * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
           k_apply_lines<P, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags,
                                                                c.d_cols + cr.offset, cr.count, c.nz, c.n_s,

@@ -13,6 +13,7 @@
 // J_h is obtained by applying D to the nodal coordinates (isoparametric).
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -310,6 +311,47 @@ std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double>
       if (colour[e] == cmax) f |= kLast;
       flags[e * nh + t] = f;
     }
+  }
+  // owner-computes assembly: every horizontal node belongs to the lowest-numbered column that
+  // has it; a column's other nodes get face slots, numbered column by column in local order
+  {
+    std::vector<int32_t> owner(n_s, INT32_MAX);
+    for (int64_t e = 0; e < n_eh; ++e)
+      for (int t = 0; t < nh; ++t) {
+        int32_t id = m.eh_nodes[e * nh + t];
+        owner[id] = std::min(owner[id], (int32_t)e);
+      }
+    c.h_slot.assign(n_eh * nh, -1);
+    int64_t ns = 0;
+    for (int64_t e = 0; e < n_eh; ++e)
+      for (int t = 0; t < nh; ++t) {
+        int32_t id = m.eh_nodes[e * nh + t];
+        if (owner[id] == e)
+          flags[e * nh + t] |= kOwned;
+        else
+          c.h_slot[e * nh + t] = (int32_t)ns++;
+        if (count[id] > 1) flags[e * nh + t] |= kShared;
+      }
+    if (ns >= INT32_MAX) return "too many face slots for the owner-computes apply";
+    c.n_slots = ns;
+    c.h_ps_node.clear();
+    c.h_ps_slot.clear();
+    c.h_ps_ptr.assign(1, 0);
+    for (int64_t n = 0; n < n_s; ++n) {
+      if (count[n] < 2) continue;
+      c.h_ps_node.push_back((int32_t)n);
+      for (int64_t q = off[n]; q < off[n + 1]; ++q) {
+        const int32_t e = adj[q];   // increasing column id
+        if (e == owner[n]) continue;
+        for (int t = 0; t < nh; ++t)
+          if (m.eh_nodes[(int64_t)e * nh + t] == n) {
+            c.h_ps_slot.push_back(c.h_slot[(int64_t)e * nh + t]);
+            break;
+          }
+      }
+      c.h_ps_ptr.push_back((int32_t)c.h_ps_slot.size());
+    }
+    c.n_ps = (int)c.h_ps_node.size();
   }
   return "";
 }

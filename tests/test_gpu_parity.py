@@ -54,10 +54,15 @@ def _case(name):
         wl.eta0 = lambda x, y: 0.05 * np.cos(np.asarray(x)) * np.sin(np.asarray(y))
         wl.phi0 = lambda x, y: 0.1 * np.sin(np.asarray(x) + 0.3 * np.asarray(y))
         return wl
+    if name.endswith("_blocked"):
+        wl = _case(name[: -len("_blocked")])
+        wl.mesh = wm.renumber_blocked(wl.mesh)
+        return wl
     raise KeyError(name)
 
 
-CASES = ["slice_periodic", "slice_walls", "box_periodic", "box_mixed", "box_walls_p6", "cylinder"]
+CASES = ["slice_periodic", "slice_walls", "box_periodic", "box_mixed", "box_walls_p6", "cylinder",
+         "box_mixed_blocked", "cylinder_blocked"]
 
 
 class Pair:
@@ -108,8 +113,8 @@ def test_geometry_parity(name, variant):
     assert np.abs(host(diag) - dref).max() < 1e-13 * np.abs(dref).max()
 
 
-@pytest.mark.parametrize("variant", [0, 6])
-@pytest.mark.parametrize("name", ["slice_periodic", "box_periodic", "cylinder"])
+@pytest.mark.parametrize("variant", [0, 6, 7])
+@pytest.mark.parametrize("name", ["slice_periodic", "box_periodic", "cylinder", "box_mixed_blocked"])
 def test_apply_equals_dense_matrix(name, variant):
     pr = Pair(_case(name), variant=variant)
     pr.ctx.geom(pr.d_eta, pr.d_h)
@@ -123,7 +128,7 @@ def test_apply_equals_dense_matrix(name, variant):
     assert np.abs(Ag @ np.ones(n)).max() <= 1e-12 * np.abs(A).max()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 6])
+@pytest.mark.parametrize("variant", [0, 1, 6, 7])
 @pytest.mark.parametrize("name", CASES)
 def test_apply_random_fp64_fp32(name, variant):
     pr = Pair(_case(name), fp32=True, variant=variant)
@@ -155,7 +160,7 @@ def test_neumann_load_parity(name):
     assert np.abs(f - fo).max() < 1e-13 * np.abs(fo).max()
 
 
-@pytest.mark.parametrize("variant", [0, 6])
+@pytest.mark.parametrize("variant", [0, 6, 7])
 @pytest.mark.parametrize("name", CASES)
 def test_solve_w_rhs_parity(name, variant):
     pr = Pair(_case(name), fp32=True, variant=variant)
@@ -244,7 +249,7 @@ def test_c2_full_size_apply_and_solve():
     yo = op.apply(pr.m, Go, xv)
     assert rel(host(pr.ctx.laplace_apply(dev(xv))), yo) < 1e-13
     assert rel(host(pr.ctx.laplace_apply(dev(xv).float())), yo) < 2e-6
-    for v in (1, 6):
+    for v in (1, 6, 7):
         other = Pair(wl, fp32=True, variant=v)
         other.ctx.geom(other.d_eta, other.d_h)
         assert rel(host(other.ctx.laplace_apply(dev(xv))), yo) < 1e-13
@@ -265,7 +270,7 @@ def test_c2_full_size_apply_and_solve():
         assert rel(host(pr.ctx.w_surface(phi)), wo) < 1e-12
 
 
-@pytest.mark.parametrize("variant", [0, 6])
+@pytest.mark.parametrize("variant", [0, 6, 7])
 def test_c5_sampled_apply(variant):
     """C5 (43,675,392 DoF): apply parity at the nodes of sampled columns (oracle on their neighbourhood)."""
     wl = configs.c5()

@@ -89,3 +89,51 @@ def test_layer_major_surface_slice():
     top = dofs.reshape(m.n_e, m.p + 1, m.p + 1)[m.nz - 1::m.nz, m.p, :]
     # the top node level of the top layer is the contiguous slice [p nz n_s, (p nz + 1) n_s)
     assert top.min() == m.p * m.nz * m.n_s and top.max() == m.n_v - 1
+
+
+@pytest.mark.parametrize("periodic", [(True, False), (False, False), (True, True)])
+def test_renumber_blocked(periodic):
+    """Blocked numbering: a consistent bijection; each column's own nodes are one run, shared first."""
+    m = wm.structured_box(5, 4, 0.0, 2.0, 0.0, 1.5, periodic[0], periodic[1], p=3, nz=2)
+    b = wm.renumber_blocked(m)
+    geo.check_numbering(b)
+    # the same physical node at every (column, local node)
+    perm = np.full(m.n_s, -1)
+    perm[m.eh_nodes.ravel()] = b.eh_nodes.ravel()
+    assert np.all(np.sort(perm) == np.arange(m.n_s))
+    assert np.all(perm[m.eh_nodes] == b.eh_nodes)
+    counts = np.bincount(b.eh_nodes.ravel(), minlength=b.n_s)
+    nxt = 0
+    for e in range(b.n_eh):
+        ids = b.eh_nodes[e]
+        owned = [g for g in ids if not np.any(b.eh_nodes[:e] == g)]
+        assert sorted(owned) == list(range(nxt, nxt + len(owned)))
+        shared = [g for g in owned if counts[g] > 1]
+        assert sorted(shared) == list(range(nxt, nxt + len(shared)))
+        nxt += len(owned)
+    assert nxt == b.n_s
+
+
+def test_apply_invariant_under_renumbering():
+    """The oracle's apply commutes with a renumbering of the horizontal nodes."""
+    from oracle import operator as op
+    wl = configs.small_box(nx=4, ny=3, nz=2, p=3, periodic=(True, False))
+    m = wl.mesh
+    b = wm.renumber_blocked(m)
+    perm = np.full(m.n_s, -1)
+    perm[m.eh_nodes.ravel()] = b.eh_nodes.ravel()
+    levels = m.p * m.nz + 1
+    vperm = (np.arange(levels)[:, None] * m.n_s + perm[None, :]).ravel()   # old volume index -> new
+    x, y = geo.node_xy(m)
+    h, eta = wl.depth(x, y), wl.eta0(x, y)
+    G, _, _ = geo.factors(m, eta, h)
+    xb_pos = geo.node_xy(b)
+    Gb, _, _ = geo.factors(b, eta[np.argsort(perm)], h[np.argsort(perm)])
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(m.n_v)
+    ub = np.empty_like(u)
+    ub[vperm] = u
+    ya = op.apply(m, G, u)
+    yb = op.apply(b, Gb, ub)
+    assert np.abs(yb[vperm] - ya).max() < 1e-13 * np.abs(ya).max()
+    assert np.abs(xb_pos[0][perm] - x).max() < 1e-14

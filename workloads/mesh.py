@@ -293,3 +293,33 @@ def cylinder_tank_mesh(p: int = 4, nz: int = 4, seed: int = 0, n_theta: int = 48
     m = quad_mesh_from_vertices(verts, quads, p, nz, arcs=np.array(arcs), face_tag=np.array(tags), name=name)
     m.extra.update(dict(tank=tank, center=(cx, cy), radius=radius, n_block=int(len(quads) - n_theta * n_rad)))
     return m
+
+
+def renumber_blocked(m: HexMesh) -> HexMesh:
+    """The same mesh with its horizontal nodes renumbered column by column.
+
+    Every node goes to the lowest-numbered horizontal element (column) that has it; each
+    column's nodes get consecutive ids, the ones it shares with other columns first, then its
+    interior ones, both in local order.  A volume vector (layer-major) then holds each
+    column's own nodes at a node level as one contiguous run, and the shared ones of a column
+    as a shorter run at its start.
+    """
+    import dataclasses
+    nodes = m.eh_nodes.astype(np.int64)
+    n_eh, nh = nodes.shape
+    g = nodes.ravel()
+    col = np.repeat(np.arange(n_eh), nh)
+    loc = np.tile(np.arange(nh), n_eh)
+    owner = np.full(m.n_s, n_eh, dtype=np.int64)
+    np.minimum.at(owner, g, col)
+    count = np.bincount(g, minlength=m.n_s)
+    mine = col == owner[g]
+    og, oloc = g[mine], loc[mine]
+    key_col = owner[og]
+    key_int = (count[og] == 1).astype(np.int64)
+    order = np.lexsort((oloc, key_int, key_col))
+    new = np.empty(m.n_s, dtype=np.int64)
+    new[og[order]] = np.arange(og.size)
+    extra = dict(m.extra)
+    extra["numbering"] = "blocked"
+    return dataclasses.replace(m, eh_nodes=new[nodes].astype(np.int32), extra=extra)

@@ -191,7 +191,7 @@ def adjoint_leg(nsteps, rtol, fd_dirs):
     # rest), so that the gauges see the bathymetry within the differentiated steps
     eta_in = torch.tensor(wl.relax_wave.eta(x, y, 0.0), device="cuda")
     phi_in = torch.tensor(wl.relax_wave.phi(x, y, 0.0), device="cuda")
-    o = fnpf.default_opts(rtol=rtol, check_every=25)
+    o = fnpf.default_opts(rtol=rtol, check_every=5)
     with torch.no_grad():
         obs = rollout(fctx, eta_in, phi_in, B @ c_true, 0.0, wl.dt, nsteps, opts=o) @ P.T
 
@@ -258,6 +258,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-steps", action="store_true")
+    ap.add_argument("--no-jacobi-steps", action="store_true",
+                    help="skip the reference mixed steps with the Jacobi preconditioner")
     ap.add_argument("--apply-only", action="store_true",
                     help="only the apply loops (FP64, FP32) and a calibration copy of n_v doubles (for counters)")
     ap.add_argument("--variant", type=int, default=0, help="apply variant (fnpf_set_apply_variant)")
@@ -308,8 +310,10 @@ def main():
         return
 
     # -- ERK4 steps --------------------------------------------------------------------
-    o_mixed = fnpf.default_opts(precision=1, rtol=args.rtol, inner_rtol=1e-4, check_every=25, max_outer=30)
-    o_f64 = fnpf.default_opts(precision=0, rtol=args.rtol, check_every=25)
+    o_mixed = fnpf.default_opts(precision=1, rtol=args.rtol, inner_rtol=1e-4, check_every=5, max_outer=30)
+    o_f64 = fnpf.default_opts(precision=0, rtol=args.rtol, check_every=5)
+    o_jacobi = fnpf.default_opts(precision=1, precond=1, rtol=args.rtol, inner_rtol=1e-4, check_every=25,
+                                 max_outer=30)
     ctx.set_warm_start(None)
     e, p, t, _ = run_steps(s, wl, o_mixed, args.warmup)
     torch.cuda.synchronize()
@@ -329,6 +333,17 @@ def main():
         torch.cuda.synchronize()
         t_f64 = (time.perf_counter() - t0) / args.steps
         print(f"[bench] fp64 step {t_f64:.3f} s, iters {it_f64}", file=sys.stderr, flush=True)
+
+    t_jac, it_jac = None, None
+    if not args.no_jacobi_steps:
+        ctx.set_warm_start(None)
+        e, p, t, _ = run_steps(s, wl, o_jacobi, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, it_jac = run_steps(s, wl, o_jacobi, args.steps, t0=t, eta=e, phi=p)
+        torch.cuda.synchronize()
+        t_jac = (time.perf_counter() - t0) / args.steps
+        print(f"[bench] mixed Jacobi-PCG step {t_jac:.3f} s, iters {it_jac}", file=sys.stderr, flush=True)
 
     adj = None
     if args.adjoint_steps > 0:
@@ -355,8 +370,9 @@ def main():
                     parallelism="single GPU"),
         apply_gdofs=dict(f64=m.n_v / t64 / 1e9, f32=m.n_v / t32 / 1e9),
         apply_ms=dict(f64=t64 * 1e3, f32=t32 * 1e3, f64_mean=t64_mean * 1e3, f32_mean=t32_mean * 1e3),
-        s_per_rk4_step=dict(f64=t_f64, mixed=t_mixed),
-        pcg_iters_per_stage=dict(f64=it_f64, mixed=it_mixed),
+        s_per_rk4_step=dict(f64=t_f64, mixed=t_mixed, mixed_jacobi=t_jac),
+        pcg_iters_per_stage=dict(f64=it_f64, mixed=it_mixed, mixed_jacobi=it_jac),
+        preconditioner="p-multigrid V-cycle (degrees 6, 3, 1; Chebyshev-Jacobi smoothing, degree 3)",
         adjoint_forward_ratio=None if adj is None else adj["ratio"],
         adjoint=adj,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,

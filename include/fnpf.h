@@ -101,8 +101,19 @@ typedef struct {
  *                (residual with the FP64 operator, FP64 solution update)
  *                around an FP32 inner PCG (FP32 geometric factors, vectors
  *                and apply; FP64 dot products and scalars).
- *   precond   1: Jacobi (assembled diagonal); the only preconditioner of
- *                this build (other values are rejected with FNPF_ERR_ARG).
+ *   precond   0: none (CG on A_II).  1: Jacobi (assembled diagonal).
+ *             2: p-multigrid V-cycle (the paper's CG uses algebraic
+ *                multigrid, Sec. 4): levels of degree p, p/2, ..., 1 on the
+ *                same mesh, each a context of this library with its geometry
+ *                interpolated from eta + h and h; tensor-product Lagrange
+ *                interpolation between levels and its transpose; Chebyshev
+ *                smoothing of D^-1 A of degree cheb_degree before and after
+ *                each coarse correction (interval [lmax/4, lmax], lmax 1.1x a
+ *                power-iteration estimate refreshed after every fnpf_geom)
+ *                and 10 Chebyshev steps on the degree-1 level.  The V-cycle is
+ *                a fixed SPD operator, so the outer iteration is plain CG.
+ *                The levels are built on first use (device memory about 0.3x
+ *                of the fine level's vectors per precision).
  *   Stop when ||r||_2 <= max(rtol ||b||_2, atol), b = f_I - A_IS phi_s
  *   (unpreconditioned 2-norms over the non-surface nodes).
  *   max_iter bounds the total PCG iterations (inner ones for mixed);
@@ -125,6 +136,7 @@ typedef struct {
   double inner_rtol;
   int32_t max_outer;
   int32_t extrapolate;
+  int32_t cheb_degree;   /* precond 2: smoothing degree, 1 .. 8 (default 3) */
 } fnpf_solve_opts;
 
 typedef struct {
@@ -134,8 +146,8 @@ typedef struct {
   double bnorm;         /* ||b||_2 */
 } fnpf_solve_info;
 
-/* Defaults: FP64, Jacobi, rtol 1e-8, atol 0, max_iter 20000, check_every 25,
- * inner_rtol 1e-4, max_outer 30, extrapolate 1. */
+/* Defaults: FP64, p-multigrid (precond 2), rtol 1e-8, atol 0, max_iter 20000,
+ * check_every 8, inner_rtol 1e-4, max_outer 30, extrapolate 1, cheb_degree 3. */
 void fnpf_default_opts(fnpf_solve_opts *opts);
 
 /* Create a context on the current HIP device: validates and copies the mesh,

@@ -55,6 +55,9 @@ void dfree(T *&p) {
 }
 
 void free_all(Ctx &c) {
+  mg_free(c);
+  dfree(c.d_mask);
+  dfree(c.d_mask32);
   dfree(c.d_eh_nodes);
   dfree(c.d_cols);
   dfree(c.d_slot);
@@ -157,7 +160,7 @@ fnpf_status ensure32(Ctx &c) {
   HIPCHK(dalloc(&c.d_p32, c.n_v));
   HIPCHK(dalloc(&c.d_q32, c.n_v));
   HIPCHK(dalloc(&c.d_d32, c.n_v));
-  if (c.dim == 3) HIPCHK(dalloc(&c.d_F32, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(c.n_slots, 1)));
+  HIPCHK(dalloc(&c.d_F32, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(c.n_slots, 1)));
   c.want32 = true;
   c.have_geom32 = false;
   return FNPF_OK;
@@ -200,19 +203,54 @@ int apply_blocks(const Ctx &c) {
   return c.max_colour_blocks;
 }
 
+// Diagonal scaling of the preconditioner choice: the Jacobi inverse (1), or the mask of the
+// non-surface unknowns (0: none; 2: the first direction before the multigrid one replaces it).
+fnpf_status ensure_mask(Ctx &c, hipStream_t s) {
+  if (c.d_mask) return FNPF_OK;
+  HIPCHK(dalloc(&c.d_mask, c.n_v));
+  HIPCHK(launch_fill(c.d_mask, 1.0, c.n_v, s));
+  HIPCHK(launch_fill(c.d_mask + (c.n_v - c.n_s), 0.0, c.n_s, s));
+  if (c.want32) {
+    HIPCHK(dalloc(&c.d_mask32, c.n_v));
+    HIPCHK(launch_cast_f32(c.d_mask, c.d_mask32, c.n_v, s));
+  }
+  return FNPF_OK;
+}
+
 // PCG on A_II (FP64), x = phi holds the guess with its surface level set.
 fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, int &iters, hipStream_t s) {
   PcgScalars *sc = c.d_sc;
+  const bool mg = o.precond == 2;
+  if (o.precond != 1) {
+    fnpf_status st = ensure_mask(c, s);
+    if (st != FNPF_OK) return st;
+  }
+  if (mg) {
+    fnpf_status st = mg_refresh<double>(c, s);
+    if (st != FNPF_OK) return fail(&c, st, c.err.empty() ? "p-multigrid setup failed" : c.err);
+  }
+  const double *dinv = o.precond == 1 ? c.d_dinv : c.d_mask;
+  double *z = mg ? c.mg_f64[0] : nullptr;
   HIPCHK(launch_apply(c, FNPF_F64, x, c.d_q, true, nullptr, nullptr, s));
-  HIPCHK(launch_pcg_init<double>(f, c.d_q, c.d_r, c.d_p, c.d_dinv, c.n_v, c.n_s, c.d_partial, sc, false, 0.0, s));
+  HIPCHK(launch_pcg_init<double>(f, c.d_q, c.d_r, c.d_p, dinv, c.n_v, c.n_s, c.d_partial, sc, false, 0.0, s));
+  if (mg) {
+    HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, s));
+    HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 1, s));
+  }
   const int nb = apply_blocks(c);
   iters = 0;
   for (;;) {
     for (int k = 0; k < o.check_every; ++k) {
       HIPCHK(launch_apply(c, FNPF_F64, c.d_p, c.d_q, true, c.d_partial, &sc->done, s));
       HIPCHK(launch_finalize_pq(c.d_partial, nb, sc, s));
-      HIPCHK((launch_pcg_update<double, double>(x, c.d_r, c.d_p, c.d_q, c.d_dinv, c.n_v, c.d_partial, sc, s)));
-      HIPCHK(launch_pcg_dir<double>(c.d_p, c.d_r, c.d_dinv, c.n_v, sc, s));
+      if (mg) {
+        HIPCHK(launch_mg_update(c, FNPF_F64, x, c.d_r, c.d_p, c.d_q, c.d_partial, sc, s));
+        HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, s));
+        HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 0, s));
+      } else {
+        HIPCHK((launch_pcg_update<double, double>(x, c.d_r, c.d_p, c.d_q, dinv, c.n_v, c.d_partial, sc, s)));
+        HIPCHK(launch_pcg_dir<double>(c.d_p, c.d_r, dinv, c.n_v, sc, s));
+      }
     }
     HIPCHK(hipMemcpyAsync(c.h_sc, c.d_sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -220,7 +258,8 @@ fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, 
     if (c.h_sc[0].done || iters >= o.max_iter) break;
   }
   if (c.h_sc[0].breakdown == 2) return fail(&c, FNPF_ERR_NAN, "non-finite residual in PCG");
-  if (c.h_sc[0].breakdown == 1) return fail(&c, FNPF_ERR_BREAKDOWN, "PCG breakdown: p^T A p <= 0");
+  if (c.h_sc[0].breakdown == 1)
+    return fail(&c, FNPF_ERR_BREAKDOWN, "PCG breakdown: p^T A p <= 0 or r^T z <= 0");
   if (!c.h_sc[0].done) return fail(&c, FNPF_ERR_NOCONV, "PCG did not reach the tolerance within max_iter");
   return FNPF_OK;
 }
@@ -229,13 +268,28 @@ fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, 
 fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, int &iters, int &outer,
                       hipStream_t s) {
   PcgScalars *so = c.d_sc, *si = c.d_sc + 1;
+  const bool mg = o.precond == 2;
+  if (o.precond != 1) {
+    fnpf_status st = ensure_mask(c, s);
+    if (st != FNPF_OK) return st;
+  }
+  if (mg) {
+    fnpf_status st = mg_refresh<float>(c, s);
+    if (st != FNPF_OK) return fail(&c, st, c.err.empty() ? "p-multigrid setup failed" : c.err);
+  }
+  const float *dinv = o.precond == 1 ? c.d_dinv32 : c.d_mask32;
+  float *z = mg ? c.mg_f32[0] : nullptr;
   const int nb = apply_blocks(c);
   iters = 0;
   outer = 0;
   for (;;) {
     HIPCHK(launch_apply(c, FNPF_F64, x, c.d_q, true, nullptr, nullptr, s));
-    HIPCHK(launch_resid_to32(f, c.d_q, c.d_r32, c.d_p32, c.d_d32, c.d_dinv32, c.n_v, c.n_s, c.d_partial, so, si,
+    HIPCHK(launch_resid_to32(f, c.d_q, c.d_r32, c.d_p32, c.d_d32, dinv, c.n_v, c.n_s, c.d_partial, so, si,
                              o.inner_rtol, s));
+    if (mg) {
+      HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, s));
+      HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 1, s));
+    }
     ++outer;
     HIPCHK(hipMemcpyAsync(c.h_sc, c.d_sc, 2 * sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -247,9 +301,15 @@ fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts 
       for (int k = 0; k < o.check_every; ++k) {
         HIPCHK(launch_apply(c, FNPF_F32, c.d_p32, c.d_q32, true, c.d_partial, &si->done, s));
         HIPCHK(launch_finalize_pq(c.d_partial, nb, si, s));
-        HIPCHK((launch_pcg_update<float, float>(c.d_d32, c.d_r32, c.d_p32, c.d_q32, c.d_dinv32, c.n_v, c.d_partial,
-                                                si, s)));
-        HIPCHK(launch_pcg_dir<float>(c.d_p32, c.d_r32, c.d_dinv32, c.n_v, si, s));
+        if (mg) {
+          HIPCHK(launch_mg_update(c, FNPF_F32, c.d_d32, c.d_r32, c.d_p32, c.d_q32, c.d_partial, si, s));
+          HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, s));
+          HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 0, s));
+        } else {
+          HIPCHK((launch_pcg_update<float, float>(c.d_d32, c.d_r32, c.d_p32, c.d_q32, dinv, c.n_v, c.d_partial, si,
+                                                  s)));
+          HIPCHK(launch_pcg_dir<float>(c.d_p32, c.d_r32, dinv, c.n_v, si, s));
+        }
       }
       HIPCHK(hipMemcpyAsync(c.h_sc + 1, si, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -265,7 +325,10 @@ fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts 
 
 fnpf_status validate_opts(Ctx &c, const fnpf_solve_opts &o) {
   if (o.precision != 0 && o.precision != 1) return fail(&c, FNPF_ERR_ARG, "opts.precision must be 0 or 1");
-  if (o.precond != 1) return fail(&c, FNPF_ERR_ARG, "opts.precond must be 1 (Jacobi)");
+  if (o.precond < 0 || o.precond > 2)
+    return fail(&c, FNPF_ERR_ARG, "opts.precond must be 0 (none), 1 (Jacobi) or 2 (p-multigrid)");
+  if (o.precond == 2 && (o.cheb_degree < 1 || o.cheb_degree > 8))
+    return fail(&c, FNPF_ERR_ARG, "opts.cheb_degree must be in 1..8 for the p-multigrid preconditioner");
   if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || (o.rtol == 0.0 && o.atol == 0.0))
     return fail(&c, FNPF_ERR_ARG, "opts.rtol/atol must be >= 0 and not both 0");
   if (o.max_iter < 1 || o.check_every < 1) return fail(&c, FNPF_ERR_ARG, "opts.max_iter and check_every must be >= 1");
@@ -310,24 +373,43 @@ fnpf_status geom_impl(Ctx &c, const double *eta, const double *h, hipStream_t s)
   c.have_geom = true;
   c.have_geom32 = c.want32;
   c.have_G = store;
+  c.mg_stale64 = c.mg_stale32 = true;
   return FNPF_OK;
 }
 
 }  // namespace
+
+namespace fnpf {
+
+Ctx &ctx_of(fnpf_ctx h) { return h->c; }
+
+fnpf_status ctx_ensure32(Ctx &c) { return ensure32(c); }
+
+// geometry from eta + h (H) and h, as the coarse levels of the p-multigrid get it
+fnpf_status geom_impl_total(Ctx &c, const double *H, const double *h, hipStream_t s) {
+  HIPCHK(launch_geom(c, H, h, false, true, s));
+  c.have_geom = true;
+  c.have_geom32 = c.want32;
+  c.have_G = false;
+  return FNPF_OK;
+}
+
+}  // namespace fnpf
 
 extern "C" {
 
 void fnpf_default_opts(fnpf_solve_opts *o) {
   if (!o) return;
   o->precision = 0;
-  o->precond = 1;
+  o->precond = 2;
   o->rtol = 1e-8;
   o->atol = 0.0;
   o->max_iter = 20000;
-  o->check_every = 25;
+  o->check_every = 8;
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
   o->extrapolate = 1;
+  o->cheb_degree = 3;
 }
 
 const char *fnpf_status_string(fnpf_status s) {
@@ -428,7 +510,7 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   } while (0)
   UP(c.d_eh_nodes, c.h_eh_nodes.data(), c.h_eh_nodes.size());
   UP(c.d_cols, cols.data(), cols.size());
-  if (c.dim == 3) {
+  {
     UP(c.d_slot, c.h_slot.data(), c.h_slot.size());
     UP(c.d_ps_node, c.h_ps_node.data(), std::max<size_t>(c.h_ps_node.size(), 1));
     UP(c.d_ps_ptr, c.h_ps_ptr.data(), c.h_ps_ptr.size());

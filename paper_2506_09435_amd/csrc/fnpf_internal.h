@@ -119,6 +119,19 @@ hipError_t launch_zero_i32(int32_t *v, int64_t n, hipStream_t s);
 constexpr int kVecBlocks = 1024;   // fixed grid of the grid-stride vector kernels (deterministic partials)
 constexpr int kVecThreads = 256;
 
+// one coarse level of the p-multigrid preconditioner
+struct MgLevel {
+  fnpf_ctx child = nullptr;               // context of the same mesh at the coarse degree (owned)
+  struct Ctx *c = nullptr;                // its state
+  double *Hc = nullptr, *hc = nullptr;    // eta + h and h at its surface nodes
+  double *v64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // b, x, r, d, q
+  float *v32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double lam64 = 0.0, lam32 = 0.0;        // estimated largest eigenvalue of D^-1 A
+  double *ev64 = nullptr;                 // its eigenvector estimate (power-iteration warm start)
+  float *ev32 = nullptr;
+  bool ev_ok64 = false, ev_ok32 = false;
+};
+
 struct Ctx {
   // mesh
   int dim = 3, p = 1, nz = 1, n_eh = 0;
@@ -126,6 +139,9 @@ struct Ctx {
   int nh = 1, np = 1, ng = 6;
   double g = 9.81;
   std::vector<int32_t> h_eh_nodes;
+  std::vector<double> h_corner;           // [n_eh][2^(dim-1)][dim-1]
+  std::vector<double> h_arc;              // [n_eh][4][3] or empty
+  std::vector<int32_t> h_tags;            // [n_eh][2(dim-1)]
   std::vector<double> h_node_xy;          // [n_s][dim-1]
   std::vector<double> h_layer_s;          // [nz+1]
   std::vector<double> h_sigma;            // [p nz + 1]
@@ -201,6 +217,18 @@ struct Ctx {
   double *d_kbe = nullptr, *d_kbp = nullptr, *d_ybe = nullptr, *d_ybp = nullptr;
   double *d_acce = nullptr, *d_accp = nullptr, *d_wbar = nullptr, *d_zero_s = nullptr;
   bool have_adjoint = false;
+  // p-multigrid preconditioner (built on first use; the fine level is this context)
+  std::vector<MgLevel> mg;
+  bool mg_built = false;
+  bool mg_stale64 = true, mg_stale32 = true;   // geometry changed since the last refresh
+  double *mg_f64[4] = {nullptr, nullptr, nullptr, nullptr};  // fine-level z, r, d, q
+  float *mg_f32[4] = {nullptr, nullptr, nullptr, nullptr};
+  double lam64 = 0.0, lam32 = 0.0;
+  double *mg_ev64 = nullptr;              // fine-level eigenvector estimate
+  float *mg_ev32 = nullptr;
+  bool mg_ev_ok64 = false, mg_ev_ok32 = false;
+  double *d_mask = nullptr;               // 1 below the surface level, 0 on it (no preconditioner)
+  float *d_mask32 = nullptr;
   // relaxation
   double *d_cr = nullptr, *d_rec = nullptr, *d_res = nullptr, *d_rpc = nullptr, *d_rps = nullptr;
   double relax_omega = 0.0, relax_tramp = 0.0;
@@ -214,8 +242,25 @@ struct Ctx {
 bool owner_apply_active(const Ctx &c);
 int owner_apply_blocks(const Ctx &c);
 
+// p-multigrid (multigrid.hip)
+fnpf_status mg_build(Ctx &c);
+void mg_free(Ctx &c);
+template <typename T>
+fnpf_status mg_refresh(Ctx &c, hipStream_t s);
+template <typename T>
+hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth, hipStream_t s);
+hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void *p, const void *q, double *partial,
+                            PcgScalars *sc, hipStream_t s);
+hipError_t launch_mg_dot_dir(Ctx &c, fnpf_dtype dt, const void *r, const void *z, void *p, double *partial,
+                             PcgScalars *sc, int first, hipStream_t s);
+Ctx &ctx_of(fnpf_ctx h);
+fnpf_status ctx_ensure32(Ctx &c);
+fnpf_status geom_impl_total(Ctx &c, const double *H, const double *h, hipStream_t s);
+hipError_t launch_faces(Ctx &c, fnpf_dtype dt, void *y, bool mask, hipStream_t s, const int32_t *skip);
+
 // host setup (setup.cpp)
 void gll_host(int p, double *x, double *w, double *D);
+std::string coarse_numbering(const Ctx &f, int pc, std::vector<int32_t> &nodes, int64_t &n_s);
 std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double> &hm, std::vector<uint8_t> &flags,
                             std::vector<int32_t> &cols, std::vector<double> &mlump_w, std::vector<double> &mlump_s);
 

@@ -993,6 +993,34 @@ static int face_blocks(const Ctx &c) {
   return ((c.n_ps + 255) / 256) * ((c.p * c.nz + 1 + kFaceLevels - 1) / kFaceLevels);
 }
 
+// the face pass alone (k_apply_faces without the dot product): y at the shared nodes += the face
+// slots of the context's F buffer of y's precision
+hipError_t launch_faces(Ctx &c, fnpf_dtype dt, void *y, bool mask, hipStream_t s, const int32_t *skip) {
+  if (c.n_ps == 0) return hipSuccess;
+  const int nb = face_blocks(c);
+  const int nlev = c.p * c.nz + 1;
+  if (dt == FNPF_F64) {
+    if (mask)
+      k_apply_faces<double, true, false><<<nb, 256, 0, s>>>(nullptr, (double *)y, c.d_F64, c.d_ps_node, c.d_ps_ptr,
+                                                            c.d_ps_slot, c.n_ps, nlev, c.n_s, c.n_slots, nullptr,
+                                                            skip);
+    else
+      k_apply_faces<double, false, false><<<nb, 256, 0, s>>>(nullptr, (double *)y, c.d_F64, c.d_ps_node,
+                                                             c.d_ps_ptr, c.d_ps_slot, c.n_ps, nlev, c.n_s,
+                                                             c.n_slots, nullptr, skip);
+  } else {
+    if (mask)
+      k_apply_faces<float, true, false><<<nb, 256, 0, s>>>(nullptr, (float *)y, c.d_F32, c.d_ps_node, c.d_ps_ptr,
+                                                           c.d_ps_slot, c.n_ps, nlev, c.n_s, c.n_slots, nullptr,
+                                                           skip);
+    else
+      k_apply_faces<float, false, false><<<nb, 256, 0, s>>>(nullptr, (float *)y, c.d_F32, c.d_ps_node, c.d_ps_ptr,
+                                                            c.d_ps_slot, c.n_ps, nlev, c.n_s, c.n_slots, nullptr,
+                                                            skip);
+  }
+  return hipGetLastError();
+}
+
 int owner_apply_blocks(const Ctx &c) {
   if (c.dim != 3) return 0;
   const int cpb = 256 / c.nh;

@@ -1,0 +1,824 @@
+// p-multigrid preconditioner for the Laplace system on A_II.
+//
+// The paper solves the Laplace system with CG preconditioned by algebraic multigrid (Sec. 4
+// solver settings).  Here the preconditioner is a V-cycle over polynomial degrees of the same
+// extruded mesh, p -> p/2 -> ... -> 1: every level is a full context of the library at its
+// degree (same columns, layers and corners; geometry from eta + h and h interpolated to its
+// surface nodes), with Chebyshev smoothing of the Jacobi-scaled operator D^-1 A.  The transfer
+// between a level of degree pf and the next of degree pc = pf/2 is the tensor-product Lagrange
+// interpolation P of the coarse element polynomial at the fine GLL nodes, element by element;
+// the restriction is its exact transpose.  With the same polynomial before and after the coarse
+// correction, the V-cycle is a fixed symmetric positive definite operator, so the outer
+// iteration stays plain CG.
+//
+// Deterministic: each fine node takes its interpolated value from the column that owns it, the
+// restriction counts each fine node once (in its owner column, the shared layer level in the
+// upper layer), and coarse sums are assembled with the owner-computes face slots of the coarse
+// level; every reduction has a fixed order.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fnpf_internal.h"
+
+namespace fnpf {
+
+namespace {
+
+constexpr int kMgCoarseSteps = 10;      // Chebyshev steps on the coarsest level
+constexpr double kMgSafety = 1.1;       // upper end of the smoothing interval over the estimate
+constexpr double kMgSmoothRatio = 4.0;  // smoothing interval [lmax / 4, lmax]
+constexpr double kMgCoarseRatio = 30.0;
+constexpr int kPowFirst = 15, kPowNext = 4;   // power iterations (cold, warm start)
+
+// Interpolation tables for a fine degree pf (2..8) and pc = pf / 2:
+//   c_IP[pf][r (pc+1) + a] = l^c_a(x^f_r)   coarse Lagrange basis at the fine GLL nodes
+//   c_IS[pf][a (pf+1) + i] = l^f_i(x^c_a)   fine Lagrange basis at the coarse GLL nodes
+__constant__ double c_IP64[kMaxN1][kMaxN1 * kMaxN1];
+__constant__ float c_IP32[kMaxN1][kMaxN1 * kMaxN1];
+__constant__ double c_IS64[kMaxN1][kMaxN1 * kMaxN1];
+
+template <typename T>
+__device__ __forceinline__ T ip(int pf, int k);
+template <>
+__device__ __forceinline__ double ip<double>(int pf, int k) { return c_IP64[pf][k]; }
+template <>
+__device__ __forceinline__ float ip<float>(int pf, int k) { return c_IP32[pf][k]; }
+
+double lagrange(const double *X, int n1, int j, double x) {
+  double v = 1.0;
+  for (int m = 0; m < n1; ++m)
+    if (m != j) v *= (x - X[m]) / (X[j] - X[m]);
+  return v;
+}
+
+hipError_t upload_tables() {
+  static double IP[kMaxN1][kMaxN1 * kMaxN1];
+  static float IP32[kMaxN1][kMaxN1 * kMaxN1];
+  static double IS[kMaxN1][kMaxN1 * kMaxN1];
+  std::memset(IP, 0, sizeof IP);
+  std::memset(IP32, 0, sizeof IP32);
+  std::memset(IS, 0, sizeof IS);
+  for (int pf = 2; pf <= kMaxP; ++pf) {
+    const int pc = pf / 2;
+    double xf[kMaxN1], xc[kMaxN1];
+    gll_host(pf, xf, nullptr, nullptr);
+    gll_host(pc, xc, nullptr, nullptr);
+    for (int r = 0; r <= pf; ++r)
+      for (int a = 0; a <= pc; ++a) {
+        IP[pf][r * (pc + 1) + a] = lagrange(xc, pc + 1, a, xf[r]);
+        IP32[pf][r * (pc + 1) + a] = (float)IP[pf][r * (pc + 1) + a];
+      }
+    for (int a = 0; a <= pc; ++a)
+      for (int i = 0; i <= pf; ++i) IS[pf][a * (pf + 1) + i] = lagrange(xf, pf + 1, i, xc[a]);
+  }
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_IP64), IP, sizeof IP);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_IP32), IP32, sizeof IP32);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_IS64), IS, sizeof IS);
+}
+
+template <int P, int DIM>
+struct Lay {
+  static constexpr int N1 = P + 1;
+  static constexpr int NH = DIM == 3 ? N1 * N1 : N1;
+  static constexpr int CPB = 256 / NH;
+  static constexpr int NT = CPB * NH;
+};
+
+// ---- transfer kernels ------------------------------------------------------------------------
+
+// Coarse surface data (eta + h and h) at the coarse nodes from the fine nodal values.
+template <int PF, int DIM>
+__global__ __launch_bounds__(256) void k_mg_surf(const double *__restrict__ Hf, const double *__restrict__ hf,
+                                                 const int32_t *__restrict__ nodes_f,
+                                                 const int32_t *__restrict__ nodes_c,
+                                                 const uint8_t *__restrict__ flags_c, int ncols,
+                                                 double *__restrict__ Hc, double *__restrict__ hc) {
+  constexpr int PC = PF / 2, N1F = PF + 1, N1C = PC + 1;
+  constexpr int NHC = Lay<PC, DIM>::NH, NHF = Lay<PF, DIM>::NH;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t col = g / NHC;
+  const int t = (int)(g - col * NHC);
+  if (col >= ncols) return;
+  if (!(flags_c[col * NHC + t] & kOwned)) return;
+  const int a = t % N1C, b = DIM == 3 ? t / N1C : 0;
+  double sH = 0.0, sh = 0.0;
+  for (int j = 0; j < (DIM == 3 ? N1F : 1); ++j) {
+    const double wj = DIM == 3 ? c_IS64[PF][b * N1F + j] : 1.0;
+    for (int i = 0; i < N1F; ++i) {
+      const double w = wj * c_IS64[PF][a * N1F + i];
+      const int n = nodes_f[col * NHF + j * N1F + i];
+      sH += w * Hf[n];
+      sh += w * hf[n];
+    }
+  }
+  const int n = nodes_c[col * NHC + t];
+  Hc[n] = sH;
+  hc[n] = sh;
+}
+
+// Restriction b_c = P^T r_f.  One thread per (column, fine horizontal node); per layer, the fine
+// line (owner columns only; the shared layer level counts in the upper layer) is contracted
+// vertically in registers, then threads of coarse horizontal nodes contract horizontally from
+// LDS and assemble: coarse nodes owned by the column go to b_c, the others to the coarse face
+// slots (summed by the coarse level's face pass).  The coarse surface level is set to zero.
+template <int PF, int DIM, typename T>
+__global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, T *__restrict__ bc, T *__restrict__ Fc,
+                                                  const int32_t *__restrict__ nodes_f,
+                                                  const uint8_t *__restrict__ flags_f,
+                                                  const int32_t *__restrict__ nodes_c,
+                                                  const uint8_t *__restrict__ flags_c,
+                                                  const int32_t *__restrict__ slot_c, int ncols, int nz,
+                                                  int64_t ns_f, int64_t ns_c, int64_t nslots_c,
+                                                  const int32_t *__restrict__ skip) {
+  using LF = Lay<PF, DIM>;
+  constexpr int PC = PF / 2, N1F = PF + 1, N1C = PC + 1;
+  constexpr int NHF = LF::NH, CPB = LF::CPB, NHC = Lay<PC, DIM>::NH;
+  __shared__ T sW[CPB * N1C * NHF];
+  if (skip != nullptr && *skip) return;
+  const int lc = threadIdx.x / NHF;
+  const int t = threadIdx.x - lc * NHF;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? ci : 0;
+  const int hn = active ? nodes_f[col * NHF + t] : 0;
+  const bool own = active && (flags_f[col * NHF + t] & kOwned);
+  const bool cthr = active && t < NHC;
+  const int hnc = cthr ? nodes_c[col * NHC + t] : 0;
+  const uint8_t flc = cthr ? flags_c[col * NHC + t] : 0;
+  const int32_t slc = cthr ? slot_c[col * NHC + t] : 0;
+  const int a = t % N1C, b = DIM == 3 ? (t / N1C) % N1C : 0;
+  T *W = sW + lc * N1C * NHF;
+  const int vtop = PC * nz;
+  T carry = T(0);
+  for (int l = 0; l < nz; ++l) {
+    T w[N1C];
+#pragma unroll
+    for (int c = 0; c < N1C; ++c) w[c] = T(0);
+    if (own) {
+      const int kmax = (l == nz - 1) ? N1F : PF;
+#pragma unroll
+      for (int k = 0; k < N1F; ++k) {
+        if (k < kmax) {
+          const T r = rf[(int64_t)(l * PF + k) * ns_f + hn];
+#pragma unroll
+          for (int c = 0; c < N1C; ++c) w[c] += ip<T>(PF, k * N1C + c) * r;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < N1C; ++c) W[c * NHF + t] = w[c];
+    __syncthreads();
+    if (cthr) {
+      T out[N1C];
+#pragma unroll
+      for (int c = 0; c < N1C; ++c) {
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < (DIM == 3 ? N1F : 1); ++j) {
+          T inner = T(0);
+#pragma unroll
+          for (int i = 0; i < N1F; ++i) inner += ip<T>(PF, i * N1C + a) * W[c * NHF + j * N1F + i];
+          acc += (DIM == 3 ? ip<T>(PF, j * N1C + b) : T(1)) * inner;
+        }
+        out[c] = acc;
+      }
+      out[0] += carry;
+      const int kend = (l == nz - 1) ? N1C : PC;
+#pragma unroll
+      for (int c = 0; c < N1C; ++c) {
+        if (c < kend) {
+          const int v = l * PC + c;
+          if (flc & kOwned)
+            bc[(int64_t)v * ns_c + hnc] = (v == vtop) ? T(0) : out[c];
+          else if (v != vtop)
+            Fc[(int64_t)v * nslots_c + slc] = out[c];
+        }
+      }
+      carry = out[PC];
+    }
+    __syncthreads();
+  }
+}
+
+// Prolongation x_f += P x_c, written by the owner column of each fine node.
+template <int PF, int DIM, typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(const T *__restrict__ xc, T *__restrict__ xf,
+                                                     const int32_t *__restrict__ nodes_f,
+                                                     const uint8_t *__restrict__ flags_f,
+                                                     const int32_t *__restrict__ nodes_c, int ncols, int nz,
+                                                     int64_t ns_f, int64_t ns_c, const int32_t *__restrict__ skip) {
+  using LF = Lay<PF, DIM>;
+  constexpr int PC = PF / 2, N1F = PF + 1, N1C = PC + 1;
+  constexpr int NHF = LF::NH, CPB = LF::CPB, NHC = Lay<PC, DIM>::NH;
+  __shared__ T sX[CPB * N1C * NHC];
+  if (skip != nullptr && *skip) return;
+  const int lc = threadIdx.x / NHF;
+  const int t = threadIdx.x - lc * NHF;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? ci : 0;
+  const int hn = active ? nodes_f[col * NHF + t] : 0;
+  const bool own = active && (flags_f[col * NHF + t] & kOwned);
+  const bool cthr = active && t < NHC;
+  const int hnc = cthr ? nodes_c[col * NHC + t] : 0;
+  const int i = t % N1F, j = DIM == 3 ? t / N1F : 0;
+  T *X = sX + lc * N1C * NHC;
+  for (int l = 0; l < nz; ++l) {
+    if (cthr) {
+#pragma unroll
+      for (int c = 0; c < N1C; ++c) X[c * NHC + t] = xc[(int64_t)(l * PC + c) * ns_c + hnc];
+    }
+    __syncthreads();
+    if (own) {
+      T w[N1C];
+#pragma unroll
+      for (int c = 0; c < N1C; ++c) {
+        T acc = T(0);
+#pragma unroll
+        for (int b = 0; b < (DIM == 3 ? N1C : 1); ++b) {
+          T inner = T(0);
+#pragma unroll
+          for (int a = 0; a < N1C; ++a) inner += ip<T>(PF, i * N1C + a) * X[c * NHC + b * N1C + a];
+          acc += (DIM == 3 ? ip<T>(PF, j * N1C + b) : T(1)) * inner;
+        }
+        w[c] = acc;
+      }
+      const int kend = (l == nz - 1) ? N1F : PF;
+#pragma unroll
+      for (int k = 0; k < N1F; ++k) {
+        if (k < kend) {
+          T u = T(0);
+#pragma unroll
+          for (int c = 0; c < N1C; ++c) u += ip<T>(PF, k * N1C + c) * w[c];
+          xf[(int64_t)(l * PF + k) * ns_f + hn] += u;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- vector kernels (grid-stride, fixed grid, deterministic partials) -----------------------
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NS>
+__device__ __forceinline__ void block_partials(double (&v)[NS], double *partial) {
+  constexpr int NW = kVecThreads / 64;
+  __shared__ double s[NS][NW];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double r = wsum(v[k]);
+    if (lane == 0) s[k][wv] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      double a = 0.0;
+      for (int w = 0; w < NW; ++w) a += s[k][w];
+      partial[blockIdx.x * NS + k] = a;
+    }
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ void final_sums(const double *partial, int np, double (&out)[NS]) {
+  __shared__ double s[NS][kVecThreads];
+  double a[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) a[k] = 0.0;
+  for (int b = threadIdx.x; b < np; b += kVecThreads)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) a[k] += partial[b * NS + k];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int w = kVecThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < NS; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) out[k] = s[k][0];
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// first Chebyshev step from x = 0: r = b, d = c dinv b, x = d
+template <typename T>
+__global__ void k_cheb0(const T *b, T *r, T *d, T *x, const T *dinv, T c, int64_t n, const int32_t *skip) {
+  if (skip != nullptr && *skip) return;
+  GRID_STRIDE(i, n) {
+    const T bi = b[i];
+    const T di = c * dinv[i] * bi;
+    r[i] = bi;
+    d[i] = di;
+    x[i] = di;
+  }
+}
+
+// first Chebyshev step from x: r = b - q (q = A x), d = c dinv r, x += d
+template <typename T>
+__global__ void k_cheb1(const T *b, const T *q, T *r, T *d, T *x, const T *dinv, T c, int64_t n,
+                        const int32_t *skip) {
+  if (skip != nullptr && *skip) return;
+  GRID_STRIDE(i, n) {
+    const T ri = b[i] - q[i];
+    const T di = c * dinv[i] * ri;
+    r[i] = ri;
+    d[i] = di;
+    x[i] += di;
+  }
+}
+
+// later steps: r -= q (q = A d), d = c1 d + c2 dinv r, x += d
+template <typename T>
+__global__ void k_cheb_step(T *r, const T *q, T *d, T *x, const T *dinv, T c1, T c2, int64_t n,
+                            const int32_t *skip) {
+  if (skip != nullptr && *skip) return;
+  GRID_STRIDE(i, n) {
+    const T ri = r[i] - q[i];
+    const T di = c1 * d[i] + c2 * dinv[i] * ri;
+    r[i] = ri;
+    d[i] = di;
+    x[i] += di;
+  }
+}
+
+template <typename T>
+__global__ void k_sub(T *r, const T *q, int64_t n, const int32_t *skip) {
+  if (skip != nullptr && *skip) return;
+  GRID_STRIDE(i, n) r[i] -= q[i];
+}
+
+// PCG with a general preconditioner: x += alpha p, r -= alpha q; partial r.r
+template <typename T, typename TX>
+__global__ __launch_bounds__(kVecThreads) void k_mg_update(TX *x, T *r, const T *p, const T *q, int64_t n,
+                                                           double *partial, const PcgScalars *sc) {
+  if (sc->done) return;
+  const T a = (T)sc->alpha;
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    v[0] += (double)ri * (double)ri;
+  }
+  block_partials<1>(v, partial);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_mg_fin_rr(const double *partial, int np, PcgScalars *sc) {
+  if (sc->done) return;
+  double s[1];
+  final_sums<1>(partial, np, s);
+  if (threadIdx.x == 0) {
+    sc->rr = s[0];
+    sc->iters += 1;
+    if (!(s[0] == s[0]) || !(s[0] <= 1e300)) {
+      sc->breakdown = 2;
+      sc->done = 1;
+    } else if (s[0] <= sc->tol2) {
+      sc->done = 1;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_dot(const T *a, const T *b, int64_t n, double *partial,
+                                                     const PcgScalars *sc) {
+  if (sc->done) return;
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) v[0] += (double)a[i] * (double)b[i];
+  block_partials<1>(v, partial);
+}
+
+// beta = (r.z)_new / (r.z)_old (first: beta = 0); a non-positive r.z means the preconditioner
+// is not positive definite on this residual
+__global__ __launch_bounds__(kVecThreads) void k_mg_fin_rz(const double *partial, int np, PcgScalars *sc,
+                                                           int first) {
+  if (sc->done) return;
+  double s[1];
+  final_sums<1>(partial, np, s);
+  if (threadIdx.x == 0) {
+    sc->beta = first ? 0.0 : s[0] / sc->rz;
+    sc->rz = s[0];
+    if (!(s[0] > 0.0) || !(s[0] <= 1e300)) {
+      sc->breakdown = (s[0] == s[0]) ? 1 : 2;
+      sc->done = 1;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_mg_dir(T *p, const T *z, int64_t n, const PcgScalars *sc, int first) {
+  if (sc->done) return;
+  const T b = (T)sc->beta;
+  GRID_STRIDE(i, n) p[i] = first ? z[i] : z[i] + b * p[i];
+}
+
+// power iteration on D^-1 A: pw[0] = (v.Av)/(v.Dv) (Rayleigh quotient), pw[1] = 1/sqrt(v.Dv)
+template <typename T>
+__global__ void k_pow_start(T *v, const T *dinv, int64_t n) {
+  GRID_STRIDE(i, n) v[i] = dinv[i] != T(0) ? T(1.0 + 0.5 * sin(0.7 * (double)i) + 0.25 * cos(0.013 * (double)i)) : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_pow_dots(const T *v, const T *q, const T *dinv, int64_t n,
+                                                          double *partial) {
+  double s[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double vi = (double)v[i];
+    s[0] += vi * (double)q[i];
+    if (dinv[i] != T(0)) s[1] += vi * vi / (double)dinv[i];
+  }
+  block_partials<2>(s, partial);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_pow_fin(const double *partial, int np, double *pw) {
+  double s[2];
+  final_sums<2>(partial, np, s);
+  if (threadIdx.x == 0) {
+    pw[0] = s[1] > 0.0 ? s[0] / s[1] : 0.0;
+    pw[1] = s[1] > 0.0 ? 1.0 / sqrt(s[1]) : 1.0;
+  }
+}
+
+template <typename T>
+__global__ void k_pow_next(T *v, const T *q, const T *dinv, int64_t n, const double *pw) {
+  const T sc = (T)pw[1];
+  GRID_STRIDE(i, n) v[i] = dinv[i] * q[i] * sc;
+}
+
+// ---- host side --------------------------------------------------------------------------------
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+  static constexpr fnpf_dtype dt = FNPF_F64;
+  static double *const *lv(MgLevel &L) { return L.v64; }
+  static double *const *fv(Ctx &c) { return c.mg_f64; }
+  static const double *dinv(Ctx &c) { return c.d_dinv; }
+  static double &lam(MgLevel &L) { return L.lam64; }
+  static double &lamf(Ctx &c) { return c.lam64; }
+  static bool &stale(Ctx &c) { return c.mg_stale64; }
+  static double *&ev(MgLevel &L) { return L.ev64; }
+  static double *&evf(Ctx &c) { return c.mg_ev64; }
+  static bool &evok(MgLevel &L) { return L.ev_ok64; }
+  static bool &evokf(Ctx &c) { return c.mg_ev_ok64; }
+};
+template <>
+struct Prec<float> {
+  static constexpr fnpf_dtype dt = FNPF_F32;
+  static float *const *lv(MgLevel &L) { return L.v32; }
+  static float *const *fv(Ctx &c) { return c.mg_f32; }
+  static const float *dinv(Ctx &c) { return c.d_dinv32; }
+  static double &lam(MgLevel &L) { return L.lam32; }
+  static double &lamf(Ctx &c) { return c.lam32; }
+  static bool &stale(Ctx &c) { return c.mg_stale32; }
+  static float *&ev(MgLevel &L) { return L.ev32; }
+  static float *&evf(Ctx &c) { return c.mg_ev32; }
+  static bool &evok(MgLevel &L) { return L.ev_ok32; }
+  static bool &evokf(Ctx &c) { return c.mg_ev_ok32; }
+};
+
+template <typename T>
+hipError_t dalloc_t(T **p, size_t n) {
+  return hipMalloc((void **)p, n * sizeof(T));
+}
+
+#define MG_DISPATCH(DIMV, PV, CALL)                    \
+  switch (PV) {                                        \
+    case 2: { constexpr int PF_ = 2; CALL; } break;    \
+    case 3: { constexpr int PF_ = 3; CALL; } break;    \
+    case 4: { constexpr int PF_ = 4; CALL; } break;    \
+    case 5: { constexpr int PF_ = 5; CALL; } break;    \
+    case 6: { constexpr int PF_ = 6; CALL; } break;    \
+    case 7: { constexpr int PF_ = 7; CALL; } break;    \
+    case 8: { constexpr int PF_ = 8; CALL; } break;    \
+    default: return hipErrorInvalidValue;              \
+  }
+
+template <int PF, int DIM, typename T>
+hipError_t restrict_impl(Ctx &F, Ctx &C, const T *rf, T *bc, T *Fc, const int32_t *skip, hipStream_t s) {
+  using LF = Lay<PF, DIM>;
+  const int nb = (F.n_eh + LF::CPB - 1) / LF::CPB;
+  k_restrict<PF, DIM, T><<<nb, LF::NT, 0, s>>>(rf, bc, Fc, F.d_eh_nodes, F.d_flags, C.d_eh_nodes, C.d_flags,
+                                               C.d_slot, F.n_eh, F.nz, F.n_s, C.n_s, C.n_slots, skip);
+  return hipGetLastError();
+}
+
+template <int PF, int DIM, typename T>
+hipError_t prolong_impl(Ctx &F, Ctx &C, const T *xc, T *xf, const int32_t *skip, hipStream_t s) {
+  using LF = Lay<PF, DIM>;
+  const int nb = (F.n_eh + LF::CPB - 1) / LF::CPB;
+  k_prolong_add<PF, DIM, T><<<nb, LF::NT, 0, s>>>(xc, xf, F.d_eh_nodes, F.d_flags, C.d_eh_nodes, F.n_eh, F.nz,
+                                                  F.n_s, C.n_s, skip);
+  return hipGetLastError();
+}
+
+template <int PF, int DIM>
+hipError_t surf_impl(Ctx &F, Ctx &C, double *Hc, double *hc, hipStream_t s) {
+  constexpr int NHC = Lay<PF / 2, DIM>::NH;
+  const int64_t nthr = (int64_t)F.n_eh * NHC;
+  k_mg_surf<PF, DIM><<<(unsigned)((nthr + 255) / 256), 256, 0, s>>>(F.d_geoH, F.d_geoh, F.d_eh_nodes, C.d_eh_nodes,
+                                                                     C.d_flags, F.n_eh, Hc, hc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t restrict_to(Ctx &F, Ctx &C, const T *rf, T *bc, const int32_t *skip, hipStream_t s) {
+  T *Fc = nullptr;
+  if constexpr (sizeof(T) == 8) Fc = (T *)C.d_F64; else Fc = (T *)C.d_F32;
+  if (F.dim == 3) {
+    MG_DISPATCH(3, F.p, { hipError_t e = (restrict_impl<PF_, 3, T>(F, C, rf, bc, Fc, skip, s)); if (e != hipSuccess) return e; });
+  } else {
+    MG_DISPATCH(2, F.p, { hipError_t e = (restrict_impl<PF_, 2, T>(F, C, rf, bc, Fc, skip, s)); if (e != hipSuccess) return e; });
+  }
+  return launch_faces(C, Prec<T>::dt, bc, true, s, skip);
+}
+
+template <typename T>
+hipError_t prolong_to(Ctx &F, Ctx &C, const T *xc, T *xf, const int32_t *skip, hipStream_t s) {
+  if (F.dim == 3) {
+    MG_DISPATCH(3, F.p, return (prolong_impl<PF_, 3, T>(F, C, xc, xf, skip, s)));
+  } else {
+    MG_DISPATCH(2, F.p, return (prolong_impl<PF_, 2, T>(F, C, xc, xf, skip, s)));
+  }
+  return hipSuccess;
+}
+
+hipError_t surf_to(Ctx &F, Ctx &C, double *Hc, double *hc, hipStream_t s) {
+  if (F.dim == 3) {
+    MG_DISPATCH(3, F.p, return (surf_impl<PF_, 3>(F, C, Hc, hc, s)));
+  } else {
+    MG_DISPATCH(2, F.p, return (surf_impl<PF_, 2>(F, C, Hc, hc, s)));
+  }
+  return hipSuccess;
+}
+
+// Chebyshev smoothing of A x = b on level L (D^-1 A spectrum estimate lam), m steps.  From zero:
+// x = p(D^-1 A) D^-1 b; otherwise x += p(D^-1 A) D^-1 (b - A x).  On return r = b - A x_{m-1}
+// and d = x_m - x_{m-1}.
+template <typename T>
+hipError_t smooth(Ctx &L, const T *b, T *x, T *r, T *d, T *q, double lam, int m, double ratio, bool from_zero,
+                  const int32_t *skip, hipStream_t s) {
+  const double lmax = kMgSafety * lam, lmin = lmax / ratio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho0 = 1.0 / sigma;
+  const T *dinv = Prec<T>::dinv(L);
+  const int64_t n = L.n_v;
+  if (from_zero) {
+    k_cheb0<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, r, d, x, dinv, (T)(1.0 / theta), n, skip);
+  } else {
+    hipError_t e = launch_apply(L, Prec<T>::dt, x, q, true, nullptr, skip, s);
+    if (e != hipSuccess) return e;
+    k_cheb1<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, q, r, d, x, dinv, (T)(1.0 / theta), n, skip);
+  }
+  for (int k = 2; k <= m; ++k) {
+    hipError_t e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s);
+    if (e != hipSuccess) return e;
+    const double rho1 = 1.0 / (2.0 * sigma - rho0);
+    k_cheb_step<T><<<kVecBlocks, kVecThreads, 0, s>>>(r, q, d, x, dinv, (T)(rho1 * rho0), (T)(2.0 * rho1 / delta), n,
+                                                      skip);
+    rho0 = rho1;
+  }
+  return hipGetLastError();
+}
+
+// V-cycle on level l (0 = this context) for the right-hand side b, result in x.
+template <typename T>
+hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, hipStream_t s) {
+  Ctx &L = l == 0 ? c : *c.mg[l - 1].c;
+  T *r, *d, *q;
+  double lam;
+  if (l == 0) {
+    r = Prec<T>::fv(c)[1];
+    d = Prec<T>::fv(c)[2];
+    q = Prec<T>::fv(c)[3];
+    lam = Prec<T>::lamf(c);
+  } else {
+    r = Prec<T>::lv(c.mg[l - 1])[2];
+    d = Prec<T>::lv(c.mg[l - 1])[3];
+    q = Prec<T>::lv(c.mg[l - 1])[4];
+    lam = Prec<T>::lam(c.mg[l - 1]);
+  }
+  const int last = (int)c.mg.size();
+  if (l == last) return smooth<T>(L, b, x, r, d, q, lam, kMgCoarseSteps, kMgCoarseRatio, true, skip, s);
+  hipError_t e = smooth<T>(L, b, x, r, d, q, lam, m, kMgSmoothRatio, true, skip, s);
+  if (e != hipSuccess) return e;
+  // residual of the smoothed x: r - A d
+  e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s);
+  if (e != hipSuccess) return e;
+  k_sub<T><<<kVecBlocks, kVecThreads, 0, s>>>(r, q, L.n_v, skip);
+  MgLevel &C = c.mg[l];
+  T *bc = Prec<T>::lv(C)[0], *xc = Prec<T>::lv(C)[1];
+  e = restrict_to<T>(L, *C.c, r, bc, skip, s);
+  if (e != hipSuccess) return e;
+  e = vcycle<T>(c, l + 1, bc, xc, skip, m, s);
+  if (e != hipSuccess) return e;
+  e = prolong_to<T>(L, *C.c, xc, x, skip, s);
+  if (e != hipSuccess) return e;
+  return smooth<T>(L, b, x, r, d, q, lam, m, kMgSmoothRatio, false, skip, s);
+}
+
+// Rayleigh-quotient power iteration for the largest eigenvalue of D^-1 A on level L.  v holds the
+// previous top eigenvector estimate when warm.
+template <typename T>
+hipError_t estimate_lambda(Ctx &c, Ctx &L, T *v, T *q, bool warm, double &lam, hipStream_t s) {
+  const T *dinv = Prec<T>::dinv(L);
+  const int64_t n = L.n_v;
+  if (!warm) k_pow_start<T><<<kVecBlocks, kVecThreads, 0, s>>>(v, dinv, n);
+  const int its = warm ? kPowNext : kPowFirst;
+  double *pw = c.d_partial + c.n_partial - 4;   // two scalars past the partials the dots use
+  for (int it = 0; it < its; ++it) {
+    hipError_t e = launch_apply(L, Prec<T>::dt, v, q, true, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
+    k_pow_dots<T><<<kVecBlocks, kVecThreads, 0, s>>>(v, q, dinv, n, c.d_partial);
+    k_pow_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, pw);
+    k_pow_next<T><<<kVecBlocks, kVecThreads, 0, s>>>(v, q, dinv, n, pw);
+  }
+  double h[2];
+  hipError_t e = hipMemcpyAsync(h, pw, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  lam = h[0];
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Builds the coarse levels (contexts at degrees p/2, p/4, ..., 1) and their work vectors.
+fnpf_status mg_build(Ctx &c) {
+  if (c.mg_built) return FNPF_OK;
+  static bool uploaded[64] = {false};
+  if (c.device >= 0 && c.device < 64 && !uploaded[c.device]) {
+    if (upload_tables() != hipSuccess) return FNPF_ERR_HIP;
+    uploaded[c.device] = true;
+  }
+  Ctx *F = &c;
+  while (F->p > 1) {
+    const int pc = F->p / 2;
+    std::vector<int32_t> nodes;
+    int64_t ns = 0;
+    std::string err = coarse_numbering(*F, pc, nodes, ns);
+    if (!err.empty()) {
+      c.err = "p-multigrid: " + err;
+      return FNPF_ERR_ARG;
+    }
+    fnpf_mesh_desc d{};
+    d.dim = F->dim;
+    d.p = pc;
+    d.nz = F->nz;
+    d.n_eh = F->n_eh;
+    d.n_s = ns;
+    d.eh_nodes = nodes.data();
+    d.eh_corner = F->h_corner.data();
+    d.eh_arc = F->h_arc.empty() ? nullptr : F->h_arc.data();
+    d.eh_face_tag = F->h_tags.data();
+    d.layer_s = F->h_layer_s.data();
+    d.g = F->g;
+    MgLevel L;
+    fnpf_status st = fnpf_create(&d, &L.child);
+    if (st != FNPF_OK) {
+      c.err = std::string("p-multigrid: coarse level: ") + fnpf_last_error(nullptr);
+      return st;
+    }
+    L.c = &ctx_of(L.child);
+    if (dalloc_t(&L.Hc, L.c->n_s) != hipSuccess || dalloc_t(&L.hc, L.c->n_s) != hipSuccess) {
+      c.mg.push_back(L);
+      return FNPF_ERR_ALLOC;
+    }
+    c.mg.push_back(L);
+    F = c.mg.back().c;
+  }
+  c.mg_built = true;
+  c.mg_stale64 = c.mg_stale32 = true;
+  return FNPF_OK;
+}
+
+void mg_free(Ctx &c) {
+  for (auto &L : c.mg) {
+    if (L.Hc) (void)hipFree(L.Hc);
+    if (L.hc) (void)hipFree(L.hc);
+    for (int k = 0; k < 5; ++k) {
+      if (L.v64[k]) (void)hipFree(L.v64[k]);
+      if (L.v32[k]) (void)hipFree(L.v32[k]);
+    }
+    if (L.ev64) (void)hipFree(L.ev64);
+    if (L.ev32) (void)hipFree(L.ev32);
+    if (L.child) fnpf_destroy(L.child);
+  }
+  c.mg.clear();
+  for (int k = 0; k < 4; ++k) {
+    if (c.mg_f64[k]) (void)hipFree(c.mg_f64[k]);
+    if (c.mg_f32[k]) (void)hipFree(c.mg_f32[k]);
+    c.mg_f64[k] = nullptr;
+    c.mg_f32[k] = nullptr;
+  }
+  if (c.mg_ev64) (void)hipFree(c.mg_ev64);
+  if (c.mg_ev32) (void)hipFree(c.mg_ev32);
+  c.mg_ev64 = nullptr;
+  c.mg_ev32 = nullptr;
+  c.mg_ev_ok64 = c.mg_ev_ok32 = false;
+  c.mg_built = false;
+}
+
+// Brings the coarse levels up to the current geometry (and FP32 data when T is float) and
+// re-estimates the smoothing intervals.  The work vectors of precision T are allocated here.
+template <typename T>
+fnpf_status mg_refresh(Ctx &c, hipStream_t s) {
+  fnpf_status st = mg_build(c);
+  if (st != FNPF_OK) return st;
+  const bool fresh = Prec<T>::fv(c)[0] == nullptr;
+  if (fresh) {
+    T **fv = const_cast<T **>(Prec<T>::fv(c));
+    for (int k = 0; k < 4; ++k)
+      if (dalloc_t(&fv[k], c.n_v) != hipSuccess) return FNPF_ERR_ALLOC;
+    if (dalloc_t(&Prec<T>::evf(c), c.n_v) != hipSuccess) return FNPF_ERR_ALLOC;
+    for (auto &L : c.mg) {
+      T **lv = const_cast<T **>(Prec<T>::lv(L));
+      for (int k = 0; k < 5; ++k)
+        if (dalloc_t(&lv[k], L.c->n_v) != hipSuccess) return FNPF_ERR_ALLOC;
+      if (dalloc_t(&Prec<T>::ev(L), L.c->n_v) != hipSuccess) return FNPF_ERR_ALLOC;
+      if (sizeof(T) == 4 && ctx_ensure32(*L.c) != FNPF_OK) return FNPF_ERR_ALLOC;
+    }
+  }
+  if (!Prec<T>::stale(c)) return FNPF_OK;
+  Ctx *F = &c;
+  for (auto &L : c.mg) {
+    if (surf_to(*F, *L.c, L.Hc, L.hc, s) != hipSuccess) return FNPF_ERR_HIP;
+    st = geom_impl_total(*L.c, L.Hc, L.hc, s);
+    if (st != FNPF_OK) return st;
+    F = L.c;
+  }
+  // eigenvalue estimates, warm-started from the previous geometry's eigenvector estimates
+  {
+    double lam = 0.0;
+    if (estimate_lambda<T>(c, c, Prec<T>::evf(c), Prec<T>::fv(c)[3], Prec<T>::evokf(c), lam, s) != hipSuccess)
+      return FNPF_ERR_HIP;
+    Prec<T>::lamf(c) = lam;
+    Prec<T>::evokf(c) = true;
+    for (auto &L : c.mg) {
+      if (estimate_lambda<T>(c, *L.c, Prec<T>::ev(L), Prec<T>::lv(L)[4], Prec<T>::evok(L), lam, s) != hipSuccess)
+        return FNPF_ERR_HIP;
+      Prec<T>::lam(L) = lam;
+      Prec<T>::evok(L) = true;
+    }
+  }
+  if (!(Prec<T>::lamf(c) > 0.0)) return FNPF_ERR_NAN;
+  Prec<T>::stale(c) = false;
+  return FNPF_OK;
+}
+template fnpf_status mg_refresh<double>(Ctx &, hipStream_t);
+template fnpf_status mg_refresh<float>(Ctx &, hipStream_t);
+
+template <typename T>
+hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth_deg, hipStream_t s) {
+  return vcycle<T>(c, 0, r, z, skip, smooth_deg, s);
+}
+template hipError_t mg_vcycle<double>(Ctx &, const double *, double *, const int32_t *, int, hipStream_t);
+template hipError_t mg_vcycle<float>(Ctx &, const float *, float *, const int32_t *, int, hipStream_t);
+
+hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void *p, const void *q, double *partial,
+                            PcgScalars *sc, hipStream_t s) {
+  if (dt == FNPF_F64)
+    k_mg_update<double, double><<<kVecBlocks, kVecThreads, 0, s>>>((double *)x, (double *)r, (const double *)p,
+                                                                    (const double *)q, c.n_v, partial, sc);
+  else
+    k_mg_update<float, float><<<kVecBlocks, kVecThreads, 0, s>>>((float *)x, (float *)r, (const float *)p,
+                                                                  (const float *)q, c.n_v, partial, sc);
+  k_mg_fin_rr<<<1, kVecThreads, 0, s>>>(partial, kVecBlocks, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_mg_dot_dir(Ctx &c, fnpf_dtype dt, const void *r, const void *z, void *p, double *partial,
+                             PcgScalars *sc, int first, hipStream_t s) {
+  if (dt == FNPF_F64)
+    k_dot<double><<<kVecBlocks, kVecThreads, 0, s>>>((const double *)r, (const double *)z, c.n_v, partial, sc);
+  else
+    k_dot<float><<<kVecBlocks, kVecThreads, 0, s>>>((const float *)r, (const float *)z, c.n_v, partial, sc);
+  k_mg_fin_rz<<<1, kVecThreads, 0, s>>>(partial, kVecBlocks, sc, first);
+  if (dt == FNPF_F64)
+    k_mg_dir<double><<<kVecBlocks, kVecThreads, 0, s>>>((double *)p, (const double *)z, c.n_v, sc, first);
+  else
+    k_mg_dir<float><<<kVecBlocks, kVecThreads, 0, s>>>((float *)p, (const float *)z, c.n_v, sc, first);
+  return hipGetLastError();
+}
+
+}  // namespace fnpf

@@ -13,6 +13,8 @@
 // J_h is obtained by applying D to the nodal coordinates (isoparametric).
 
 #include <algorithm>
+#include <map>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -129,6 +131,14 @@ std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double>
 
   // node ids
   c.h_eh_nodes.assign(m.eh_nodes, m.eh_nodes + n_eh * nh);
+  c.h_corner.assign(m.eh_corner, m.eh_corner + n_eh * (dim == 3 ? 8 : 2));
+  if (m.eh_arc && dim == 3)
+    c.h_arc.assign(m.eh_arc, m.eh_arc + n_eh * 12);
+  else
+    c.h_arc.clear();
+  c.h_tags.assign((size_t)n_eh * 2 * (dim - 1), 0);
+  if (m.eh_face_tag)
+    for (size_t k = 0; k < c.h_tags.size(); ++k) c.h_tags[k] = m.eh_face_tag[k];
   std::vector<int32_t> count(n_s, 0);
   for (int64_t e = 0; e < n_eh; ++e) {
     for (int t = 0; t < nh; ++t) {
@@ -353,6 +363,69 @@ std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double>
     }
     c.n_ps = (int)c.h_ps_node.size();
   }
+  return "";
+}
+
+
+// Numbering of the same horizontal elements at degree pc < p (levels of the p-multigrid
+// preconditioner).  It follows the topology of the fine numbering: a vertex is identified by its
+// fine id, an edge node by the edge's two fine nodes next to its ends (their smaller id fixes a
+// direction along the edge, so both elements of an edge agree) and its position, an interior
+// node by its element.  Ids are column-blocked: each node belongs to the lowest-numbered column
+// that has it; column by column, shared nodes first, then interior ones.
+std::string coarse_numbering(const Ctx &f, int pc, std::vector<int32_t> &nodes, int64_t &n_s) {
+  const int pf = f.p, n1f = pf + 1, n1c = pc + 1;
+  const int dim = f.dim;
+  const int nhf = dim == 3 ? n1f * n1f : n1f, nhc = dim == 3 ? n1c * n1c : n1c;
+  if (pc < 1 || pc >= pf) return "coarse degree must lie in [1, p)";
+  if (pc >= 2 && pf < 3) return "edge nodes of the coarse level need p >= 3";
+  const int64_t n_eh = f.n_eh;
+  auto fid = [&](int64_t e, int i, int j) -> int64_t { return f.h_eh_nodes[e * nhf + j * n1f + i]; };
+  std::vector<std::array<int64_t, 3>> keys((size_t)n_eh * nhc);
+  for (int64_t e = 0; e < n_eh; ++e) {
+    for (int t = 0; t < nhc; ++t) {
+      const int ic = t % n1c, jc = dim == 3 ? t / n1c : 0;
+      const bool bi = ic == 0 || ic == pc, bj = dim == 2 || jc == 0 || jc == pc;
+      std::array<int64_t, 3> k{};
+      if (dim == 2) {
+        k = bi ? std::array<int64_t, 3>{0, fid(e, ic == 0 ? 0 : pf, 0), 0} : std::array<int64_t, 3>{2, e, t};
+      } else if (bi && bj) {
+        k = {0, fid(e, ic == 0 ? 0 : pf, jc == 0 ? 0 : pf), 0};
+      } else if (bi) {   // edge at xi = -1 or +1, position jc along eta
+        const int i = ic == 0 ? 0 : pf;
+        const int64_t a = fid(e, i, 1), b = fid(e, i, pf - 1);
+        k = a < b ? std::array<int64_t, 3>{1, a, jc} : std::array<int64_t, 3>{1, b, pc - jc};
+      } else if (bj) {   // edge at eta = -1 or +1, position ic along xi
+        const int j = jc == 0 ? 0 : pf;
+        const int64_t a = fid(e, 1, j), b = fid(e, pf - 1, j);
+        k = a < b ? std::array<int64_t, 3>{1, a, ic} : std::array<int64_t, 3>{1, b, pc - ic};
+      } else {
+        k = {2, e, t};
+      }
+      keys[e * nhc + t] = k;
+    }
+  }
+  std::map<std::array<int64_t, 3>, std::array<int64_t, 3>> info;   // key -> {count, owner, id}
+  for (int64_t e = 0; e < n_eh; ++e)
+    for (int t = 0; t < nhc; ++t) {
+      auto it = info.find(keys[e * nhc + t]);
+      if (it == info.end())
+        info.emplace(keys[e * nhc + t], std::array<int64_t, 3>{1, e, -1});
+      else
+        it->second[0] += 1;
+    }
+  int64_t next = 0;
+  for (int64_t e = 0; e < n_eh; ++e)
+    for (int pass = 0; pass < 2; ++pass)
+      for (int t = 0; t < nhc; ++t) {
+        auto &v = info[keys[e * nhc + t]];
+        if (v[1] != e || v[2] >= 0) continue;
+        if ((pass == 0) != (v[0] > 1)) continue;
+        v[2] = next++;
+      }
+  n_s = next;
+  nodes.resize((size_t)n_eh * nhc);
+  for (size_t k = 0; k < nodes.size(); ++k) nodes[k] = (int32_t)info[keys[k]][2];
   return "";
 }
 

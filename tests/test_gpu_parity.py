@@ -222,14 +222,16 @@ def test_rk4_relaxation_parity():
     assert rel(host(e), eta) < 1e-10 and rel(host(p), phi) < 1e-10
 
 
-def test_c1_full_run():
-    """C1: 32 ERK4 steps (one period) of the standing wave; FP64 path vs the oracle."""
+@pytest.mark.parametrize("precond", [1, 2])
+def test_c1_full_run(precond):
+    """C1: 32 ERK4 steps (one period) of the standing wave; FP64 path vs the oracle (solves at
+    rtol 1e-13: 128 solves whose errors accumulate in the state)."""
     wl = configs.c1()
     pr = Pair(wl)
     md = ts.Model(wl, solver="dense")
     eo, po = md.run()
     e, p = pr.d_eta.clone(), pr.d_phis.clone()
-    opts = fnpf.default_opts(rtol=1e-12)
+    opts = fnpf.default_opts(rtol=1e-13, precond=precond)
     t = 0.0
     for n in range(wl.nsteps):
         pr.ctx.rk4_step(e, p, pr.d_h, t, wl.dt, opts=opts)
@@ -318,7 +320,9 @@ def test_error_paths():
     _, info = pr.ctx.solve(pr.d_phis, raise_on_error=False)
     assert info["status"] == "ERR_GEOM"
     with pytest.raises(fnpf.FnpfError):
-        pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precond=0))
+        pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precond=3))
+    with pytest.raises(fnpf.FnpfError):
+        pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precond=2, cheb_degree=0))
 
 
 def test_bitwise_repeatable():
@@ -328,3 +332,62 @@ def test_bitwise_repeatable():
     a, _ = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(rtol=1e-12, check_every=3))
     b, _ = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(rtol=1e-12, check_every=11))
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precond", [0, 2])
+@pytest.mark.parametrize("name", ["slice_walls", "box_mixed", "box_walls_p6", "cylinder", "cylinder_blocked"])
+def test_solve_preconditioners(name, precond):
+    """No preconditioner and the p-multigrid V-cycle reach the oracle's solution like Jacobi does."""
+    pr = Pair(_case(name), fp32=True)
+    pr.ctx.geom(pr.d_eta, pr.d_h)
+    Go, _, _ = pr.oracle_factors()
+    phio = sv.solve_dense(pr.m, op.assemble_dense(pr.m, Go), pr.phis)
+    phi, info = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(rtol=1e-13, check_every=5, precond=precond))
+    assert info["status"] == "OK" and info["rel_res"] <= 1e-13
+    assert rel(host(phi), phio) < 1e-10
+    _, info_j = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(rtol=1e-13, check_every=5, precond=1))
+    if precond == 2 and pr.m.p >= 3:
+        assert info["iters"] < info_j["iters"]
+    phim, infom = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precision=1, rtol=1e-11, inner_rtol=1e-3,
+                                                                  precond=precond))
+    assert infom["status"] == "OK"
+    assert rel(host(phim), phio) < 1e-8
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_rk4_step_multigrid(precision):
+    """ERK4 steps with the p-multigrid preconditioner (geometry refreshed every stage)."""
+    wl = _case("box_walls_p6")
+    pr = Pair(wl, fp32=precision == 1)
+    md = ts.Model(wl, solver="dense")
+    dt = 0.02
+    e1, p1 = md.rk4_step(pr.eta, pr.phis, 0.0, dt)
+    e2, p2 = md.rk4_step(e1, p1, dt, dt)
+    e, p = pr.d_eta.clone(), pr.d_phis.clone()
+    opts = fnpf.default_opts(precision=precision, rtol=1e-13 if precision == 0 else 1e-12, inner_rtol=1e-3,
+                             precond=2)
+    pr.ctx.rk4_step(e, p, pr.d_h, 0.0, dt, opts=opts)
+    infos = pr.ctx.rk4_step(e, p, pr.d_h, dt, dt, opts=opts)
+    tol = 1e-10 if precision == 0 else 1e-8
+    assert rel(host(e), e2) < tol and rel(host(p), p2) < tol
+    assert all(i["rel_res"] <= opts.rtol for i in infos)
+
+
+def test_multigrid_repeatable_and_c2():
+    """C2 full size: the multigrid solve is bitwise repeatable and satisfies the oracle's residual."""
+    wl = configs.c2()
+    pr = Pair(wl, fp32=True)
+    pr.ctx.geom(pr.d_eta, pr.d_h)
+    o = fnpf.default_opts(rtol=1e-10, precond=2, check_every=3)
+    a, ia = pr.ctx.solve(pr.d_phis, opts=o)
+    b, ib = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(rtol=1e-10, precond=2, check_every=7))
+    assert torch.equal(a, b) and ia["iters"] == ib["iters"]
+    _, ij = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(rtol=1e-10, precond=1))
+    assert ia["iters"] * 4 < ij["iters"]
+    Go, _, _ = pr.oracle_factors()
+    lift = np.zeros(pr.m.n_v)
+    lift[sv.surface_slice(pr.m)] = pr.phis
+    bvec = -op.apply(pr.m, Go, lift)
+    r = -op.apply(pr.m, Go, host(a))
+    I = sv.interior_mask(pr.m)
+    assert np.linalg.norm(r[I]) <= 1.05e-10 * np.linalg.norm(bvec[I])

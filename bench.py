@@ -372,7 +372,7 @@ def main():
         apply_ms=dict(f64=t64 * 1e3, f32=t32 * 1e3, f64_mean=t64_mean * 1e3, f32_mean=t32_mean * 1e3),
         s_per_rk4_step=dict(f64=t_f64, mixed=t_mixed, mixed_jacobi=t_jac),
         pcg_iters_per_stage=dict(f64=it_f64, mixed=it_mixed, mixed_jacobi=it_jac),
-        preconditioner="p-multigrid V-cycle (degrees 6, 3, 1; Chebyshev-Jacobi smoothing, degree 3)",
+        preconditioner="p-multigrid V-cycle (degrees 6, 3, 1; Chebyshev-Jacobi smoothing, degree 2)",
         adjoint_forward_ratio=None if adj is None else adj["ratio"],
         adjoint=adj,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,

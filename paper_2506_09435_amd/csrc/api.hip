@@ -409,7 +409,7 @@ void fnpf_default_opts(fnpf_solve_opts *o) {
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
   o->extrapolate = 1;
-  o->cheb_degree = 3;
+  o->cheb_degree = 2;
 }
 
 const char *fnpf_status_string(fnpf_status s) {

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -122,13 +123,16 @@ __global__ __launch_bounds__(256) void k_mg_surf(const double *__restrict__ Hf, 
   hc[n] = sh;
 }
 
-// Restriction b_c = P^T r_f.  One thread per (column, fine horizontal node); per layer, the fine
-// line (owner columns only; the shared layer level counts in the upper layer) is contracted
-// vertically in registers, then threads of coarse horizontal nodes contract horizontally from
-// LDS and assemble: coarse nodes owned by the column go to b_c, the others to the coarse face
-// slots (summed by the coarse level's face pass).  The coarse surface level is set to zero.
+// Restriction b_c = P^T (r_f - q_f) (q_f = NULL: P^T r_f).  One thread per (column, fine
+// horizontal node) loads its fine line (owner columns only; the shared layer level counts in the
+// upper layer) and contracts it vertically in registers; the horizontal contraction is split in
+// two LDS stages over all threads of the column: (a, j, c) sums over i, then (a, b, c) over j.
+// Coarse nodes owned by the column go to b_c, the others to the coarse face slots (summed by the
+// coarse level's face pass); the coarse surface level is set to zero.  The vertical carry of the
+// shared layer level passes through a double-buffered LDS slot per coarse horizontal node.
 template <int PF, int DIM, typename T>
-__global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, T *__restrict__ bc, T *__restrict__ Fc,
+__global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, const T *__restrict__ qf,
+                                                  T *__restrict__ bc, T *__restrict__ Fc,
                                                   const int32_t *__restrict__ nodes_f,
                                                   const uint8_t *__restrict__ flags_f,
                                                   const int32_t *__restrict__ nodes_c,
@@ -139,7 +143,12 @@ __global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, T *_
   using LF = Lay<PF, DIM>;
   constexpr int PC = PF / 2, N1F = PF + 1, N1C = PC + 1;
   constexpr int NHF = LF::NH, CPB = LF::CPB, NHC = Lay<PC, DIM>::NH;
+  constexpr int NJ = DIM == 3 ? N1F : 1;               // fine rows left after stage A
+  constexpr int NA = N1C * NJ * N1C;                   // stage A items (a, j, c)
+  constexpr int NB = NHC * N1C;                        // stage B items (a, b, c)
   __shared__ T sW[CPB * N1C * NHF];
+  __shared__ T sA[CPB * NA];
+  __shared__ T sC[CPB * 2 * NHC];
   if (skip != nullptr && *skip) return;
   const int lc = threadIdx.x / NHF;
   const int t = threadIdx.x - lc * NHF;
@@ -148,59 +157,65 @@ __global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, T *_
   const int col = active ? ci : 0;
   const int hn = active ? nodes_f[col * NHF + t] : 0;
   const bool own = active && (flags_f[col * NHF + t] & kOwned);
-  const bool cthr = active && t < NHC;
-  const int hnc = cthr ? nodes_c[col * NHC + t] : 0;
-  const uint8_t flc = cthr ? flags_c[col * NHC + t] : 0;
-  const int32_t slc = cthr ? slot_c[col * NHC + t] : 0;
-  const int a = t % N1C, b = DIM == 3 ? (t / N1C) % N1C : 0;
   T *W = sW + lc * N1C * NHF;
+  T *A = sA + lc * NA;
+  T *Cr = sC + lc * 2 * NHC;
   const int vtop = PC * nz;
-  T carry = T(0);
   for (int l = 0; l < nz; ++l) {
     T w[N1C];
 #pragma unroll
     for (int c = 0; c < N1C; ++c) w[c] = T(0);
     if (own) {
       const int kmax = (l == nz - 1) ? N1F : PF;
+      T rv[N1F];
 #pragma unroll
       for (int k = 0; k < N1F; ++k) {
-        if (k < kmax) {
-          const T r = rf[(int64_t)(l * PF + k) * ns_f + hn];
-#pragma unroll
-          for (int c = 0; c < N1C; ++c) w[c] += ip<T>(PF, k * N1C + c) * r;
-        }
+        const int64_t idx = (int64_t)(l * PF + k) * ns_f + hn;
+        rv[k] = k < kmax ? (qf ? rf[idx] - qf[idx] : rf[idx]) : T(0);
       }
+#pragma unroll
+      for (int k = 0; k < N1F; ++k)
+#pragma unroll
+        for (int c = 0; c < N1C; ++c) w[c] += ip<T>(PF, k * N1C + c) * rv[k];
     }
 #pragma unroll
     for (int c = 0; c < N1C; ++c) W[c * NHF + t] = w[c];
     __syncthreads();
-    if (cthr) {
-      T out[N1C];
-#pragma unroll
-      for (int c = 0; c < N1C; ++c) {
+    if constexpr (DIM == 3) {
+      // stage A: A[(c NJ + j) N1C + a] = sum_i IP[i][a] W[c][j][i]
+      for (int it = t; it < NA; it += NHF) {
+        const int a = it % N1C, j = (it / N1C) % NJ, c = it / (N1C * NJ);
         T acc = T(0);
 #pragma unroll
-        for (int j = 0; j < (DIM == 3 ? N1F : 1); ++j) {
-          T inner = T(0);
-#pragma unroll
-          for (int i = 0; i < N1F; ++i) inner += ip<T>(PF, i * N1C + a) * W[c * NHF + j * N1F + i];
-          acc += (DIM == 3 ? ip<T>(PF, j * N1C + b) : T(1)) * inner;
-        }
-        out[c] = acc;
+        for (int i = 0; i < N1F; ++i) acc += ip<T>(PF, i * N1C + a) * W[c * NHF + j * N1F + i];
+        A[it] = acc;
       }
-      out[0] += carry;
-      const int kend = (l == nz - 1) ? N1C : PC;
+      __syncthreads();
+    }
+    // stage B: coarse value (a, b, c) of this layer's element, assembled
+    for (int it = active ? t : NB; it < NB; it += NHF) {
+      const int h = it % NHC, c = it / NHC;            // h = b N1C + a
+      const int a = h % N1C, b = h / N1C;
+      T acc = T(0);
+      if constexpr (DIM == 3) {
 #pragma unroll
-      for (int c = 0; c < N1C; ++c) {
-        if (c < kend) {
-          const int v = l * PC + c;
-          if (flc & kOwned)
-            bc[(int64_t)v * ns_c + hnc] = (v == vtop) ? T(0) : out[c];
-          else if (v != vtop)
-            Fc[(int64_t)v * nslots_c + slc] = out[c];
-        }
+        for (int j = 0; j < N1F; ++j) acc += ip<T>(PF, j * N1C + b) * A[(c * NJ + j) * N1C + a];
+      } else {
+#pragma unroll
+        for (int i = 0; i < N1F; ++i) acc += ip<T>(PF, i * N1C + a) * W[c * NHF + i];
       }
-      carry = out[PC];
+      if (c == 0 && l > 0) acc += Cr[((l - 1) & 1) * NHC + h];
+      if (c == PC && l < nz - 1) {
+        Cr[(l & 1) * NHC + h] = acc;                   // the shared layer level, finished above
+        continue;
+      }
+      const int v = l * PC + c;
+      const int hnc = nodes_c[col * NHC + h];
+      const uint8_t flc = flags_c[col * NHC + h];
+      if (flc & kOwned)
+        bc[(int64_t)v * ns_c + hnc] = (v == vtop) ? T(0) : acc;
+      else if (v != vtop)
+        Fc[(int64_t)v * nslots_c + slot_c[col * NHC + h]] = acc;
     }
     __syncthreads();
   }
@@ -320,7 +335,8 @@ __device__ __forceinline__ void final_sums(const double *partial, int np, double
 
 // first Chebyshev step from x = 0: r = b, d = c dinv b, x = d
 template <typename T>
-__global__ void k_cheb0(const T *b, T *r, T *d, T *x, const T *dinv, T c, int64_t n, const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_cheb0(const T *b, T *r, T *d, T *x, const T *dinv, T c, int64_t n,
+                                                       const int32_t *skip) {
   if (skip != nullptr && *skip) return;
   GRID_STRIDE(i, n) {
     const T bi = b[i];
@@ -333,8 +349,8 @@ __global__ void k_cheb0(const T *b, T *r, T *d, T *x, const T *dinv, T c, int64_
 
 // first Chebyshev step from x: r = b - q (q = A x), d = c dinv r, x += d
 template <typename T>
-__global__ void k_cheb1(const T *b, const T *q, T *r, T *d, T *x, const T *dinv, T c, int64_t n,
-                        const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_cheb1(const T *b, const T *q, T *r, T *d, T *x, const T *dinv, T c,
+                                                       int64_t n, const int32_t *skip) {
   if (skip != nullptr && *skip) return;
   GRID_STRIDE(i, n) {
     const T ri = b[i] - q[i];
@@ -347,8 +363,8 @@ __global__ void k_cheb1(const T *b, const T *q, T *r, T *d, T *x, const T *dinv,
 
 // later steps: r -= q (q = A d), d = c1 d + c2 dinv r, x += d
 template <typename T>
-__global__ void k_cheb_step(T *r, const T *q, T *d, T *x, const T *dinv, T c1, T c2, int64_t n,
-                            const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_cheb_step(T *r, const T *q, T *d, T *x, const T *dinv, T c1, T c2,
+                                                           int64_t n, const int32_t *skip) {
   if (skip != nullptr && *skip) return;
   GRID_STRIDE(i, n) {
     const T ri = r[i] - q[i];
@@ -359,15 +375,44 @@ __global__ void k_cheb_step(T *r, const T *q, T *d, T *x, const T *dinv, T c1, T
   }
 }
 
+// Two-step smoothing written out (the default degree): with d1 = c0 D^-1 r0 and
+// d2 = c1 d1 + c2 D^-1 (r0 - A d1), x2 = x0 + (1 + c1) d1 + c2 D^-1 (r0 - A d1); only the
+// vectors each formula needs are read, and no residual or step vector survives it.
+//   y = c dinv b
 template <typename T>
-__global__ void k_sub(T *r, const T *q, int64_t n, const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_scale(T *y, const T *b, const T *dinv, T c, int64_t n,
+                                                       const int32_t *skip) {
   if (skip != nullptr && *skip) return;
-  GRID_STRIDE(i, n) r[i] -= q[i];
+  GRID_STRIDE(i, n) y[i] = c * dinv[i] * b[i];
+}
+
+//   from zero: x = a1 y + a2 dinv (b - q), y = d1, q = A d1
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_pre2(T *x, const T *y, const T *b, const T *q, const T *dinv, T a1,
+                                                      T a2, int64_t n, const int32_t *skip) {
+  if (skip != nullptr && *skip) return;
+  GRID_STRIDE(i, n) x[i] = a1 * y[i] + a2 * dinv[i] * (b[i] - q[i]);
+}
+
+//   from x: d1 = c dinv (b - q1), q1 = A x
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_post2a(T *d, const T *b, const T *q1, const T *dinv, T c, int64_t n,
+                                                        const int32_t *skip) {
+  if (skip != nullptr && *skip) return;
+  GRID_STRIDE(i, n) d[i] = c * dinv[i] * (b[i] - q1[i]);
+}
+
+//   x += a1 d1 + a2 dinv (b - q1 - q2), q2 = A d1
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_post2b(T *x, const T *d, const T *b, const T *q1, const T *q2,
+                                                        const T *dinv, T a1, T a2, int64_t n, const int32_t *skip) {
+  if (skip != nullptr && *skip) return;
+  GRID_STRIDE(i, n) x[i] += a1 * d[i] + a2 * dinv[i] * (b[i] - q1[i] - q2[i]);
 }
 
 // PCG with a general preconditioner: x += alpha p, r -= alpha q; partial r.r
-template <typename T, typename TX>
-__global__ __launch_bounds__(kVecThreads) void k_mg_update(TX *x, T *r, const T *p, const T *q, int64_t n,
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_mg_update(T *x, T *r, const T *p, const T *q, int64_t n,
                                                            double *partial, const PcgScalars *sc) {
   if (sc->done) return;
   const T a = (T)sc->alpha;
@@ -424,7 +469,8 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_fin_rz(const double *partial
 }
 
 template <typename T>
-__global__ void k_mg_dir(T *p, const T *z, int64_t n, const PcgScalars *sc, int first) {
+__global__ __launch_bounds__(kVecThreads) void k_mg_dir(T *p, const T *z, int64_t n, const PcgScalars *sc,
+                                                        int first) {
   if (sc->done) return;
   const T b = (T)sc->beta;
   GRID_STRIDE(i, n) p[i] = first ? z[i] : z[i] + b * p[i];
@@ -514,10 +560,11 @@ hipError_t dalloc_t(T **p, size_t n) {
   }
 
 template <int PF, int DIM, typename T>
-hipError_t restrict_impl(Ctx &F, Ctx &C, const T *rf, T *bc, T *Fc, const int32_t *skip, hipStream_t s) {
+hipError_t restrict_impl(Ctx &F, Ctx &C, const T *rf, const T *qf, T *bc, T *Fc, const int32_t *skip,
+                         hipStream_t s) {
   using LF = Lay<PF, DIM>;
   const int nb = (F.n_eh + LF::CPB - 1) / LF::CPB;
-  k_restrict<PF, DIM, T><<<nb, LF::NT, 0, s>>>(rf, bc, Fc, F.d_eh_nodes, F.d_flags, C.d_eh_nodes, C.d_flags,
+  k_restrict<PF, DIM, T><<<nb, LF::NT, 0, s>>>(rf, qf, bc, Fc, F.d_eh_nodes, F.d_flags, C.d_eh_nodes, C.d_flags,
                                                C.d_slot, F.n_eh, F.nz, F.n_s, C.n_s, C.n_slots, skip);
   return hipGetLastError();
 }
@@ -541,13 +588,13 @@ hipError_t surf_impl(Ctx &F, Ctx &C, double *Hc, double *hc, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t restrict_to(Ctx &F, Ctx &C, const T *rf, T *bc, const int32_t *skip, hipStream_t s) {
+hipError_t restrict_to(Ctx &F, Ctx &C, const T *rf, const T *qf, T *bc, const int32_t *skip, hipStream_t s) {
   T *Fc = nullptr;
   if constexpr (sizeof(T) == 8) Fc = (T *)C.d_F64; else Fc = (T *)C.d_F32;
   if (F.dim == 3) {
-    MG_DISPATCH(3, F.p, { hipError_t e = (restrict_impl<PF_, 3, T>(F, C, rf, bc, Fc, skip, s)); if (e != hipSuccess) return e; });
+    MG_DISPATCH(3, F.p, { hipError_t e = (restrict_impl<PF_, 3, T>(F, C, rf, qf, bc, Fc, skip, s)); if (e != hipSuccess) return e; });
   } else {
-    MG_DISPATCH(2, F.p, { hipError_t e = (restrict_impl<PF_, 2, T>(F, C, rf, bc, Fc, skip, s)); if (e != hipSuccess) return e; });
+    MG_DISPATCH(2, F.p, { hipError_t e = (restrict_impl<PF_, 2, T>(F, C, rf, qf, bc, Fc, skip, s)); if (e != hipSuccess) return e; });
   }
   return launch_faces(C, Prec<T>::dt, bc, true, s, skip);
 }
@@ -619,15 +666,36 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
   }
   const int last = (int)c.mg.size();
   if (l == last) return smooth<T>(L, b, x, r, d, q, lam, kMgCoarseSteps, kMgCoarseRatio, true, skip, s);
-  hipError_t e = smooth<T>(L, b, x, r, d, q, lam, m, kMgSmoothRatio, true, skip, s);
-  if (e != hipSuccess) return e;
-  // residual of the smoothed x: r - A d
-  e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s);
-  if (e != hipSuccess) return e;
-  k_sub<T><<<kVecBlocks, kVecThreads, 0, s>>>(r, q, L.n_v, skip);
   MgLevel &C = c.mg[l];
   T *bc = Prec<T>::lv(C)[0], *xc = Prec<T>::lv(C)[1];
-  e = restrict_to<T>(L, *C.c, r, bc, skip, s);
+  const int64_t n = L.n_v;
+  const T *dinv = Prec<T>::dinv(L);
+  hipError_t e = hipSuccess;
+  if (m == 2) {
+    // coefficients of the two Chebyshev steps on [lmax / ratio, lmax]
+    const double lmax = kMgSafety * lam, lmin = lmax / kMgSmoothRatio;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+    const T c0 = (T)(1.0 / theta), a1 = (T)(1.0 + rho1 * rho0), a2 = (T)(2.0 * rho1 / delta);
+    k_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, dinv, c0, n, skip);
+    if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
+    k_pre2<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, q, dinv, a1, a2, n, skip);
+    if ((e = launch_apply(L, Prec<T>::dt, x, q, true, nullptr, skip, s)) != hipSuccess) return e;
+    if ((e = restrict_to<T>(L, *C.c, b, q, bc, skip, s)) != hipSuccess) return e;   // P^T (b - A x)
+    if ((e = vcycle<T>(c, l + 1, bc, xc, skip, m, s)) != hipSuccess) return e;
+    if ((e = prolong_to<T>(L, *C.c, xc, x, skip, s)) != hipSuccess) return e;
+    if ((e = launch_apply(L, Prec<T>::dt, x, r, true, nullptr, skip, s)) != hipSuccess) return e;
+    k_post2a<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, r, dinv, c0, n, skip);
+    if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
+    k_post2b<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, r, q, dinv, a1, a2, n, skip);
+    return hipGetLastError();
+  }
+  e = smooth<T>(L, b, x, r, d, q, lam, m, kMgSmoothRatio, true, skip, s);
+  if (e != hipSuccess) return e;
+  // residual of the smoothed x, r - A d, restricted directly
+  e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s);
+  if (e != hipSuccess) return e;
+  e = restrict_to<T>(L, *C.c, r, q, bc, skip, s);
   if (e != hipSuccess) return e;
   e = vcycle<T>(c, l + 1, bc, xc, skip, m, s);
   if (e != hipSuccess) return e;
@@ -798,11 +866,11 @@ template hipError_t mg_vcycle<float>(Ctx &, const float *, float *, const int32_
 hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void *p, const void *q, double *partial,
                             PcgScalars *sc, hipStream_t s) {
   if (dt == FNPF_F64)
-    k_mg_update<double, double><<<kVecBlocks, kVecThreads, 0, s>>>((double *)x, (double *)r, (const double *)p,
-                                                                    (const double *)q, c.n_v, partial, sc);
+    k_mg_update<double><<<kVecBlocks, kVecThreads, 0, s>>>((double *)x, (double *)r, (const double *)p,
+                                                           (const double *)q, c.n_v, partial, sc);
   else
-    k_mg_update<float, float><<<kVecBlocks, kVecThreads, 0, s>>>((float *)x, (float *)r, (const float *)p,
-                                                                  (const float *)q, c.n_v, partial, sc);
+    k_mg_update<float><<<kVecBlocks, kVecThreads, 0, s>>>((float *)x, (float *)r, (const float *)p,
+                                                          (const float *)q, c.n_v, partial, sc);
   k_mg_fin_rr<<<1, kVecThreads, 0, s>>>(partial, kVecBlocks, sc);
   return hipGetLastError();
 }

@@ -391,3 +391,47 @@ def test_multigrid_repeatable_and_c2():
     r = -op.apply(pr.m, Go, host(a))
     I = sv.interior_mask(pr.m)
     assert np.linalg.norm(r[I]) <= 1.05e-10 * np.linalg.norm(bvec[I])
+
+
+def test_c3_full_size_cylinder():
+    """C3 (cylinder in a tank, 771,528 DoF, unstructured O-grid + jittered block, relaxation zones):
+    apply parity everywhere, multigrid solves that satisfy the oracle's equations, w parity, and
+    ERK4 steps with relaxation whose FP64 and mixed results agree."""
+    wl = configs.c3()
+    pr = Pair(wl, fp32=True)
+    pr.ctx.geom(pr.d_eta, pr.d_h)
+    Go, _, _ = pr.oracle_factors()
+    rng = np.random.default_rng(3)
+    xv = rng.standard_normal(pr.m.n_v)
+    yo = op.apply(pr.m, Go, xv)
+    # curved (arc) and jittered elements: the factors vary inside every element and the two sides
+    # form them in different orders, so the sums differ by a few 1e-13
+    assert rel(host(pr.ctx.laplace_apply(dev(xv))), yo) < 1e-12
+    assert rel(host(pr.ctx.laplace_apply(dev(xv).float())), yo) < 2e-6
+    # a wavy state so the solve is not trivial
+    eta = 0.02 * np.cos(pr.x) * np.sin(0.7 * pr.y)
+    phis = 0.05 * np.sin(pr.x + 0.2 * pr.y)
+    pr.ctx.geom(dev(eta), pr.d_h)
+    G2, _, _ = geo.factors(pr.m, eta, pr.h, pr.xh)
+    lift = np.zeros(pr.m.n_v)
+    lift[sv.surface_slice(pr.m)] = phis
+    b = -op.apply(pr.m, G2, lift)
+    I = sv.interior_mask(pr.m)
+    for precision in (0, 1):
+        phi, info = pr.ctx.solve(dev(phis), opts=fnpf.default_opts(precision=precision, rtol=1e-10))
+        assert info["status"] == "OK" and info["iters"] < 120
+        r = -op.apply(pr.m, G2, host(phi))
+        assert np.linalg.norm(r[I]) <= 1.05e-10 * np.linalg.norm(b[I])
+    wo = sf.w_surface(pr.m, host(phi), eta, pr.h, pr.xh)
+    assert rel(host(pr.ctx.w_surface(phi)), wo) < 1e-12
+    x, y = pr.ctx.node_xy()
+    ra = wl.relaxation_arrays(x, y)
+    pr.ctx.set_relaxation(*ra, omega=wl.relax_wave.omega, t_ramp=wl.t_ramp)
+    res = []
+    for precision in (0, 1):
+        e, p = dev(eta), dev(phis)
+        o = fnpf.default_opts(precision=precision, rtol=1e-11, inner_rtol=1e-3)
+        for n in range(3):
+            pr.ctx.rk4_step(e, p, pr.d_h, n * wl.dt, wl.dt, opts=o)
+        res.append((host(e), host(p)))
+    assert rel(res[1][0], res[0][0]) < 1e-8 and rel(res[1][1], res[0][1]) < 1e-8

@@ -68,14 +68,18 @@ def apply_flops(n_q, p):
 
 
 def kernel_source_sha256():
-    """sha256 of the apply-kernel region of kernels_column.hip (buffer helpers to the last apply kernel)."""
+    """sha256 of the sources that fix the apply's memory traffic: the apply-kernel region of
+    kernels_column.hip (buffer helpers to the last apply kernel) and the host setup (ownership,
+    face slots)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2506_09435_amd", "csrc", "kernels_column.hip")
-    with open(src, encoding="utf-8") as f:
+    csrc = os.path.join(ROOT, "paper_2506_09435_amd", "csrc")
+    with open(os.path.join(csrc, "kernels_column.hip"), encoding="utf-8") as f:
         text = f.read()
     i0 = text.index("// Raw buffer access")
     i1 = text.index("bool owner_apply_active(const Ctx &c) {")
-    return hashlib.sha256(text[i0:i1].encode()).hexdigest()
+    with open(os.path.join(csrc, "setup.cpp"), encoding="utf-8") as f:
+        setup = f.read()
+    return hashlib.sha256((text[i0:i1] + setup).encode()).hexdigest()
 
 
 def time_applies(ctx, x, reps, warm=3):

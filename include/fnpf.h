@@ -137,6 +137,9 @@ typedef struct {
   int32_t max_outer;
   int32_t extrapolate;
   int32_t cheb_degree;   /* precond 2: smoothing degree, 1 .. 8 (default 2) */
+  int32_t use_graph;     /* 1: the check_every iterations between host checks are captured
+                            once as a HIP graph and replayed (default); 0: launched one by one.
+                            Results are identical. */
 } fnpf_solve_opts;
 
 typedef struct {
@@ -147,7 +150,7 @@ typedef struct {
 } fnpf_solve_info;
 
 /* Defaults: FP64, p-multigrid (precond 2), rtol 1e-8, atol 0, max_iter 20000,
- * check_every 8, inner_rtol 1e-4, max_outer 30, extrapolate 1, cheb_degree 2. */
+ * check_every 8, inner_rtol 1e-4, max_outer 30, extrapolate 1, cheb_degree 2, use_graph 1. */
 void fnpf_default_opts(fnpf_solve_opts *opts);
 
 /* Create a context on the current HIP device: validates and copies the mesh,

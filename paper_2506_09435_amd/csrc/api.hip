@@ -54,7 +54,20 @@ void dfree(T *&p) {
   p = nullptr;
 }
 
+void free_graphs(Ctx &c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c.g_exec[k]) (void)hipGraphExecDestroy(c.g_exec[k]);
+    if (c.g_graph[k]) (void)hipGraphDestroy(c.g_graph[k]);
+    c.g_exec[k] = nullptr;
+    c.g_graph[k] = nullptr;
+    c.g_key[k] = Ctx::GraphKey();
+  }
+}
+
 void free_all(Ctx &c) {
+  free_graphs(c);
+  if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
+  c.cap_stream = nullptr;
   mg_free(c);
   dfree(c.d_mask);
   dfree(c.d_mask32);
@@ -217,6 +230,56 @@ fnpf_status ensure_mask(Ctx &c, hipStream_t s) {
   return FNPF_OK;
 }
 
+// Runs body (check_every PCG iterations enqueued on a stream): directly, or as a HIP graph captured
+// on the context's capture stream and replayed on s.  A graph is reused while its key (solution
+// pointer, preconditioner and schedule settings) is unchanged; every kernel in it reads its
+// scalars (alpha, beta, Chebyshev coefficients, the done flag) from device memory.
+template <typename Body>
+fnpf_status run_chunk(Ctx &c, int slot, const Ctx::GraphKey &key, bool use_graph, hipStream_t s, Body body) {
+  if (!use_graph) return body(s);
+  if (!c.g_exec[slot] || !(c.g_key[slot] == key)) {
+    if (c.g_exec[slot]) (void)hipGraphExecDestroy(c.g_exec[slot]);
+    if (c.g_graph[slot]) (void)hipGraphDestroy(c.g_graph[slot]);
+    c.g_exec[slot] = nullptr;
+    c.g_graph[slot] = nullptr;
+    if (!c.cap_stream) HIPCHK(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+    fnpf_status st = body(c.cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c.cap_stream, &g);
+    if (st != FNPF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hipfail(&c, e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hipfail(&c, e, "hipGraphInstantiate");
+    }
+    c.g_graph[slot] = g;
+    c.g_exec[slot] = x;
+    c.g_key[slot] = key;
+  }
+  HIPCHK(hipGraphLaunch(c.g_exec[slot], s));
+  return FNPF_OK;
+}
+
+Ctx::GraphKey graph_key(const Ctx &c, const void *x, const fnpf_solve_opts &o, int nb) {
+  Ctx::GraphKey k;
+  k.x = x;
+  k.precond = o.precond;
+  k.check_every = o.check_every;
+  k.cheb = o.cheb_degree;
+  k.variant = c.apply_variant;
+  k.tune = c.apply_tune;
+  k.lines = c.apply_lines;
+  k.owner = c.apply_owner;
+  k.nb = nb;
+  return k;
+}
+
 // PCG on A_II (FP64), x = phi holds the guess with its surface level set.
 fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, int &iters, hipStream_t s) {
   PcgScalars *sc = c.d_sc;
@@ -238,20 +301,26 @@ fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, 
     HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 1, s));
   }
   const int nb = apply_blocks(c);
-  iters = 0;
-  for (;;) {
+  auto body = [&](hipStream_t st) -> fnpf_status {
     for (int k = 0; k < o.check_every; ++k) {
-      HIPCHK(launch_apply(c, FNPF_F64, c.d_p, c.d_q, true, c.d_partial, &sc->done, s));
-      HIPCHK(launch_finalize_pq(c.d_partial, nb, sc, s));
+      HIPCHK(launch_apply(c, FNPF_F64, c.d_p, c.d_q, true, c.d_partial, &sc->done, st));
+      HIPCHK(launch_finalize_pq(c.d_partial, nb, sc, st));
       if (mg) {
-        HIPCHK(launch_mg_update(c, FNPF_F64, x, c.d_r, c.d_p, c.d_q, c.d_partial, sc, s));
-        HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, s));
-        HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 0, s));
+        HIPCHK(launch_mg_update(c, FNPF_F64, x, c.d_r, c.d_p, c.d_q, c.d_partial, sc, st));
+        HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, st));
+        HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 0, st));
       } else {
-        HIPCHK((launch_pcg_update<double, double>(x, c.d_r, c.d_p, c.d_q, dinv, c.n_v, c.d_partial, sc, s)));
-        HIPCHK(launch_pcg_dir<double>(c.d_p, c.d_r, dinv, c.n_v, sc, s));
+        HIPCHK((launch_pcg_update<double, double>(x, c.d_r, c.d_p, c.d_q, dinv, c.n_v, c.d_partial, sc, st)));
+        HIPCHK(launch_pcg_dir<double>(c.d_p, c.d_r, dinv, c.n_v, sc, st));
       }
     }
+    return FNPF_OK;
+  };
+  const Ctx::GraphKey key = graph_key(c, x, o, nb);
+  iters = 0;
+  for (;;) {
+    fnpf_status st = run_chunk(c, 0, key, o.use_graph != 0, s, body);
+    if (st != FNPF_OK) return st;
     HIPCHK(hipMemcpyAsync(c.h_sc, c.d_sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     iters = c.h_sc[0].iters;
@@ -280,6 +349,23 @@ fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts 
   const float *dinv = o.precond == 1 ? c.d_dinv32 : c.d_mask32;
   float *z = mg ? c.mg_f32[0] : nullptr;
   const int nb = apply_blocks(c);
+  auto body = [&](hipStream_t st) -> fnpf_status {
+    for (int k = 0; k < o.check_every; ++k) {
+      HIPCHK(launch_apply(c, FNPF_F32, c.d_p32, c.d_q32, true, c.d_partial, &si->done, st));
+      HIPCHK(launch_finalize_pq(c.d_partial, nb, si, st));
+      if (mg) {
+        HIPCHK(launch_mg_update(c, FNPF_F32, c.d_d32, c.d_r32, c.d_p32, c.d_q32, c.d_partial, si, st));
+        HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, st));
+        HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 0, st));
+      } else {
+        HIPCHK((launch_pcg_update<float, float>(c.d_d32, c.d_r32, c.d_p32, c.d_q32, dinv, c.n_v, c.d_partial, si,
+                                                st)));
+        HIPCHK(launch_pcg_dir<float>(c.d_p32, c.d_r32, dinv, c.n_v, si, st));
+      }
+    }
+    return FNPF_OK;
+  };
+  const Ctx::GraphKey key = graph_key(c, c.d_d32, o, nb);
   iters = 0;
   outer = 0;
   for (;;) {
@@ -298,19 +384,8 @@ fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts 
     if (outer > o.max_outer || iters >= o.max_iter)
       return fail(&c, FNPF_ERR_NOCONV, "mixed-precision solve did not reach the tolerance");
     for (;;) {
-      for (int k = 0; k < o.check_every; ++k) {
-        HIPCHK(launch_apply(c, FNPF_F32, c.d_p32, c.d_q32, true, c.d_partial, &si->done, s));
-        HIPCHK(launch_finalize_pq(c.d_partial, nb, si, s));
-        if (mg) {
-          HIPCHK(launch_mg_update(c, FNPF_F32, c.d_d32, c.d_r32, c.d_p32, c.d_q32, c.d_partial, si, s));
-          HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, s));
-          HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 0, s));
-        } else {
-          HIPCHK((launch_pcg_update<float, float>(c.d_d32, c.d_r32, c.d_p32, c.d_q32, dinv, c.n_v, c.d_partial, si,
-                                                  s)));
-          HIPCHK(launch_pcg_dir<float>(c.d_p32, c.d_r32, dinv, c.n_v, si, s));
-        }
-      }
+      fnpf_status st = run_chunk(c, 1, key, o.use_graph != 0, s, body);
+      if (st != FNPF_OK) return st;
       HIPCHK(hipMemcpyAsync(c.h_sc + 1, si, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       if (c.h_sc[1].done || iters + c.h_sc[1].iters >= o.max_iter) break;
@@ -333,6 +408,7 @@ fnpf_status validate_opts(Ctx &c, const fnpf_solve_opts &o) {
     return fail(&c, FNPF_ERR_ARG, "opts.rtol/atol must be >= 0 and not both 0");
   if (o.max_iter < 1 || o.check_every < 1) return fail(&c, FNPF_ERR_ARG, "opts.max_iter and check_every must be >= 1");
   if (o.extrapolate != 0 && o.extrapolate != 1) return fail(&c, FNPF_ERR_ARG, "opts.extrapolate must be 0 or 1");
+  if (o.use_graph != 0 && o.use_graph != 1) return fail(&c, FNPF_ERR_ARG, "opts.use_graph must be 0 or 1");
   if (o.precision == 1 && (!(o.inner_rtol > 0.0) || !(o.inner_rtol < 1.0) || o.max_outer < 1))
     return fail(&c, FNPF_ERR_ARG, "opts.inner_rtol must be in (0,1) and max_outer >= 1 for the mixed path");
   return FNPF_OK;
@@ -410,6 +486,7 @@ void fnpf_default_opts(fnpf_solve_opts *o) {
   o->max_outer = 30;
   o->extrapolate = 1;
   o->cheb_degree = 2;
+  o->use_graph = 1;
 }
 
 const char *fnpf_status_string(fnpf_status s) {

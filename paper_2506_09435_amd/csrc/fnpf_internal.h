@@ -224,9 +224,25 @@ struct Ctx {
   double *mg_f64[4] = {nullptr, nullptr, nullptr, nullptr};  // fine-level z, r, d, q
   float *mg_f32[4] = {nullptr, nullptr, nullptr, nullptr};
   double lam64 = 0.0, lam32 = 0.0;
+  double *d_mgc = nullptr;                // Chebyshev coefficient table [precision][level][32]
+  std::vector<double> h_mgc;
   double *mg_ev64 = nullptr;              // fine-level eigenvector estimate
   float *mg_ev32 = nullptr;
   bool mg_ev_ok64 = false, mg_ev_ok32 = false;
+  // captured PCG iteration chunks, replayed with hipGraphLaunch: [0] FP64 solve, [1] FP32 inner
+  struct GraphKey {
+    const void *x = nullptr;
+    int precond = -1, check_every = 0, cheb = 0, variant = -1, tune = -1, nb = 0;
+    bool lines = false, owner = false;
+    bool operator==(const GraphKey &o) const {
+      return x == o.x && precond == o.precond && check_every == o.check_every && cheb == o.cheb &&
+             variant == o.variant && tune == o.tune && nb == o.nb && lines == o.lines && owner == o.owner;
+    }
+  };
+  hipGraph_t g_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t g_exec[2] = {nullptr, nullptr};
+  GraphKey g_key[2];
+  hipStream_t cap_stream = nullptr;       // capture-only stream (default priority)
   double *d_mask = nullptr;               // 1 below the surface level, 0 on it (no preconditioner)
   float *d_mask32 = nullptr;
   // relaxation

@@ -34,6 +34,7 @@ constexpr double kMgSafety = 1.1;       // upper end of the smoothing interval o
 constexpr double kMgSmoothRatio = 4.0;  // smoothing interval [lmax / 4, lmax]
 constexpr double kMgCoarseRatio = 30.0;
 constexpr int kPowFirst = 15, kPowNext = 4;   // power iterations (cold, warm start)
+constexpr int kMgCoef = 32;                   // coefficient-table entries per level
 
 // Interpolation tables for a fine degree pf (2..8) and pc = pf / 2:
 //   c_IP[pf][r (pc+1) + a] = l^c_a(x^f_r)   coarse Lagrange basis at the fine GLL nodes
@@ -335,9 +336,10 @@ __device__ __forceinline__ void final_sums(const double *partial, int np, double
 
 // first Chebyshev step from x = 0: r = b, d = c dinv b, x = d
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_cheb0(const T *b, T *r, T *d, T *x, const T *dinv, T c, int64_t n,
-                                                       const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_cheb0(const T *b, T *r, T *d, T *x, const T *dinv,
+                                                       const double *cf, int64_t n, const int32_t *skip) {
   if (skip != nullptr && *skip) return;
+  const T c = (T)cf[0];
   GRID_STRIDE(i, n) {
     const T bi = b[i];
     const T di = c * dinv[i] * bi;
@@ -349,9 +351,10 @@ __global__ __launch_bounds__(kVecThreads) void k_cheb0(const T *b, T *r, T *d, T
 
 // first Chebyshev step from x: r = b - q (q = A x), d = c dinv r, x += d
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_cheb1(const T *b, const T *q, T *r, T *d, T *x, const T *dinv, T c,
-                                                       int64_t n, const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_cheb1(const T *b, const T *q, T *r, T *d, T *x, const T *dinv,
+                                                       const double *cf, int64_t n, const int32_t *skip) {
   if (skip != nullptr && *skip) return;
+  const T c = (T)cf[0];
   GRID_STRIDE(i, n) {
     const T ri = b[i] - q[i];
     const T di = c * dinv[i] * ri;
@@ -363,9 +366,11 @@ __global__ __launch_bounds__(kVecThreads) void k_cheb1(const T *b, const T *q, T
 
 // later steps: r -= q (q = A d), d = c1 d + c2 dinv r, x += d
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_cheb_step(T *r, const T *q, T *d, T *x, const T *dinv, T c1, T c2,
-                                                           int64_t n, const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_cheb_step(T *r, const T *q, T *d, T *x, const T *dinv,
+                                                           const double *cf, int k, int64_t n,
+                                                           const int32_t *skip) {
   if (skip != nullptr && *skip) return;
+  const T c1 = (T)cf[3 + 2 * (k - 2)], c2 = (T)cf[4 + 2 * (k - 2)];
   GRID_STRIDE(i, n) {
     const T ri = r[i] - q[i];
     const T di = c1 * d[i] + c2 * dinv[i] * ri;
@@ -380,33 +385,38 @@ __global__ __launch_bounds__(kVecThreads) void k_cheb_step(T *r, const T *q, T *
 // vectors each formula needs are read, and no residual or step vector survives it.
 //   y = c dinv b
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_scale(T *y, const T *b, const T *dinv, T c, int64_t n,
+__global__ __launch_bounds__(kVecThreads) void k_scale(T *y, const T *b, const T *dinv, const double *cf, int64_t n,
                                                        const int32_t *skip) {
   if (skip != nullptr && *skip) return;
+  const T c = (T)cf[0];
   GRID_STRIDE(i, n) y[i] = c * dinv[i] * b[i];
 }
 
 //   from zero: x = a1 y + a2 dinv (b - q), y = d1, q = A d1
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_pre2(T *x, const T *y, const T *b, const T *q, const T *dinv, T a1,
-                                                      T a2, int64_t n, const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_pre2(T *x, const T *y, const T *b, const T *q, const T *dinv,
+                                                      const double *cf, int64_t n, const int32_t *skip) {
   if (skip != nullptr && *skip) return;
+  const T a1 = (T)cf[1], a2 = (T)cf[2];
   GRID_STRIDE(i, n) x[i] = a1 * y[i] + a2 * dinv[i] * (b[i] - q[i]);
 }
 
 //   from x: d1 = c dinv (b - q1), q1 = A x
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_post2a(T *d, const T *b, const T *q1, const T *dinv, T c, int64_t n,
-                                                        const int32_t *skip) {
+__global__ __launch_bounds__(kVecThreads) void k_post2a(T *d, const T *b, const T *q1, const T *dinv,
+                                                        const double *cf, int64_t n, const int32_t *skip) {
   if (skip != nullptr && *skip) return;
+  const T c = (T)cf[0];
   GRID_STRIDE(i, n) d[i] = c * dinv[i] * (b[i] - q1[i]);
 }
 
 //   x += a1 d1 + a2 dinv (b - q1 - q2), q2 = A d1
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_post2b(T *x, const T *d, const T *b, const T *q1, const T *q2,
-                                                        const T *dinv, T a1, T a2, int64_t n, const int32_t *skip) {
+                                                        const T *dinv, const double *cf, int64_t n,
+                                                        const int32_t *skip) {
   if (skip != nullptr && *skip) return;
+  const T a1 = (T)cf[1], a2 = (T)cf[2];
   GRID_STRIDE(i, n) x[i] += a1 * d[i] + a2 * dinv[i] * (b[i] - q1[i] - q2[i]);
 }
 
@@ -618,31 +628,52 @@ hipError_t surf_to(Ctx &F, Ctx &C, double *Hc, double *hc, hipStream_t s) {
   return hipSuccess;
 }
 
+// Device table of the Chebyshev coefficients, kMgCoef doubles per (precision, level): [0] 1/theta,
+// [1] 1 + c1_2 and [2] c2_2 (closed-form degree 2), then (c1_k, c2_k) for steps k = 2 .. 10 of the
+// three-term recurrence on [lmax / ratio, lmax], lmax = 1.1 lam.  Kernels read it from device
+// memory, so captured iteration graphs stay valid when the estimates change.
+template <typename T>
+const double *coef_table(Ctx &c, int l) {
+  return c.d_mgc + ((sizeof(T) == 8 ? 0 : 1) * (int)(c.mg.size() + 1) + l) * kMgCoef;
+}
+
+void chebyshev_coefficients(double lam, double ratio, double *cf) {
+  const double lmax = kMgSafety * lam, lmin = lmax / ratio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  for (int k = 0; k < kMgCoef; ++k) cf[k] = 0.0;
+  cf[0] = 1.0 / theta;
+  double rho0 = 1.0 / sigma;
+  for (int k = 2; k <= kMgCoarseSteps; ++k) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho0);
+    cf[3 + 2 * (k - 2)] = rho1 * rho0;
+    cf[4 + 2 * (k - 2)] = 2.0 * rho1 / delta;
+    if (k == 2) {
+      cf[1] = 1.0 + rho1 * rho0;
+      cf[2] = 2.0 * rho1 / delta;
+    }
+    rho0 = rho1;
+  }
+}
+
 // Chebyshev smoothing of A x = b on level L (D^-1 A spectrum estimate lam), m steps.  From zero:
 // x = p(D^-1 A) D^-1 b; otherwise x += p(D^-1 A) D^-1 (b - A x).  On return r = b - A x_{m-1}
 // and d = x_m - x_{m-1}.
 template <typename T>
-hipError_t smooth(Ctx &L, const T *b, T *x, T *r, T *d, T *q, double lam, int m, double ratio, bool from_zero,
+hipError_t smooth(Ctx &L, const T *b, T *x, T *r, T *d, T *q, const double *cf, int m, bool from_zero,
                   const int32_t *skip, hipStream_t s) {
-  const double lmax = kMgSafety * lam, lmin = lmax / ratio;
-  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
-  double rho0 = 1.0 / sigma;
   const T *dinv = Prec<T>::dinv(L);
   const int64_t n = L.n_v;
   if (from_zero) {
-    k_cheb0<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, r, d, x, dinv, (T)(1.0 / theta), n, skip);
+    k_cheb0<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, r, d, x, dinv, cf, n, skip);
   } else {
     hipError_t e = launch_apply(L, Prec<T>::dt, x, q, true, nullptr, skip, s);
     if (e != hipSuccess) return e;
-    k_cheb1<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, q, r, d, x, dinv, (T)(1.0 / theta), n, skip);
+    k_cheb1<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, q, r, d, x, dinv, cf, n, skip);
   }
   for (int k = 2; k <= m; ++k) {
     hipError_t e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s);
     if (e != hipSuccess) return e;
-    const double rho1 = 1.0 / (2.0 * sigma - rho0);
-    k_cheb_step<T><<<kVecBlocks, kVecThreads, 0, s>>>(r, q, d, x, dinv, (T)(rho1 * rho0), (T)(2.0 * rho1 / delta), n,
-                                                      skip);
-    rho0 = rho1;
+    k_cheb_step<T><<<kVecBlocks, kVecThreads, 0, s>>>(r, q, d, x, dinv, cf, k, n, skip);
   }
   return hipGetLastError();
 }
@@ -652,45 +683,38 @@ template <typename T>
 hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, hipStream_t s) {
   Ctx &L = l == 0 ? c : *c.mg[l - 1].c;
   T *r, *d, *q;
-  double lam;
   if (l == 0) {
     r = Prec<T>::fv(c)[1];
     d = Prec<T>::fv(c)[2];
     q = Prec<T>::fv(c)[3];
-    lam = Prec<T>::lamf(c);
   } else {
     r = Prec<T>::lv(c.mg[l - 1])[2];
     d = Prec<T>::lv(c.mg[l - 1])[3];
     q = Prec<T>::lv(c.mg[l - 1])[4];
-    lam = Prec<T>::lam(c.mg[l - 1]);
   }
+  const double *cf = coef_table<T>(c, l);
   const int last = (int)c.mg.size();
-  if (l == last) return smooth<T>(L, b, x, r, d, q, lam, kMgCoarseSteps, kMgCoarseRatio, true, skip, s);
+  if (l == last) return smooth<T>(L, b, x, r, d, q, cf, kMgCoarseSteps, true, skip, s);
   MgLevel &C = c.mg[l];
   T *bc = Prec<T>::lv(C)[0], *xc = Prec<T>::lv(C)[1];
   const int64_t n = L.n_v;
   const T *dinv = Prec<T>::dinv(L);
   hipError_t e = hipSuccess;
   if (m == 2) {
-    // coefficients of the two Chebyshev steps on [lmax / ratio, lmax]
-    const double lmax = kMgSafety * lam, lmin = lmax / kMgSmoothRatio;
-    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
-    const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
-    const T c0 = (T)(1.0 / theta), a1 = (T)(1.0 + rho1 * rho0), a2 = (T)(2.0 * rho1 / delta);
-    k_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, dinv, c0, n, skip);
+    k_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
-    k_pre2<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, q, dinv, a1, a2, n, skip);
+    k_pre2<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, q, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, x, q, true, nullptr, skip, s)) != hipSuccess) return e;
     if ((e = restrict_to<T>(L, *C.c, b, q, bc, skip, s)) != hipSuccess) return e;   // P^T (b - A x)
     if ((e = vcycle<T>(c, l + 1, bc, xc, skip, m, s)) != hipSuccess) return e;
     if ((e = prolong_to<T>(L, *C.c, xc, x, skip, s)) != hipSuccess) return e;
     if ((e = launch_apply(L, Prec<T>::dt, x, r, true, nullptr, skip, s)) != hipSuccess) return e;
-    k_post2a<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, r, dinv, c0, n, skip);
+    k_post2a<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, r, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
-    k_post2b<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, r, q, dinv, a1, a2, n, skip);
+    k_post2b<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, r, q, dinv, cf, n, skip);
     return hipGetLastError();
   }
-  e = smooth<T>(L, b, x, r, d, q, lam, m, kMgSmoothRatio, true, skip, s);
+  e = smooth<T>(L, b, x, r, d, q, cf, m, true, skip, s);
   if (e != hipSuccess) return e;
   // residual of the smoothed x, r - A d, restricted directly
   e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s);
@@ -701,7 +725,7 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
   if (e != hipSuccess) return e;
   e = prolong_to<T>(L, *C.c, xc, x, skip, s);
   if (e != hipSuccess) return e;
-  return smooth<T>(L, b, x, r, d, q, lam, m, kMgSmoothRatio, false, skip, s);
+  return smooth<T>(L, b, x, r, d, q, cf, m, false, skip, s);
 }
 
 // Rayleigh-quotient power iteration for the largest eigenvalue of D^-1 A on level L.  v holds the
@@ -775,6 +799,7 @@ fnpf_status mg_build(Ctx &c) {
     c.mg.push_back(L);
     F = c.mg.back().c;
   }
+  if (dalloc_t(&c.d_mgc, (size_t)2 * (c.mg.size() + 1) * kMgCoef) != hipSuccess) return FNPF_ERR_ALLOC;
   c.mg_built = true;
   c.mg_stale64 = c.mg_stale32 = true;
   return FNPF_OK;
@@ -804,6 +829,8 @@ void mg_free(Ctx &c) {
   c.mg_ev64 = nullptr;
   c.mg_ev32 = nullptr;
   c.mg_ev_ok64 = c.mg_ev_ok32 = false;
+  if (c.d_mgc) (void)hipFree(c.d_mgc);
+  c.d_mgc = nullptr;
   c.mg_built = false;
 }
 
@@ -850,6 +877,21 @@ fnpf_status mg_refresh(Ctx &c, hipStream_t s) {
     }
   }
   if (!(Prec<T>::lamf(c) > 0.0)) return FNPF_ERR_NAN;
+  // coefficient table of this precision (stream-ordered before any later use)
+  {
+    const int nl = (int)c.mg.size() + 1;
+    std::vector<double> &tab = c.h_mgc;
+    tab.resize((size_t)2 * nl * kMgCoef);
+    const int base = (sizeof(T) == 8 ? 0 : 1) * nl;
+    for (int l = 0; l < nl; ++l) {
+      const double lam = l == 0 ? Prec<T>::lamf(c) : Prec<T>::lam(c.mg[l - 1]);
+      chebyshev_coefficients(lam, l == nl - 1 ? kMgCoarseRatio : kMgSmoothRatio, tab.data() + (base + l) * kMgCoef);
+    }
+    if (hipMemcpyAsync(c.d_mgc + base * kMgCoef, tab.data() + base * kMgCoef, sizeof(double) * nl * kMgCoef,
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+      return FNPF_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return FNPF_ERR_HIP;
+  }
   Prec<T>::stale(c) = false;
   return FNPF_OK;
 }

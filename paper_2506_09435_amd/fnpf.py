@@ -40,7 +40,8 @@ class MeshDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double),
                 ("max_iter", C.c_int32), ("check_every", C.c_int32), ("inner_rtol", C.c_double),
-                ("max_outer", C.c_int32), ("extrapolate", C.c_int32), ("cheb_degree", C.c_int32)]
+                ("max_outer", C.c_int32), ("extrapolate", C.c_int32), ("cheb_degree", C.c_int32),
+                ("use_graph", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -435,3 +435,33 @@ def test_c3_full_size_cylinder():
             pr.ctx.rk4_step(e, p, pr.d_h, n * wl.dt, wl.dt, opts=o)
         res.append((host(e), host(p)))
     assert rel(res[1][0], res[0][0]) < 1e-8 and rel(res[1][1], res[0][1]) < 1e-8
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_match_eager(precision, precond):
+    """Iteration chunks replayed as HIP graphs give bitwise the eager result, replay after replay,
+    with eager work (geometry, RHS, surface kernels, host checks) between the replays."""
+    wl = _case("box_walls_p6")
+    pe, pg = Pair(wl, fp32=True), Pair(wl, fp32=True)
+    kw = dict(precision=precision, precond=precond, rtol=1e-12, inner_rtol=1e-3, check_every=3)
+    oe, og = fnpf.default_opts(use_graph=0, **kw), fnpf.default_opts(use_graph=1, **kw)
+    ee, phe = pe.d_eta.clone(), pe.d_phis.clone()
+    eg, phg = pg.d_eta.clone(), pg.d_phis.clone()
+    t, dt = 0.0, 0.02
+    for n in range(4):
+        ie = pe.ctx.rk4_step(ee, phe, pe.d_h, t, dt, opts=oe)
+        ig = pg.ctx.rk4_step(eg, phg, pg.d_h, t, dt, opts=og)
+        torch.cuda.synchronize()
+        assert torch.equal(ee, eg) and torch.equal(phe, phg), f"step {n}"
+        assert [i["iters"] for i in ie] == [i["iters"] for i in ig]
+        t += dt
+    # fnpf_solve into caller tensors: a new solution pointer captures a new graph
+    for k in range(3):
+        xe = torch.zeros(pe.m.n_v, dtype=torch.float64, device="cuda")
+        xg = torch.zeros(pg.m.n_v, dtype=torch.float64, device="cuda")
+        pe.ctx.geom(ee, pe.d_h)
+        pg.ctx.geom(eg, pg.d_h)
+        _, a = pe.ctx.solve(phe, phi=xe, opts=oe)
+        _, b = pg.ctx.solve(phg, phi=xg, opts=og)
+        assert torch.equal(xe, xg) and a["iters"] == b["iters"], f"solve {k}"

@@ -43,10 +43,15 @@ class Model:
 
     ``solver``: "dense" (assembled matrix, direct solve; tiny meshes) or "cg"
     (Jacobi-PCG on the matrix-free apply, warm-started from the last stage).
+    ``linear``: the linear potential-flow (LPF) model the paper runs beside FNPF (Sec. 2.1
+    remark, Sec. 4.1.2): the free surface stays at z = 0, so the Laplace domain is the fixed
+    column [-h, 0], and the kinematic and dynamic conditions (Eqs. 2-3) keep only their
+    linear terms, d eta/dt = w and d phi_s/dt = -g eta.
     """
 
-    def __init__(self, workload, solver="dense", rtol=1e-13):
+    def __init__(self, workload, solver="dense", rtol=1e-13, linear=False):
         self.wl = workload
+        self.linear = linear
         self.mesh = workload.mesh
         self.g = workload.g
         self.solver = solver
@@ -84,6 +89,11 @@ class Model:
     # -- one RK stage (Steps 4.1-4.6) -----------------------------------------
     def stage(self, eta, phi_s, h=None, phi_guess=None):
         h = self.h if h is None else h
+        if self.linear:
+            flat = np.zeros_like(np.asarray(eta))
+            phi = self.laplace(flat, phi_s, h, phi_guess)
+            w = sf.w_surface(self.mesh, phi, flat, h, self.xh)
+            return w, -self.g * np.asarray(eta), phi, w
         phi = self.laplace(eta, phi_s, h, phi_guess)
         w = sf.w_surface(self.mesh, phi, eta, h, self.xh)
         deta, dphi = sf.free_surface_rhs(self.mesh, eta, phi_s, w, self.g, metrics=self.metrics)

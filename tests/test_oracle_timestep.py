@@ -178,3 +178,76 @@ def test_complex_step_matches_central_differences():
     Jm = ts.gauge_loss(md, P, obs, 3, dt, eta0 - eps * de, phi0, h - eps * dh)
     d_fd = (Jp - Jm) / (2 * eps)
     assert abs(d_cs - d_fd) < 1e-7 * abs(d_fd) + 1e-18
+
+
+def _dtn_matrix(md):
+    """Discrete LPF Dirichlet-to-Neumann map S (w = S phi_s on the flat domain), column by column."""
+    n = md.mesh.n_s
+    flat = np.zeros(n)
+    S = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        _, _, _, w = md.stage(flat, e)
+        S[:, k] = w
+    return S
+
+
+def test_lpf_exact_eigenmode_follows_rk4_closed_form():
+    """LPF on C1: started from an eigenvector v of the discrete DtN map (S v = lam v), the
+    semi-discrete system is the 2x2 oscillator (eta, phi_s)' = [[0, lam], [-g, 0]] (eta, phi_s) on
+    span(v), so N ERK4 steps equal the N-th power of the RK4 polynomial of dt times that matrix."""
+    wl = configs.c1()
+    md = ts.Model(wl, solver="dense", linear=True)
+    S = _dtn_matrix(md)
+    vals, vecs = np.linalg.eig(S)
+    k = wl.meta["k"]
+    target = k * math.tanh(k * wl.meta["h"])
+    i = int(np.argmin(np.abs(vals - target)))
+    lam, v = float(vals[i].real), np.real(vecs[:, i])
+    assert abs(vals[i].imag) < 1e-10 * abs(lam)
+    assert np.linalg.norm(S @ v - lam * v) < 1e-10 * np.linalg.norm(lam * v)
+    assert abs(lam / target - 1) < 3e-3                      # spatial error of C1's DtN map
+    g, dt, N = wl.g, wl.dt, 16
+    L = dt * np.array([[0.0, lam], [-g, 0.0]])
+    Pm = np.eye(2) + L + L @ L / 2 + L @ L @ L / 6 + L @ L @ L @ L / 24
+    y = np.linalg.matrix_power(Pm, N) @ np.array([1e-3, 0.0])
+    eta, phi = 1e-3 * v, np.zeros_like(v)
+    t = 0.0
+    for n in range(N):
+        eta, phi = md.rk4_step(eta, phi, t, dt)
+        t += dt
+    assert np.linalg.norm(eta - y[0] * v) < 1e-11 * 1e-3 * np.linalg.norm(v)
+    assert np.linalg.norm(phi - y[1] * v) < 1e-11 * abs(y[1]) * np.linalg.norm(v) + 1e-18
+
+
+def test_lpf_linear_and_small_amplitude_limit():
+    """LPF is linear (superposition to rounding); FNPF minus LPF shrinks quadratically with the
+    amplitude (the neglected terms are products of two perturbation fields)."""
+    wl = configs.small_box(nx=4, ny=3, nz=2, p=3, periodic=(True, False))
+    lin = ts.Model(wl, solver="dense", linear=True)
+    fnpf = ts.Model(wl, solver="dense")
+    rng = np.random.default_rng(9)
+    x = lin.x
+    e1 = np.cos(2 * np.pi * x / 2.0)
+    p1 = 0.3 * np.sin(2 * np.pi * x / 2.0)
+    e2, p2 = 0.2 * rng.standard_normal(lin.mesh.n_s), 0.1 * rng.standard_normal(lin.mesh.n_s)
+
+    def run(model, e, p, n=3, dt=0.02):
+        t = 0.0
+        for _ in range(n):
+            e, p = model.rk4_step(e, p, t, dt)
+            t += dt
+        return e, p
+
+    a = run(lin, e1, p1)
+    b = run(lin, e2, p2)
+    c = run(lin, 2.0 * e1 + e2, 2.0 * p1 + p2)
+    assert np.abs(c[0] - (2 * a[0] + b[0])).max() < 1e-12 * np.abs(c[0]).max()
+    assert np.abs(c[1] - (2 * a[1] + b[1])).max() < 1e-12 * np.abs(c[1]).max()
+    diffs = []
+    for amp in (1e-3, 2e-3):
+        fl = run(lin, amp * e1, amp * p1)
+        fn = run(fnpf, amp * e1, amp * p1)
+        diffs.append(np.linalg.norm(fn[0] - fl[0]))
+    assert 3.6 < diffs[1] / diffs[0] < 4.4

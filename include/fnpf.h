@@ -262,6 +262,15 @@ fnpf_status fnpf_rhs(fnpf_ctx ctx, const double *eta, const double *phi_s, const
 fnpf_status fnpf_set_relaxation(fnpf_ctx ctx, const double *cr, const double *eta_c, const double *eta_s,
                                 const double *phi_c, const double *phi_s_, double omega, double t_ramp);
 
+/* Linear potential flow (the linearised model of Sec. 2.1, small-amplitude
+ * limit of Eqs. 2-3): linear != 0 makes fnpf_rk4_step, fnpf_rk4_step_vjp,
+ * fnpf_rhs and fnpf_rhs_vjp use the fixed domain at eta = 0 (the Laplace
+ * problem is solved in -h <= z <= 0 with phi = phi_s on z = 0) and the linear
+ * free-surface conditions d eta/dt = w, d phi_s/dt = -g eta.  The default
+ * (0) is the fully nonlinear model.  fnpf_geom, fnpf_solve and fnpf_w_surface
+ * are unaffected (they take the geometry they are given). */
+fnpf_status fnpf_set_linear(fnpf_ctx ctx, int32_t linear);
+
 /* One ERK4 step (Sec. 3.2) of the Zakharov system from time t with step dt,
  * in place on eta[n_s] and phi_s[n_s] (device FP64), depth h[n_s] (device),
  * followed by relaxation at t + dt.  The volume potential of the previous

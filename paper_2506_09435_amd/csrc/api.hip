@@ -66,6 +66,8 @@ void free_graphs(Ctx &c) {
 
 void free_all(Ctx &c) {
   free_graphs(c);
+  dfree(c.d_flat);
+  dfree(c.d_scr_s);
   if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
   c.cap_stream = nullptr;
   mg_free(c);
@@ -195,6 +197,14 @@ fnpf_status ensure_history(Ctx &c) {
   if (c.d_hist[0][0]) return FNPF_OK;
   for (int s = 0; s < 4; ++s)
     for (int k = 0; k < 2; ++k) HIPCHK(dalloc(&c.d_hist[s][k], c.n_v));
+  return FNPF_OK;
+}
+
+fnpf_status ensure_flat(Ctx &c, hipStream_t s) {
+  if (c.d_flat) return FNPF_OK;
+  HIPCHK(dalloc(&c.d_flat, c.n_s));
+  HIPCHK(dalloc(&c.d_scr_s, c.n_s));
+  HIPCHK(launch_fill(c.d_flat, 0.0, c.n_s, s));
   return FNPF_OK;
 }
 
@@ -772,10 +782,17 @@ fnpf_status fnpf_rhs(fnpf_ctx ctx, const double *eta, const double *phis, const 
   if (deta == eta || deta == phis || dphi == eta || dphi == phis)
     return fail(&c, FNPF_ERR_ARG, "fnpf_rhs: outputs must not alias the inputs");
   RkStageArgs a{};
+  a.linear = c.linear ? 1 : 0;
   a.stage = -1;
   a.out_e = deta;
   a.out_p = dphi;
   HIPCHK(launch_rhs(c, eta, phis, w, a, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_set_linear(fnpf_ctx ctx, int32_t linear) {
+  if (!ctx) return FNPF_ERR_ARG;
+  ctx->c.linear = linear != 0;
   return FNPF_OK;
 }
 
@@ -821,14 +838,23 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
   if (info) std::memset(info, 0, 4 * sizeof(fnpf_solve_info));
   const double *ein = eta, *pin = phis;
   const size_t rec = (size_t)c.n_v + 2 * (size_t)c.n_s;
+  if (c.linear) {
+    // linear potential flow: one flat geometry (eta = 0) serves the four stages
+    st = ensure_flat(c, s);
+    if (st != FNPF_OK) return st;
+    st = geom_impl(c, c.d_flat, h, s);
+    if (st != FNPF_OK) return st;
+  }
   for (int stg = 0; stg < 4; ++stg) {
     if (tape) {
       HIPCHK(hipMemcpyAsync(tape + stg * rec + c.n_v, ein, c.n_s * sizeof(double), hipMemcpyDeviceToDevice, s));
       HIPCHK(hipMemcpyAsync(tape + stg * rec + c.n_v + c.n_s, pin, c.n_s * sizeof(double), hipMemcpyDeviceToDevice,
                             s));
     }
-    st = geom_impl(c, ein, h, s);
-    if (st != FNPF_OK) return st;
+    if (!c.linear) {
+      st = geom_impl(c, ein, h, s);
+      if (st != FNPF_OK) return st;
+    }
     const bool extrap = o.extrapolate && c.hist_count >= 2 && c.hist_dt == dt;
     if (extrap) {
       // linear extrapolation in time from the same stage of the two previous steps
@@ -846,6 +872,7 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
     if (tape) HIPCHK(hipMemcpyAsync(tape + stg * rec, c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_wsurf(c, c.d_phi, c.d_w, s));
     RkStageArgs a{};
+    a.linear = c.linear ? 1 : 0;
     a.eta0 = eta;
     a.phi0 = phis;
     a.acc_e = c.d_acc_e;
@@ -893,7 +920,10 @@ fnpf_status fnpf_rhs_vjp(fnpf_ctx ctx, const double *eta, const double *phis, co
   Ctx &c = ctx->c;
   if (!eta || !phis || !w || !deta_bar || !dphi_bar || !eta_bar || !phis_bar || !w_bar)
     return fail(&c, FNPF_ERR_ARG, "fnpf_rhs_vjp: null device pointer");
-  HIPCHK(launch_rhs_vjp(c, eta, phis, w, deta_bar, dphi_bar, eta_bar, phis_bar, w_bar, (hipStream_t)stream));
+  if (c.linear)
+    HIPCHK(launch_rhs_vjp_linear(deta_bar, dphi_bar, eta_bar, w_bar, c.g, c.n_s, (hipStream_t)stream));
+  else
+    HIPCHK(launch_rhs_vjp(c, eta, phis, w, deta_bar, dphi_bar, eta_bar, phis_bar, w_bar, (hipStream_t)stream));
   return FNPF_OK;
 }
 
@@ -958,6 +988,10 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
   }
   st = ensure_adjoint(c, s);
   if (st != FNPF_OK) return st;
+  if (c.linear) {
+    st = ensure_flat(c, s);
+    if (st != FNPF_OK) return st;
+  }
   if (info) std::memset(info, 0, 4 * sizeof(fnpf_solve_info));
   const size_t rec = (size_t)c.n_v + 2 * (size_t)c.n_s;
   const int64_t ns = c.n_s;
@@ -981,21 +1015,26 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
       HIPCHK(launch_lincomb(c.d_kbe, kRkB[stg] * dt, eta_bar, kRkC[stg + 1] * dt, c.d_ybe, ns, s));
       HIPCHK(launch_lincomb(c.d_kbp, kRkB[stg] * dt, phis_bar, kRkC[stg + 1] * dt, c.d_ybp, ns, s));
     }
-    // stage VJP at Y_s
-    st = geom_impl(c, eta_s, h, s);
+    // stage VJP at Y_s (linear potential flow: the geometry is the flat one, so its adjoint
+    // reaches h only; the eta adjoint of the geometry goes to a discarded scratch vector)
+    st = geom_impl(c, c.linear ? c.d_flat : eta_s, h, s);
     if (st != FNPF_OK) return st;
+    double *geo_eta_bar = c.linear ? c.d_scr_s : c.d_ybe;
     HIPCHK(launch_wsurf(c, phi_s, c.d_w, s));
     HIPCHK(launch_fill(c.d_ybe, 0.0, ns, s));
     HIPCHK(launch_fill(c.d_ybp, 0.0, ns, s));
     HIPCHK(launch_fill(c.d_wbar, 0.0, ns, s));
-    HIPCHK(launch_rhs_vjp(c, eta_s, pin_s, c.d_w, c.d_kbe, c.d_kbp, c.d_ybe, c.d_ybp, c.d_wbar, s));
+    if (c.linear)
+      HIPCHK(launch_rhs_vjp_linear(c.d_kbe, c.d_kbp, c.d_ybe, c.d_wbar, c.g, ns, s));
+    else
+      HIPCHK(launch_rhs_vjp(c, eta_s, pin_s, c.d_w, c.d_kbe, c.d_kbp, c.d_ybe, c.d_ybp, c.d_wbar, s));
     HIPCHK(launch_fill(c.d_phibar, 0.0, c.n_v, s));
-    HIPCHK(launch_wsurf_vjp(c, c.d_wbar, c.d_w, c.d_phibar, c.d_ybe, h_bar, s));
+    HIPCHK(launch_wsurf_vjp(c, c.d_wbar, c.d_w, c.d_phibar, geo_eta_bar, h_bar, s));
     st = solve_impl(c, c.d_zero_s, c.d_phibar, c.d_lam, o, info ? info + stg : nullptr, s);
     if (st != FNPF_OK) return st;
     HIPCHK(launch_apply(c, FNPF_F64, c.d_lam, c.d_q, false, nullptr, nullptr, s));
     HIPCHK(launch_surface_adj(c.d_ybp, c.d_phibar, c.d_q, c.n_v, ns, s));
-    HIPCHK(launch_geom_vjp(c, c.d_lam, phi_s, c.d_ybe, h_bar, s));
+    HIPCHK(launch_geom_vjp(c, c.d_lam, phi_s, geo_eta_bar, h_bar, s));
     HIPCHK(launch_lincomb(c.d_acce, 1.0, c.d_acce, 1.0, c.d_ybe, ns, s));
     HIPCHK(launch_lincomb(c.d_accp, 1.0, c.d_accp, 1.0, c.d_ybp, ns, s));
   }

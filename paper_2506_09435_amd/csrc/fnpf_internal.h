@@ -76,6 +76,7 @@ struct RkStageArgs {
   // relaxation (stage 3 only): f <- (1-cr) f + cr (rc f_c + rs f_s)
   const double *cr, *ec, *es, *pc, *ps;
   double rc, rs;
+  int linear;           // linear potential flow: d eta/dt = w, d phi_s/dt = -g eta
 };
 hipError_t launch_rhs(Ctx &c, const double *eta, const double *phi_s, const double *w, const RkStageArgs &a,
                       hipStream_t s);
@@ -89,6 +90,8 @@ hipError_t launch_geom_vjp(Ctx &c, const double *lam, const double *phi, double 
                            hipStream_t s);
 
 // vector kernels (kernels_vec.hip)
+hipError_t launch_rhs_vjp_linear(const double *kbe, const double *kbp, double *eta_bar, double *w_bar, double g,
+                                 int64_t n, hipStream_t s);
 hipError_t launch_lincomb(double *out, double a, const double *x, double b, const double *y, int64_t n,
                           hipStream_t s);
 hipError_t launch_relax_vjp(double *v, const double *cr, int64_t n, hipStream_t s);
@@ -245,6 +248,10 @@ struct Ctx {
   hipStream_t cap_stream = nullptr;       // capture-only stream (default priority)
   double *d_mask = nullptr;               // 1 below the surface level, 0 on it (no preconditioner)
   float *d_mask32 = nullptr;
+  // linear potential flow (flat geometry at eta = 0, linear free-surface conditions)
+  bool linear = false;
+  double *d_flat = nullptr;               // [n_s] zeros: the LPF surface
+  double *d_scr_s = nullptr;              // [n_s] scratch (discarded eta adjoint of the LPF geometry)
   // relaxation
   double *d_cr = nullptr, *d_rec = nullptr, *d_res = nullptr, *d_rpc = nullptr, *d_rps = nullptr;
   double relax_omega = 0.0, relax_tramp = 0.0;

@@ -1378,8 +1378,9 @@ __global__ __launch_bounds__(256) void k_wsurf(const double *__restrict__ phi, c
 }
 
 // ---------------------------------------------------------------------------------------------
-// Free-surface right-hand side (Step 4.6, Eqs. 2-3, lumped surface mass), fused with the ERK4
-// stage update (Sec. 3.2) and, after the last stage, the relaxation zones (Sec. 3.3).
+// Free-surface right-hand side (Step 4.6, Eqs. 2-3, lumped surface mass; linear potential flow:
+// their linear terms only), fused with the ERK4 stage update (Sec. 3.2) and, after the last
+// stage, the relaxation zones (Sec. 3.3).
 // ---------------------------------------------------------------------------------------------
 template <int P, int DIM>
 __global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ eta, const double *__restrict__ phs,
@@ -1436,8 +1437,8 @@ __global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ eta, con
   }
   const double w = wv[hn];
   const double ee = ex * ex + ey * ey;
-  const double Ek = -(ex * px + ey * py) + w * (1.0 + ee);
-  const double Ed = -g * en - 0.5 * (px * px + py * py) + 0.5 * w * w * (1.0 + ee);
+  const double Ek = a.linear ? w : -(ex * px + ey * py) + w * (1.0 + ee);
+  const double Ed = a.linear ? -g * en : -g * en - 0.5 * (px * px + py * py) + 0.5 * w * w * (1.0 + ee);
   const double ms = ws * det;
   const double sk = scatter(nk, hn, ms * Ek, fl);
   const double sd = scatter(nd, hn, ms * Ed, fl);

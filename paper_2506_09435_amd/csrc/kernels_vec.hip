@@ -335,6 +335,16 @@ __global__ void k_lincomb(double *out, double a, const double *x, double b, cons
     out[i] = (x ? a * x[i] : 0.0) + (y ? b * y[i] : 0.0);
 }
 
+// VJP of the linear free-surface conditions (d eta/dt = w, d phi_s/dt = -g eta):
+// eta_bar += -g kbar_p, w_bar += kbar_e
+__global__ void k_rhs_vjp_linear(const double *kbe, const double *kbp, double *eta_bar, double *w_bar, double g,
+                                 int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    eta_bar[i] -= g * kbp[i];
+    w_bar[i] += kbe[i];
+  }
+}
+
 __global__ void k_relax_vjp(double *v, const double *cr, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     v[i] *= (1.0 - cr[i]);
@@ -352,6 +362,12 @@ __global__ void k_surface_adj(double *phis_bar, const double *phibar, const doub
 hipError_t launch_lincomb(double *out, double a, const double *x, double b, const double *y, int64_t n,
                           hipStream_t s) {
   k_lincomb<<<kVecBlocks, kVecThreads, 0, s>>>(out, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_vjp_linear(const double *kbe, const double *kbp, double *eta_bar, double *w_bar, double g,
+                                 int64_t n, hipStream_t s) {
+  k_rhs_vjp_linear<<<kVecBlocks, kVecThreads, 0, s>>>(kbe, kbp, eta_bar, w_bar, g, n);
   return hipGetLastError();
 }
 

@@ -72,6 +72,7 @@ SIGNATURES = {
     "fnpf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_w_surface": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fnpf_set_linear": (C.c_int, [C.c_void_p, C.c_int32]),
     "fnpf_set_relaxation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_double, C.c_double]),
     "fnpf_rk4_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
@@ -265,6 +266,10 @@ class Context:
         self._check(lib().fnpf_rhs(self._h, _ptr(eta, torch.float64), _ptr(phi_s, torch.float64),
                                    _ptr(w, torch.float64), _ptr(de), _ptr(dp), _stream(stream)), "fnpf_rhs")
         return de, dp
+
+    def set_linear(self, linear=True):
+        """Linear potential flow (fixed domain at eta = 0, linear free-surface conditions)."""
+        self._check(lib().fnpf_set_linear(self._h, int(bool(linear))), "fnpf_set_linear")
 
     def set_relaxation(self, cr, eta_c, eta_s, phi_c, phi_s, omega, t_ramp):
         if cr is None:

@@ -222,6 +222,61 @@ def test_rk4_relaxation_parity():
     assert rel(host(e), eta) < 1e-10 and rel(host(p), phi) < 1e-10
 
 
+@pytest.mark.parametrize("name", ["slice_periodic", "box_mixed", "cylinder"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lpf_rk4_steps_parity(name, precision):
+    """Linear potential flow: three ERK4 steps against the oracle's linear model."""
+    wl = _case(name)
+    pr = Pair(wl, fp32=precision == 1)
+    pr.ctx.set_linear(True)
+    md = ts.Model(wl, solver="dense", linear=True)
+    dt = 0.02
+    eta, phi = pr.eta, pr.phis
+    e, p = pr.d_eta.clone(), pr.d_phis.clone()
+    opts = fnpf.default_opts(precision=precision, rtol=1e-13 if precision == 0 else 1e-12, inner_rtol=1e-3)
+    t = 0.0
+    for n in range(3):
+        eta, phi = md.rk4_step(eta, phi, t, dt)
+        infos = pr.ctx.rk4_step(e, p, pr.d_h, t, dt, opts=opts)
+        assert all(i["rel_res"] <= opts.rtol for i in infos)
+        t += dt
+    tol = 1e-10 if precision == 0 else 1e-8
+    assert rel(host(e), eta) < tol and rel(host(p), phi) < tol
+    # the linear and the nonlinear models differ at this amplitude
+    en, _ = ts.Model(wl, solver="dense").rk4_step(pr.eta, pr.phis, 0.0, dt)
+    e1, _ = md.rk4_step(pr.eta, pr.phis, 0.0, dt)
+    assert rel(e1, en) > 1e-6
+
+
+def test_lpf_rhs_and_relaxation_parity():
+    """Linear RHS is (w, -g eta) pointwise; LPF steps with relaxation zones match the oracle."""
+    wl = configs.c4(nx=8, ny=2, nz=2, p=3, nsteps=3)
+    pr = Pair(wl)
+    pr.ctx.set_linear(True)
+    rng = np.random.default_rng(8)
+    eta = 0.01 * np.cos(2 * np.pi * pr.x / 9.5) + 0.001 * rng.standard_normal(pr.m.n_s)
+    phi = 0.02 * np.sin(2 * np.pi * pr.x / 9.5)
+    w = rng.standard_normal(pr.m.n_s)
+    de, dp = pr.ctx.rhs(dev(eta), dev(phi), dev(w))
+    assert rel(host(de), w) < 1e-14 and rel(host(dp), -wl.g * eta) < 1e-14
+    ra = wl.relaxation_arrays(pr.x, pr.y)
+    pr.ctx.set_relaxation(*ra, omega=wl.relax_wave.omega, t_ramp=wl.t_ramp)
+    md = ts.Model(wl, solver="dense", linear=True)
+    e, p = dev(eta), dev(phi)
+    t = 0.3
+    for n in range(3):
+        eta, phi = md.rk4_step(eta, phi, t, wl.dt)
+        pr.ctx.rk4_step(e, p, pr.d_h, t, wl.dt, opts=fnpf.default_opts(rtol=1e-13))
+        t += wl.dt
+    assert rel(host(e), eta) < 1e-10 and rel(host(p), phi) < 1e-10
+    # switching back restores the nonlinear model
+    pr.ctx.set_linear(False)
+    md_nl = ts.Model(wl, solver="dense")
+    e2, p2 = md_nl.rk4_step(eta, phi, t, wl.dt)
+    pr.ctx.rk4_step(e, p, pr.d_h, t, wl.dt, opts=fnpf.default_opts(rtol=1e-13))
+    assert rel(host(e), e2) < 1e-10 and rel(host(p), p2) < 1e-10
+
+
 @pytest.mark.parametrize("precond", [1, 2])
 def test_c1_full_run(precond):
     """C1: 32 ERK4 steps (one period) of the standing wave; FP64 path vs the oracle (solves at

@@ -26,6 +26,7 @@ from . import geometry as geo
 from . import operator as op
 from . import solve as sv
 from . import surface as sf
+from . import filter as mfl
 from .gll import gll, lagrange_eval
 
 RK4_C = (0.0, 0.5, 0.5, 1.0)
@@ -47,11 +48,14 @@ class Model:
     remark, Sec. 4.1.2): the free surface stays at z = 0, so the Laplace domain is the fixed
     column [-h, 0], and the kinematic and dynamic conditions (Eqs. 2-3) keep only their
     linear terms, d eta/dt = w and d phi_s/dt = -g eta.
+    ``modal_filter``: None, or (cutoff, alpha, order) of the modal filter of Sec. 3.2
+    (oracle/filter.py), applied to eta and phi_s after every full step (after relaxation).
     """
 
-    def __init__(self, workload, solver="dense", rtol=1e-13, linear=False):
+    def __init__(self, workload, solver="dense", rtol=1e-13, linear=False, modal_filter=None):
         self.wl = workload
         self.linear = linear
+        self.modal_filter = modal_filter
         self.mesh = workload.mesh
         self.g = workload.g
         self.solver = solver
@@ -129,7 +133,11 @@ class Model:
                 tape.append(phi)
             acc_e = acc_e + RK4_B[s] * dt * ke
             acc_p = acc_p + RK4_B[s] * dt * kp
-        return self.relax_apply(eta + acc_e, phi_s + acc_p, t + dt)
+        eta1, phi1 = self.relax_apply(eta + acc_e, phi_s + acc_p, t + dt)
+        if self.modal_filter is not None:
+            eta1 = mfl.modal_filter(self.mesh, eta1, *self.modal_filter)
+            phi1 = mfl.modal_filter(self.mesh, phi1, *self.modal_filter)
+        return eta1, phi1
 
     def run(self, nsteps=None, dt=None, eta=None, phi_s=None, h=None, callback=None):
         nsteps = self.wl.nsteps if nsteps is None else nsteps

@@ -262,6 +262,26 @@ fnpf_status fnpf_rhs(fnpf_ctx ctx, const double *eta, const double *phi_s, const
 fnpf_status fnpf_set_relaxation(fnpf_ctx ctx, const double *cr, const double *eta_c, const double *eta_s,
                                 const double *phi_c, const double *phi_s_, double omega, double t_ramp);
 
+/* Modal filter of surface fields (Sec. 3.2, modal filtering; the paper's
+ * triangles become tensor-product quads/intervals here).  Per surface
+ * element, nodal values -> modal coefficients in the orthonormal Legendre
+ * product basis (inverse Vandermonde at the GLL nodes) -> mode (n, m) scaled
+ * by sigma(n) sigma(m) -> nodal values; a node shared by several elements
+ * takes the mean of their results.  sigma(n) = 1 for n <= cutoff, else
+ * exp(-alpha ((n - cutoff)/(p - cutoff))^order).
+ * fnpf_set_modal_filter sets the filter (0 <= cutoff < p, alpha >= 0,
+ * order >= 1); cutoff < 0 removes it.  While set, fnpf_rk4_step filters eta
+ * and phi_s after every step (after relaxation) and fnpf_rk4_step_vjp applies
+ * the transpose first.  Errors: ARG for parameters out of range. */
+fnpf_status fnpf_set_modal_filter(fnpf_ctx ctx, int32_t cutoff, double alpha, int32_t order);
+
+/* out[n_s] = filtered f[n_s] (device FP64, out must not alias f).
+ * Errors: STATE if no filter is set. */
+fnpf_status fnpf_modal_filter(fnpf_ctx ctx, const double *f, double *out, void *stream);
+
+/* VJP of fnpf_modal_filter: f_bar (+=) [n_s] from out_bar [n_s] (no aliasing). */
+fnpf_status fnpf_modal_filter_vjp(fnpf_ctx ctx, const double *out_bar, double *f_bar, void *stream);
+
 /* Linear potential flow (the linearised model of Sec. 2.1, small-amplitude
  * limit of Eqs. 2-3): linear != 0 makes fnpf_rk4_step, fnpf_rk4_step_vjp,
  * fnpf_rhs and fnpf_rhs_vjp use the fixed domain at eta = 0 (the Laplace

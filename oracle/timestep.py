@@ -50,12 +50,16 @@ class Model:
     linear terms, d eta/dt = w and d phi_s/dt = -g eta.
     ``modal_filter``: None, or (cutoff, alpha, order) of the modal filter of Sec. 3.2
     (oracle/filter.py), applied to eta and phi_s after every full step (after relaxation).
+    ``surface_quadrature``: None (lumped GLL collocation of Eq. 5), or nq >= p + 1: the
+    consistent form of Eq. 5 with nq Gauss points per direction (over-integration, Sec. 3.2).
     """
 
-    def __init__(self, workload, solver="dense", rtol=1e-13, linear=False, modal_filter=None):
+    def __init__(self, workload, solver="dense", rtol=1e-13, linear=False, modal_filter=None,
+                 surface_quadrature=None):
         self.wl = workload
         self.linear = linear
         self.modal_filter = modal_filter
+        self.nq = surface_quadrature
         self.mesh = workload.mesh
         self.g = workload.g
         self.solver = solver
@@ -65,6 +69,9 @@ class Model:
         self.x, self.y = geo.node_xy(self.mesh)
         self.h = np.asarray(workload.depth(self.x, self.y), dtype=np.float64)
         self.metrics = sf.surface_metrics(self.mesh, self.xh)
+        if self.nq:
+            self.quad = sf.surface_quadrature(self.mesh, self.nq, self.xh)
+            self.mass_c = sf.consistent_surface_mass(self.mesh, self.nq, self.xh)
         self.ms = np.bincount(self.mesh.eh_nodes.ravel(), weights=self.metrics[1].ravel(), minlength=self.mesh.n_s)
         self.dofs = geo.dof_map(self.mesh)
         ra = workload.relaxation_arrays(self.x, self.y)
@@ -100,7 +107,11 @@ class Model:
             return w, -self.g * np.asarray(eta), phi, w
         phi = self.laplace(eta, phi_s, h, phi_guess)
         w = sf.w_surface(self.mesh, phi, eta, h, self.xh)
-        deta, dphi = sf.free_surface_rhs(self.mesh, eta, phi_s, w, self.g, metrics=self.metrics)
+        if self.nq:
+            deta, dphi = sf.free_surface_rhs_consistent(self.mesh, eta, phi_s, w, self.g, self.nq,
+                                                        quad=self.quad, mass=self.mass_c)
+        else:
+            deta, dphi = sf.free_surface_rhs(self.mesh, eta, phi_s, w, self.g, metrics=self.metrics)
         return deta, dphi, phi, w
 
     def relax_apply(self, eta, phi_s, t):

@@ -68,6 +68,10 @@ void free_all(Ctx &c) {
   free_graphs(c);
   dfree(c.d_flat);
   dfree(c.d_scr_s);
+  dfree(c.d_filt_M);
+  dfree(c.d_filt_inv_mult);
+  dfree(c.d_filt_acc);
+  dfree(c.d_filt_tmp);
   if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
   c.cap_stream = nullptr;
   mg_free(c);
@@ -796,6 +800,55 @@ fnpf_status fnpf_set_linear(fnpf_ctx ctx, int32_t linear) {
   return FNPF_OK;
 }
 
+fnpf_status fnpf_set_modal_filter(fnpf_ctx ctx, int32_t cutoff, double alpha, int32_t order) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (cutoff < 0) {
+    c.filter_cutoff = -1;
+    return FNPF_OK;
+  }
+  if (cutoff >= c.p) return fail(&c, FNPF_ERR_ARG, "modal filter cutoff must satisfy 0 <= cutoff < p");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(&c, FNPF_ERR_ARG, "modal filter alpha must be >= 0");
+  if (order < 1) return fail(&c, FNPF_ERR_ARG, "modal filter order must be >= 1");
+  const int n1 = c.p + 1;
+  if (!c.d_filt_M) {
+    std::vector<double> inv(c.n_s, 0.0);
+    for (int32_t v : c.h_eh_nodes) inv[v] += 1.0;
+    for (auto &x : inv) x = 1.0 / x;
+    HIPCHK(upload(&c.d_filt_inv_mult, inv.data(), inv.size()));
+    HIPCHK(dalloc(&c.d_filt_M, (size_t)n1 * n1));
+    HIPCHK(dalloc(&c.d_filt_acc, c.n_s));
+    HIPCHK(dalloc(&c.d_filt_tmp, c.n_s));
+  }
+  std::vector<double> M((size_t)n1 * n1);
+  modal_filter_matrix(c.p, cutoff, alpha, order, M.data());
+  HIPCHK(hipMemcpy(c.d_filt_M, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice));
+  c.filter_cutoff = cutoff;
+  c.filter_alpha = alpha;
+  c.filter_order = order;
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_modal_filter(fnpf_ctx ctx, const double *f, double *out, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!f || !out) return fail(&c, FNPF_ERR_ARG, "fnpf_modal_filter: null device pointer");
+  if (f == out) return fail(&c, FNPF_ERR_ARG, "fnpf_modal_filter: out must not alias f");
+  if (c.filter_cutoff < 0) return fail(&c, FNPF_ERR_STATE, "fnpf_modal_filter: no filter set");
+  HIPCHK(launch_modal_filter(c, f, out, false, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_modal_filter_vjp(fnpf_ctx ctx, const double *out_bar, double *f_bar, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!out_bar || !f_bar) return fail(&c, FNPF_ERR_ARG, "fnpf_modal_filter_vjp: null device pointer");
+  if (out_bar == f_bar) return fail(&c, FNPF_ERR_ARG, "fnpf_modal_filter_vjp: f_bar must not alias out_bar");
+  if (c.filter_cutoff < 0) return fail(&c, FNPF_ERR_STATE, "fnpf_modal_filter_vjp: no filter set");
+  HIPCHK(launch_modal_filter(c, out_bar, f_bar, true, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
 fnpf_status fnpf_set_relaxation(fnpf_ctx ctx, const double *cr, const double *ec, const double *es, const double *pc,
                                 const double *ps, double omega, double t_ramp) {
   if (!ctx) return FNPF_ERR_ARG;
@@ -903,6 +956,14 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
     ein = a.out_e;
     pin = a.out_p;
   }
+  if (c.filter_cutoff >= 0) {
+    // modal filter of the new surface state, after relaxation
+    double *fields[2] = {eta, phis};
+    for (double *f : fields) {
+      HIPCHK(launch_modal_filter(c, f, c.d_filt_tmp, false, s));
+      HIPCHK(hipMemcpyAsync(f, c.d_filt_tmp, c.n_s * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  }
   if (o.extrapolate) {
     // the slot written this step becomes the newest
     c.hist_head = 1 - c.hist_head;
@@ -995,7 +1056,16 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
   if (info) std::memset(info, 0, 4 * sizeof(fnpf_solve_info));
   const size_t rec = (size_t)c.n_v + 2 * (size_t)c.n_s;
   const int64_t ns = c.n_s;
-  // relaxation acted last: y_{n+1} = (1 - C_r) (y_n + sum b dt k) + C_r f_true(t + dt)
+  if (c.filter_cutoff >= 0) {
+    // the modal filter acted last: ybar <- F^T ybar
+    double *bars[2] = {eta_bar, phis_bar};
+    for (double *b : bars) {
+      HIPCHK(launch_fill(c.d_filt_tmp, 0.0, ns, s));
+      HIPCHK(launch_modal_filter(c, b, c.d_filt_tmp, true, s));
+      HIPCHK(hipMemcpyAsync(b, c.d_filt_tmp, ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  // relaxation acted before: y_{n+1} = (1 - C_r) (y_n + sum b dt k) + C_r f_true(t + dt)
   if (c.have_relax) {
     HIPCHK(launch_relax_vjp(eta_bar, c.d_cr, ns, s));
     HIPCHK(launch_relax_vjp(phis_bar, c.d_cr, ns, s));

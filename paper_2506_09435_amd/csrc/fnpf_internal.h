@@ -90,6 +90,9 @@ hipError_t launch_geom_vjp(Ctx &c, const double *lam, const double *phi, double 
                            hipStream_t s);
 
 // vector kernels (kernels_vec.hip)
+// modal filter (forward: out = W (M x M) in, out != in; transpose: in_bar += (M x M)^T W out_bar)
+hipError_t launch_modal_filter(Ctx &c, const double *in, double *out, bool transpose, hipStream_t s);
+void modal_filter_matrix(int p, int cutoff, double alpha, int order, double *M);
 hipError_t launch_rhs_vjp_linear(const double *kbe, const double *kbp, double *eta_bar, double *w_bar, double g,
                                  int64_t n, hipStream_t s);
 hipError_t launch_lincomb(double *out, double a, const double *x, double b, const double *y, int64_t n,
@@ -248,6 +251,13 @@ struct Ctx {
   hipStream_t cap_stream = nullptr;       // capture-only stream (default priority)
   double *d_mask = nullptr;               // 1 below the surface level, 0 on it (no preconditioner)
   float *d_mask32 = nullptr;
+  // modal filter of the surface fields (cutoff < 0: off)
+  int filter_cutoff = -1, filter_order = 0;
+  double filter_alpha = 0.0;
+  double *d_filt_M = nullptr;             // [(p+1)^2] nodal 1D filter matrix M[i*(p+1)+k]
+  double *d_filt_inv_mult = nullptr;      // [n_s] 1 / number of surface elements at the node
+  double *d_filt_acc = nullptr;           // [n_s] colour-ordered accumulation
+  double *d_filt_tmp = nullptr;           // [n_s] filtered copy before write-back
   // linear potential flow (flat geometry at eta = 0, linear free-surface conditions)
   bool linear = false;
   double *d_flat = nullptr;               // [n_s] zeros: the LPF surface

@@ -1697,6 +1697,88 @@ hipError_t launch_rhs(Ctx &c, const double *eta, const double *phi_s, const doub
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Modal filter of a surface field (Sec. 3.2, modal filtering), tensor-product form on one
+// surface element: the nodal filter matrix M = V diag(sigma) V^-1 acts along xi and then along
+// eta (one direction in 2D).  Shared nodes take the mean of the element results (colour-ordered
+// accumulation, scaled by 1/multiplicity by the last writer).  TR: the transpose map, which
+// scales by 1/multiplicity first, applies M^T and adds the sums into out.
+// ---------------------------------------------------------------------------------------------
+template <int P, int DIM, bool TR>
+__global__ __launch_bounds__(256) void k_modal_filter(const double *__restrict__ in, double *__restrict__ out,
+                                                      const int32_t *__restrict__ eh_nodes,
+                                                      const uint8_t *__restrict__ flags,
+                                                      const int32_t *__restrict__ cols, int ncols,
+                                                      const double *__restrict__ Mg,
+                                                      const double *__restrict__ inv_mult,
+                                                      double *__restrict__ acc) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, CPB = S::CPB;
+  __shared__ double sM[N1 * N1];
+  __shared__ double sg[CPB * NH];
+  __shared__ double st[CPB * NH];
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  const bool active = ci < ncols;
+  const int col = active ? cols[ci] : 0;
+  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
+  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
+  if (threadIdx.x < N1 * N1) {
+    // stored transposed for the TR map: A[r][k] = M[k][r]
+    const int r = threadIdx.x / N1, k = threadIdx.x - r * N1;
+    sM[threadIdx.x] = TR ? Mg[k * N1 + r] : Mg[threadIdx.x];
+  }
+  double g = active ? in[hn] : 0.0;
+  if (TR && active) g *= inv_mult[hn];
+  sg[lc * NH + t] = g;
+  __syncthreads();
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < N1; ++k) v += sM[i * N1 + k] * sg[lc * NH + j * N1 + k];
+  if constexpr (DIM == 3) {
+    st[lc * NH + t] = v;
+    __syncthreads();
+    v = 0.0;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) v += sM[j * N1 + k] * st[lc * NH + k * N1 + i];
+  }
+  if (!active) return;
+  const double sum = scatter(acc, hn, v, fl);
+  if (fl & kLast) {
+    if (TR)
+      out[hn] += sum;
+    else
+      out[hn] = sum * inv_mult[hn];
+  }
+}
+
+template <int P, int DIM>
+static hipError_t modal_filter_impl(Ctx &c, const double *in, double *out, bool tr, hipStream_t s) {
+  using S = Sh<P, DIM>;
+  for (const auto &cr : c.colours) {
+    if (cr.count == 0) continue;
+    const int nb = (cr.count + S::CPB - 1) / S::CPB;
+    if (tr)
+      k_modal_filter<P, DIM, true><<<nb, S::NT, 0, s>>>(in, out, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
+                                                        cr.count, c.d_filt_M, c.d_filt_inv_mult, c.d_filt_acc);
+    else
+      k_modal_filter<P, DIM, false><<<nb, S::NT, 0, s>>>(in, out, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
+                                                         cr.count, c.d_filt_M, c.d_filt_inv_mult, c.d_filt_acc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_modal_filter(Ctx &c, const double *in, double *out, bool transpose, hipStream_t s) {
+  if (c.dim == 3) {
+    FNPF_DISPATCH(3, c.p, return (modal_filter_impl<P_, 3>(c, in, out, transpose, s)));
+  } else {
+    FNPF_DISPATCH(2, c.p, return (modal_filter_impl<P_, 2>(c, in, out, transpose, s)));
+  }
+  return hipSuccess;
+}
+
 #include "adjoint_kernels.inc"
 
 }  // namespace fnpf

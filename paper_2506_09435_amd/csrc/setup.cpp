@@ -41,6 +41,45 @@ static void legendre_pair(int p, double x, double &pp, double &pm) {
   pm = a;
 }
 
+// Nodal 1D filter matrix M = V diag(sigma) V^-1 (Sec. 3.2, modal filtering) with
+// V[i][n] = Pt_n(x_i), Pt_n = sqrt((2n+1)/2) P_n, at the GLL nodes x_i.  V^-1 follows from the
+// discrete orthogonality of the GLL rule: sum_i w_i Pt_n(x_i) Pt_m(x_i) = gamma_n delta_nm with
+// gamma_n = 1 for n < p and gamma_p = (2p+1)/p (the rule integrates Pt_p^2 inexactly), so
+// V^-1[n][i] = w_i Pt_n(x_i) / gamma_n.  sigma: the exponential filter, 1 up to the cutoff,
+// exp(-alpha ((n - cutoff)/(p - cutoff))^order) above.
+void modal_filter_matrix(int p, int cutoff, double alpha, int order, double *M) {
+  const int n1 = p + 1;
+  std::vector<double> x(n1), w(n1), D((size_t)n1 * n1), V((size_t)n1 * n1), sig(n1);
+  gll_host(p, x.data(), w.data(), D.data());
+  for (int i = 0; i < n1; ++i) {
+    double pm = 1.0, pc = x[i];   // P_0, P_1
+    for (int n = 0; n < n1; ++n) {
+      double pn;
+      if (n == 0) {
+        pn = 1.0;
+      } else if (n == 1) {
+        pn = x[i];
+      } else {
+        pn = ((2.0 * n - 1.0) * x[i] * pc - (n - 1.0) * pm) / n;
+        pm = pc;
+        pc = pn;
+      }
+      V[(size_t)i * n1 + n] = std::sqrt((2.0 * n + 1.0) / 2.0) * pn;
+    }
+  }
+  for (int n = 0; n < n1; ++n)
+    sig[n] = n <= cutoff ? 1.0 : std::exp(-alpha * std::pow((double)(n - cutoff) / (p - cutoff), order));
+  for (int i = 0; i < n1; ++i)
+    for (int k = 0; k < n1; ++k) {
+      double a = 0.0;
+      for (int n = 0; n < n1; ++n) {
+        const double gam = n < p ? 1.0 : (2.0 * p + 1.0) / p;
+        a += V[(size_t)i * n1 + n] * sig[n] * w[k] * V[(size_t)k * n1 + n] / gam;
+      }
+      M[(size_t)i * n1 + k] = a;
+    }
+}
+
 void gll_host(int p, double *x, double *w, double *D) {
   const int n1 = p + 1;
   std::vector<double> xs(n1);

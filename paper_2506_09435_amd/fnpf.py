@@ -73,6 +73,9 @@ SIGNATURES = {
     "fnpf_w_surface": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_set_linear": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fnpf_set_modal_filter": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_int32]),
+    "fnpf_modal_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fnpf_modal_filter_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_set_relaxation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_double, C.c_double]),
     "fnpf_rk4_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
@@ -270,6 +273,24 @@ class Context:
     def set_linear(self, linear=True):
         """Linear potential flow (fixed domain at eta = 0, linear free-surface conditions)."""
         self._check(lib().fnpf_set_linear(self._h, int(bool(linear))), "fnpf_set_linear")
+
+    def set_modal_filter(self, cutoff, alpha=0.0, order=1):
+        """Modal filter (cutoff < 0 removes it); rk4_step filters eta and phi_s while it is set."""
+        self._check(lib().fnpf_set_modal_filter(self._h, int(cutoff), float(alpha), int(order)),
+                    "fnpf_set_modal_filter")
+
+    def modal_filter(self, f, stream=None):
+        import torch
+        out = torch.empty(self.n_s, dtype=torch.float64, device=self.device)
+        self._check(lib().fnpf_modal_filter(self._h, _ptr(f, torch.float64), _ptr(out), _stream(stream)),
+                    "fnpf_modal_filter")
+        return out
+
+    def modal_filter_vjp(self, out_bar, f_bar, stream=None):
+        import torch
+        self._check(lib().fnpf_modal_filter_vjp(self._h, _ptr(out_bar, torch.float64), _ptr(f_bar, torch.float64),
+                                                _stream(stream)), "fnpf_modal_filter_vjp")
+        return f_bar
 
     def set_relaxation(self, cr, eta_c, eta_s, phi_c, phi_s, omega, t_ramp):
         if cr is None:

@@ -262,6 +262,26 @@ fnpf_status fnpf_rhs(fnpf_ctx ctx, const double *eta, const double *phi_s, const
 fnpf_status fnpf_set_relaxation(fnpf_ctx ctx, const double *cr, const double *eta_c, const double *eta_s,
                                 const double *phi_c, const double *phi_s_, double omega, double t_ramp);
 
+/* Free-surface form (Eq. 5; over-integration, Sec. 3.2).  nq = 0 (default):
+ * collocated GLL quadrature with the lumped surface mass, so the RHS is
+ * pointwise.  p + 1 <= nq <= 24: the consistent form; the integrands of
+ * Eqs. 2-3 are evaluated at nq Gauss-Legendre points per direction of each
+ * surface element and tested against the Lagrange basis, and the consistent
+ * surface mass system is solved for d eta/dt and d phi_s/dt by a fixed-length
+ * Chebyshev iteration preconditioned with the lumped mass (its interval is
+ * bounded from the element Jacobians; the length gives a 1e-15 contraction).
+ * nq >= (5p - 1)/2 integrates every term exactly on affine elements.  Used by
+ * fnpf_rhs, fnpf_rhs_vjp, fnpf_rk4_step and fnpf_rk4_step_vjp; ignored in
+ * linear mode, whose integrands lie in the discrete space (both forms agree).
+ * Synchronises the device.  Errors: ARG for nq out of range, GEOM for a
+ * non-positive Jacobian at a Gauss point. */
+fnpf_status fnpf_set_surface_quadrature(fnpf_ctx ctx, int32_t nq);
+
+/* Current nq, Chebyshev iteration count and eigenvalue interval of the
+ * consistent surface solve (any pointer may be NULL). */
+fnpf_status fnpf_surface_quadrature_info(fnpf_ctx ctx, int32_t *nq, int32_t *iters, double *lam_lo,
+                                         double *lam_hi);
+
 /* Modal filter of surface fields (Sec. 3.2, modal filtering; the paper's
  * triangles become tensor-product quads/intervals here).  Per surface
  * element, nodal values -> modal coefficients in the orthonormal Legendre

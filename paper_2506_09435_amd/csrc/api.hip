@@ -68,6 +68,7 @@ void free_all(Ctx &c) {
   free_graphs(c);
   dfree(c.d_flat);
   dfree(c.d_scr_s);
+  sq_free(c);
   dfree(c.d_filt_M);
   dfree(c.d_filt_inv_mult);
   dfree(c.d_filt_acc);
@@ -210,6 +211,32 @@ fnpf_status ensure_flat(Ctx &c, hipStream_t s) {
   HIPCHK(dalloc(&c.d_scr_s, c.n_s));
   HIPCHK(launch_fill(c.d_flat, 0.0, c.n_s, s));
   return FNPF_OK;
+}
+
+bool consistent_surface(const Ctx &c) { return c.sq_nq > 0 && !c.linear; }
+
+// Free-surface RHS of one stage (lumped: fused kernel; consistent: quadrature, mass solve, stage update)
+hipError_t stage_rhs(Ctx &c, const double *eta, const double *phs, const double *w, const RkStageArgs &a,
+                     hipStream_t s) {
+  if (!consistent_surface(c)) return launch_rhs(c, eta, phs, w, a, s);
+  hipError_t e = launch_sq_rhs(c, eta, phs, w, c.d_sq_b, s);
+  if (e != hipSuccess) return e;
+  e = sq_solve(c, c.d_sq_b, c.d_sq_x, s);
+  if (e != hipSuccess) return e;
+  return launch_sq_stage(a, c.d_sq_x, c.n_s, s);
+}
+
+// VJP of the free-surface RHS: adds to eta_bar, phis_bar, w_bar from kbar_e, kbar_p
+hipError_t stage_rhs_vjp(Ctx &c, const double *eta, const double *phs, const double *w, const double *kbe,
+                         const double *kbp, double *eta_bar, double *phis_bar, double *w_bar, hipStream_t s) {
+  if (c.linear) return launch_rhs_vjp_linear(kbe, kbp, eta_bar, w_bar, c.g, c.n_s, s);
+  if (!consistent_surface(c)) return launch_rhs_vjp(c, eta, phs, w, kbe, kbp, eta_bar, phis_bar, w_bar, s);
+  // the fixed-length Chebyshev solve is a symmetric map, so bbar = S kbar
+  hipError_t e = launch_sq_pack(kbe, kbp, c.d_sq_b, c.n_s, s);
+  if (e != hipSuccess) return e;
+  e = sq_solve(c, c.d_sq_b, c.d_sq_x, s);
+  if (e != hipSuccess) return e;
+  return launch_sq_rhs_vjp(c, eta, phs, w, c.d_sq_x, eta_bar, phis_bar, w_bar, s);
 }
 
 fnpf_status check_err_flag(Ctx &c, hipStream_t s) {
@@ -790,13 +817,42 @@ fnpf_status fnpf_rhs(fnpf_ctx ctx, const double *eta, const double *phis, const 
   a.stage = -1;
   a.out_e = deta;
   a.out_p = dphi;
-  HIPCHK(launch_rhs(c, eta, phis, w, a, (hipStream_t)stream));
+  HIPCHK(stage_rhs(c, eta, phis, w, a, (hipStream_t)stream));
   return FNPF_OK;
 }
 
 fnpf_status fnpf_set_linear(fnpf_ctx ctx, int32_t linear) {
   if (!ctx) return FNPF_ERR_ARG;
   ctx->c.linear = linear != 0;
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_set_surface_quadrature(fnpf_ctx ctx, int32_t nq) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (nq == 0) {
+    sq_free(c);
+    return FNPF_OK;
+  }
+  if (nq < c.p + 1 || nq > kMaxSurfaceNq)
+    return fail(&c, FNPF_ERR_ARG, "surface quadrature: nq must be 0 or in [p + 1, 24]");
+  HIPCHK(hipDeviceSynchronize());   // tables may be in use by queued work
+  const char *err = sq_setup(c, nq);
+  if (err) {
+    sq_free(c);
+    return fail(&c, std::strstr(err, "Jacobian") ? FNPF_ERR_GEOM : FNPF_ERR_ALLOC, err);
+  }
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_surface_quadrature_info(fnpf_ctx ctx, int32_t *nq, int32_t *iters, double *lam_lo,
+                                         double *lam_hi) {
+  if (!ctx) return FNPF_ERR_ARG;
+  const Ctx &c = ctx->c;
+  if (nq) *nq = c.sq_nq;
+  if (iters) *iters = c.sq_iters;
+  if (lam_lo) *lam_lo = c.sq_lo;
+  if (lam_hi) *lam_hi = c.sq_hi;
   return FNPF_OK;
 }
 
@@ -952,7 +1008,7 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
         a.rs = r * std::sin(c.relax_omega * tn);
       }
     }
-    HIPCHK(launch_rhs(c, ein, pin, c.d_w, a, s));
+    HIPCHK(stage_rhs(c, ein, pin, c.d_w, a, s));
     ein = a.out_e;
     pin = a.out_p;
   }
@@ -981,10 +1037,7 @@ fnpf_status fnpf_rhs_vjp(fnpf_ctx ctx, const double *eta, const double *phis, co
   Ctx &c = ctx->c;
   if (!eta || !phis || !w || !deta_bar || !dphi_bar || !eta_bar || !phis_bar || !w_bar)
     return fail(&c, FNPF_ERR_ARG, "fnpf_rhs_vjp: null device pointer");
-  if (c.linear)
-    HIPCHK(launch_rhs_vjp_linear(deta_bar, dphi_bar, eta_bar, w_bar, c.g, c.n_s, (hipStream_t)stream));
-  else
-    HIPCHK(launch_rhs_vjp(c, eta, phis, w, deta_bar, dphi_bar, eta_bar, phis_bar, w_bar, (hipStream_t)stream));
+  HIPCHK(stage_rhs_vjp(c, eta, phis, w, deta_bar, dphi_bar, eta_bar, phis_bar, w_bar, (hipStream_t)stream));
   return FNPF_OK;
 }
 
@@ -1094,10 +1147,7 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
     HIPCHK(launch_fill(c.d_ybe, 0.0, ns, s));
     HIPCHK(launch_fill(c.d_ybp, 0.0, ns, s));
     HIPCHK(launch_fill(c.d_wbar, 0.0, ns, s));
-    if (c.linear)
-      HIPCHK(launch_rhs_vjp_linear(c.d_kbe, c.d_kbp, c.d_ybe, c.d_wbar, c.g, ns, s));
-    else
-      HIPCHK(launch_rhs_vjp(c, eta_s, pin_s, c.d_w, c.d_kbe, c.d_kbp, c.d_ybe, c.d_ybp, c.d_wbar, s));
+    HIPCHK(stage_rhs_vjp(c, eta_s, pin_s, c.d_w, c.d_kbe, c.d_kbp, c.d_ybe, c.d_ybp, c.d_wbar, s));
     HIPCHK(launch_fill(c.d_phibar, 0.0, c.n_v, s));
     HIPCHK(launch_wsurf_vjp(c, c.d_wbar, c.d_w, c.d_phibar, geo_eta_bar, h_bar, s));
     st = solve_impl(c, c.d_zero_s, c.d_phibar, c.d_lam, o, info ? info + stg : nullptr, s);

@@ -90,6 +90,16 @@ hipError_t launch_geom_vjp(Ctx &c, const double *lam, const double *phi, double 
                            hipStream_t s);
 
 // vector kernels (kernels_vec.hip)
+// consistent over-integrated free-surface form
+constexpr int kMaxSurfaceNq = 24;
+const char *sq_setup(Ctx &c, int nq);
+void sq_free(Ctx &c);
+hipError_t launch_sq_rhs(Ctx &c, const double *eta, const double *phs, const double *w, double *b, hipStream_t s);
+hipError_t launch_sq_rhs_vjp(Ctx &c, const double *eta, const double *phs, const double *w, const double *bbar,
+                             double *eta_bar, double *phi_bar, double *w_bar, hipStream_t s);
+hipError_t sq_solve(Ctx &c, const double *b, double *x, hipStream_t s);
+hipError_t launch_sq_stage(const RkStageArgs &a, const double *k2, int64_t n_s, hipStream_t s);
+hipError_t launch_sq_pack(const double *a, const double *b, double *out, int64_t n_s, hipStream_t s);
 // modal filter (forward: out = W (M x M) in, out != in; transpose: in_bar += (M x M)^T W out_bar)
 hipError_t launch_modal_filter(Ctx &c, const double *in, double *out, bool transpose, hipStream_t s);
 void modal_filter_matrix(int p, int cutoff, double alpha, int order, double *M);
@@ -251,6 +261,13 @@ struct Ctx {
   hipStream_t cap_stream = nullptr;       // capture-only stream (default priority)
   double *d_mask = nullptr;               // 1 below the surface level, 0 on it (no preconditioner)
   float *d_mask32 = nullptr;
+  // consistent over-integrated free-surface form (sq_nq = 0: lumped GLL collocation)
+  int sq_nq = 0, sq_iters = 0;
+  double sq_lo = 0.0, sq_hi = 0.0;        // Chebyshev interval of M_L^{-1} M
+  double *d_sq_B = nullptr, *d_sq_Bd = nullptr;   // [nq][p+1] Lagrange values / derivatives at Gauss points
+  double *d_sq_met = nullptr;             // [5 | 2][n_eh * nq^(dim-1)]: J^{-1} entries, W det J
+  double *d_sq_b = nullptr, *d_sq_x = nullptr, *d_sq_r = nullptr, *d_sq_d = nullptr, *d_sq_ad = nullptr;  // [2][n_s]
+  double *d_sq_scr = nullptr;             // [3][n_s] VJP accumulation
   // modal filter of the surface fields (cutoff < 0: off)
   int filter_cutoff = -1, filter_order = 0;
   double filter_alpha = 0.0;

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fnpf_internal.h"
+#include "stage_update.h"
 
 namespace fnpf {
 
@@ -1443,31 +1444,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ eta, con
   const double sk = scatter(nk, hn, ms * Ek, fl);
   const double sd = scatter(nd, hn, ms * Ed, fl);
   if (!(fl & kLast)) return;
-  const double ke = sk / mlump_s[hn];
-  const double kp = sd / mlump_s[hn];
-  if (a.stage < 0) {
-    a.out_e[hn] = ke;
-    a.out_p[hn] = kp;
-    return;
-  }
-  const double ae = (a.stage == 0 ? 0.0 : a.acc_e[hn]) + a.bdt * ke;
-  const double ap = (a.stage == 0 ? 0.0 : a.acc_p[hn]) + a.bdt * kp;
-  if (a.stage < 3) {
-    a.acc_e[hn] = ae;
-    a.acc_p[hn] = ap;
-    a.out_e[hn] = a.eta0[hn] + a.cdt * ke;
-    a.out_p[hn] = a.phi0[hn] + a.cdt * kp;
-    return;
-  }
-  double ne = a.eta0[hn] + ae;
-  double np = a.phi0[hn] + ap;
-  if (a.cr) {
-    const double c = a.cr[hn];
-    ne = (1.0 - c) * ne + c * (a.rc * a.ec[hn] + a.rs * a.es[hn]);
-    np = (1.0 - c) * np + c * (a.rc * a.pc[hn] + a.rs * a.ps[hn]);
-  }
-  a.out_e[hn] = ne;
-  a.out_p[hn] = np;
+  stage_update(a, hn, sk / mlump_s[hn], sd / mlump_s[hn]);
 }
 
 // ---------------------------------------------------------------------------------------------

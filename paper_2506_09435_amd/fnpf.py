@@ -73,6 +73,9 @@ SIGNATURES = {
     "fnpf_w_surface": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_set_linear": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fnpf_set_surface_quadrature": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fnpf_surface_quadrature_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fnpf_set_modal_filter": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_int32]),
     "fnpf_modal_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_modal_filter_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -273,6 +276,17 @@ class Context:
     def set_linear(self, linear=True):
         """Linear potential flow (fixed domain at eta = 0, linear free-surface conditions)."""
         self._check(lib().fnpf_set_linear(self._h, int(bool(linear))), "fnpf_set_linear")
+
+    def set_surface_quadrature(self, nq):
+        """0: lumped GLL collocation of the free-surface equations; nq >= p+1: consistent form."""
+        self._check(lib().fnpf_set_surface_quadrature(self._h, int(nq)), "fnpf_set_surface_quadrature")
+
+    def surface_quadrature_info(self):
+        nq, it = C.c_int32(), C.c_int32()
+        lo, hi = C.c_double(), C.c_double()
+        self._check(lib().fnpf_surface_quadrature_info(self._h, C.byref(nq), C.byref(it), C.byref(lo), C.byref(hi)),
+                    "fnpf_surface_quadrature_info")
+        return dict(nq=nq.value, iters=it.value, lam_lo=lo.value, lam_hi=hi.value)
 
     def set_modal_filter(self, cutoff, alpha=0.0, order=1):
         """Modal filter (cutoff < 0 removes it); rk4_step filters eta and phi_s while it is set."""

@@ -36,9 +36,9 @@ METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/for
 # HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by the
 # plain-copy calibration), valid only for the kernel source they were taken from.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "628a9e80a66b01a95edd8843357119e25f2093e931c971de680278d88b9ceae5",
-    "fetch_bytes_per_apply": 1152018828,
-    "write_bytes_per_apply": 615123056,
+    "kernel_source_sha256": "ea03e5c5db850d73f4211f7f19e74e678a0cd88cf44c2dd0c51e03a042b3c562",
+    "fetch_bytes_per_apply": 1151818288,
+    "write_bytes_per_apply": 615178876,
 }
 
 
@@ -254,6 +254,63 @@ def adjoint_leg(nsteps, rtol, fd_dirs):
     return out
 
 
+def _time_steps(s, wl, opts, nsteps):
+    import torch
+    s.ctx.set_warm_start(None)
+    e, p, t, _ = run_steps(s, wl, opts, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, iters = run_steps(s, wl, opts, nsteps, t0=t, eta=e, phi=p)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / nsteps, iters
+
+
+def _time_calls(fn, reps):
+    """Median duration of fn() in seconds, HIP events on the current stream."""
+    import numpy as np
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    return float(np.median(times))
+
+
+def extensions_leg(s, wl, opts, nsteps):
+    """Linear potential flow, the modal filter and the consistent free-surface form on the same
+    workload: seconds per mixed-precision ERK4 step, and the filter / consistent RHS alone."""
+    import torch
+    ctx, m = s.ctx, wl.mesh
+    out = {}
+    ctx.set_linear(True)
+    out["lpf_s_per_step"], out["lpf_iters"] = _time_steps(s, wl, opts, nsteps)
+    ctx.set_linear(False)
+    ctx.set_modal_filter(m.p - 2, 4.0, 2)
+    f = s.eta0.clone()
+    t_f = _time_calls(lambda: ctx.modal_filter(f), 20)
+    # per call: read and write n_s doubles, 1/multiplicity, the node ids and flags of every element node
+    fbytes = 3 * 8 * m.n_s + 5 * m.n_eh * m.nh
+    out["filter_ms"] = t_f * 1e3
+    out["filter_gbs"] = fbytes / t_f / 1e9
+    out["filter_s_per_step"], _ = _time_steps(s, wl, opts, nsteps)
+    ctx.set_modal_filter(-1)
+    nq = m.p + 3
+    ctx.set_surface_quadrature(nq)
+    w = torch.zeros_like(s.eta0)
+    out["consistent_nq"] = nq
+    out["consistent_chebyshev_iters"] = ctx.surface_quadrature_info()["iters"]
+    out["consistent_rhs_ms"] = _time_calls(lambda: ctx.rhs(s.eta0, s.phi0, w), 5) * 1e3
+    out["consistent_s_per_step"], _ = _time_steps(s, wl, opts, nsteps)
+    ctx.set_surface_quadrature(0)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +328,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="apply variant (fnpf_set_apply_variant)")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="C4 steps of the adjoint leg (0: skip)")
     ap.add_argument("--adjoint-fd", type=int, default=0, help="finite-difference directions checked in the adjoint leg")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the linear-flow, modal-filter and consistent-surface timings")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -351,6 +410,11 @@ def main():
         t_jac = (time.perf_counter() - t0) / args.steps
         print(f"[bench] mixed Jacobi-PCG step {t_jac:.3f} s, iters {it_jac}", file=sys.stderr, flush=True)
 
+    ext = None
+    if not args.no_extensions:
+        ext = extensions_leg(s, wl, o_mixed, args.steps)
+        print(f"[bench] extensions {ext}", file=sys.stderr, flush=True)
+
     adj = None
     if args.adjoint_steps > 0:
         adj = adjoint_leg(args.adjoint_steps, args.rtol, args.adjoint_fd)
@@ -379,6 +443,7 @@ def main():
         s_per_rk4_step=dict(f64=t_f64, mixed=t_mixed, mixed_jacobi=t_jac),
         pcg_iters_per_stage=dict(f64=it_f64, mixed=it_mixed, mixed_jacobi=it_jac),
         preconditioner="p-multigrid V-cycle (degrees 6, 3, 1; Chebyshev-Jacobi smoothing, degree 2)",
+        extensions=ext,
         adjoint_forward_ratio=None if adj is None else adj["ratio"],
         adjoint=adj,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,

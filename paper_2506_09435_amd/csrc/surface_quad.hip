@@ -13,8 +13,9 @@
 // solve has a fixed length, needs no reductions and is a symmetric linear map of b (its VJP is
 // the same solve).
 //
-// Elements are processed one per workgroup, colour by colour (columns of one colour share no
-// surface node), accumulating shared nodes in colour order like the other surface kernels.
+// Elements are processed up to four per workgroup (one wave each), colour by colour (columns of
+// one colour share no surface node), accumulating shared nodes in colour order like the other
+// surface kernels.
 
 #include <hip/hip_runtime.h>
 
@@ -52,30 +53,37 @@ struct Carve {
   }
 };
 
-// Forward: b_k, b_d (colour-accumulated, final at the last writer) of one element.
+// Every kernel below handles epb elements per block, tpe = 256 / epb threads per element, each
+// element with its own LDS region of `per` doubles after the shared tables.  Groups without an
+// element (the ragged end of a colour) take part in the barriers only.
+
+// Forward: b_k, b_d (colour-accumulated, final at the last writer).
 template <int P, int DIM>
 __global__ __launch_bounds__(kSqThreads) void k_sq_rhs(const double *__restrict__ eta, const double *__restrict__ phs,
                                                        const double *__restrict__ wv,
                                                        const int32_t *__restrict__ eh_nodes,
                                                        const uint8_t *__restrict__ flags,
-                                                       const int32_t *__restrict__ cols, const double *__restrict__ Bg,
+                                                       const int32_t *__restrict__ cols, int count, int epb, int per,
+                                                       const double *__restrict__ Bg,
                                                        const double *__restrict__ Bdg, int nq,
                                                        const double *__restrict__ met, int64_t mstride, double g,
                                                        double *__restrict__ bk, double *__restrict__ bd) {
   constexpr int N1 = P + 1, NH = DIM == 3 ? N1 * N1 : N1;
   extern __shared__ double lds[];
-  Carve cv{lds};
-  const int tid = threadIdx.x;
+  const int tpe = kSqThreads / epb, grp = threadIdx.x / tpe, tid = threadIdx.x - grp * tpe;
+  const int ci = blockIdx.x * epb + grp;
+  const bool act = ci < count;
+  const int col = act ? cols[ci] : 0;
   const int nqd = DIM == 3 ? nq * nq : nq;
-  double *sB = cv.take(nq * N1), *sBd = cv.take(nq * N1);
+  double *sB = lds, *sBd = lds + nq * N1;
+  Carve cv{lds + 2 * nq * N1 + grp * per};
   double *se = cv.take(NH), *sp = cv.take(NH), *sw = cv.take(NH);
   double *Qk = cv.take(nqd), *Qd = cv.take(nqd);
-  const int col = cols[blockIdx.x];
-  for (int k = tid; k < nq * N1; k += kSqThreads) {
+  for (int k = threadIdx.x; k < nq * N1; k += kSqThreads) {
     sB[k] = Bg[k];
     sBd[k] = Bdg[k];
   }
-  for (int t = tid; t < NH; t += kSqThreads) {
+  for (int t = tid; act && t < NH; t += tpe) {
     const int hn = eh_nodes[(int64_t)col * NH + t];
     se[t] = eta[hn];
     sp[t] = phs[hn];
@@ -88,7 +96,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs(const double *__restrict_
            *Tw = cv.take(N1 * nq);
     double *Uk = cv.take(N1 * nq), *Ud = cv.take(N1 * nq);
     // along xi: (j, qx)
-    for (int k = tid; k < N1 * nq; k += kSqThreads) {
+    for (int k = tid; act && k < N1 * nq; k += tpe) {
       const int j = k / nq, qx = k - j * nq;
       double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
 #pragma unroll
@@ -108,7 +116,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs(const double *__restrict_
     }
     __syncthreads();
     // along eta: (qy, qx); integrands times W det
-    for (int k = tid; k < nqd; k += kSqThreads) {
+    for (int k = tid; act && k < nqd; k += tpe) {
       const int qy = k / nq, qx = k - qy * nq;
       double ev = 0, exi = 0, eet = 0, pxi = 0, pet = 0, w = 0;
 #pragma unroll
@@ -133,7 +141,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs(const double *__restrict_
     }
     __syncthreads();
     // test functions, along eta then xi
-    for (int k = tid; k < N1 * nq; k += kSqThreads) {
+    for (int k = tid; act && k < N1 * nq; k += tpe) {
       const int j = k / nq, qx = k - j * nq;
       double a0 = 0, a1 = 0;
       for (int qy = 0; qy < nq; ++qy) {
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs(const double *__restrict_
       Ud[k] = a1;
     }
     __syncthreads();
-    for (int t = tid; t < NH; t += kSqThreads) {
+    for (int t = tid; act && t < NH; t += tpe) {
       const int j = t / N1, i = t - j * N1;
       double a0 = 0, a1 = 0;
       for (int qx = 0; qx < nq; ++qx) {
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs(const double *__restrict_
       acc_colour(bd, hn, a1, fl);
     }
   } else {
-    for (int q = tid; q < nq; q += kSqThreads) {
+    for (int q = tid; act && q < nq; q += tpe) {
       double ev = 0, exi = 0, pxi = 0, w = 0;
 #pragma unroll
       for (int i = 0; i < N1; ++i) {
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs(const double *__restrict_
       Qd[q] = wd * (-g * ev - 0.5 * px * px + 0.5 * w * w * (1.0 + ee));
     }
     __syncthreads();
-    for (int i = tid; i < N1; i += kSqThreads) {
+    for (int i = tid; act && i < N1; i += tpe) {
       double a0 = 0, a1 = 0;
       for (int q = 0; q < nq; ++q) {
         a0 += sB[q * N1 + i] * Qk[q];
@@ -197,20 +205,22 @@ template <int P, int DIM>
 __global__ __launch_bounds__(kSqThreads) void k_sq_mass(const double *__restrict__ x, double *__restrict__ y,
                                                         int64_t n_s, const int32_t *__restrict__ eh_nodes,
                                                         const uint8_t *__restrict__ flags,
-                                                        const int32_t *__restrict__ cols,
-                                                        const double *__restrict__ Bg, int nq,
+                                                        const int32_t *__restrict__ cols, int count, int epb,
+                                                        int per, const double *__restrict__ Bg, int nq,
                                                         const double *__restrict__ wdet) {
   constexpr int N1 = P + 1, NH = DIM == 3 ? N1 * N1 : N1;
   extern __shared__ double lds[];
-  Carve cv{lds};
-  const int tid = threadIdx.x;
+  const int tpe = kSqThreads / epb, grp = threadIdx.x / tpe, tid = threadIdx.x - grp * tpe;
+  const int ci = blockIdx.x * epb + grp;
+  const bool act = ci < count;
+  const int col = act ? cols[ci] : 0;
   const int nqd = DIM == 3 ? nq * nq : nq;
-  double *sB = cv.take(nq * N1);
+  double *sB = lds;
+  Carve cv{lds + nq * N1 + grp * per};
   double *u0 = cv.take(NH), *u1 = cv.take(NH);
   double *Q0 = cv.take(nqd), *Q1 = cv.take(nqd);
-  const int col = cols[blockIdx.x];
-  for (int k = tid; k < nq * N1; k += kSqThreads) sB[k] = Bg[k];
-  for (int t = tid; t < NH; t += kSqThreads) {
+  for (int k = threadIdx.x; k < nq * N1; k += kSqThreads) sB[k] = Bg[k];
+  for (int t = tid; act && t < NH; t += tpe) {
     const int hn = eh_nodes[(int64_t)col * NH + t];
     u0[t] = x[hn];
     u1[t] = x[n_s + hn];
@@ -219,7 +229,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_mass(const double *__restrict
   const int64_t mb = (int64_t)col * nqd;
   if constexpr (DIM == 3) {
     double *T0 = cv.take(N1 * nq), *T1 = cv.take(N1 * nq);
-    for (int k = tid; k < N1 * nq; k += kSqThreads) {
+    for (int k = tid; act && k < N1 * nq; k += tpe) {
       const int j = k / nq, qx = k - j * nq;
       double a0 = 0, a1 = 0;
 #pragma unroll
@@ -232,7 +242,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_mass(const double *__restrict
       T1[k] = a1;
     }
     __syncthreads();
-    for (int k = tid; k < nqd; k += kSqThreads) {
+    for (int k = tid; act && k < nqd; k += tpe) {
       const int qy = k / nq, qx = k - qy * nq;
       double a0 = 0, a1 = 0;
 #pragma unroll
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_mass(const double *__restrict
       Q1[k] = wd * a1;
     }
     __syncthreads();
-    for (int k = tid; k < N1 * nq; k += kSqThreads) {
+    for (int k = tid; act && k < N1 * nq; k += tpe) {
       const int j = k / nq, qx = k - j * nq;
       double a0 = 0, a1 = 0;
       for (int qy = 0; qy < nq; ++qy) {
@@ -258,7 +268,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_mass(const double *__restrict
       T1[k] = a1;
     }
     __syncthreads();
-    for (int t = tid; t < NH; t += kSqThreads) {
+    for (int t = tid; act && t < NH; t += tpe) {
       const int j = t / N1, i = t - j * N1;
       double a0 = 0, a1 = 0;
       for (int qx = 0; qx < nq; ++qx) {
@@ -273,7 +283,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_mass(const double *__restrict
       acc_colour(y + n_s, hn, a1, fl);
     }
   } else {
-    for (int q = tid; q < nq; q += kSqThreads) {
+    for (int q = tid; act && q < nq; q += tpe) {
       double a0 = 0, a1 = 0;
 #pragma unroll
       for (int i = 0; i < N1; ++i) {
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_mass(const double *__restrict
       Q1[q] = wdet[mb + q] * a1;
     }
     __syncthreads();
-    for (int i = tid; i < N1; i += kSqThreads) {
+    for (int i = tid; act && i < N1; i += tpe) {
       double a0 = 0, a1 = 0;
       for (int q = 0; q < nq; ++q) {
         a0 += sB[q * N1 + i] * Q0[q];
@@ -300,31 +310,33 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_mass(const double *__restrict
 }
 
 // VJP of k_sq_rhs: from bbar = (bbar_k, bbar_d) [2][n_s], adds to eta_bar, phi_bar, w_bar
-// (colour-accumulated in scratch a[3][n_s], added by the last writer).
+// (colour-accumulated in scratch scr[3][n_s], added by the last writer).
 template <int P, int DIM>
 __global__ __launch_bounds__(kSqThreads) void k_sq_rhs_vjp(
     const double *__restrict__ eta, const double *__restrict__ phs, const double *__restrict__ wv,
     const double *__restrict__ bbar, int64_t n_s, const int32_t *__restrict__ eh_nodes,
-    const uint8_t *__restrict__ flags, const int32_t *__restrict__ cols, const double *__restrict__ Bg,
-    const double *__restrict__ Bdg, int nq, const double *__restrict__ met, int64_t mstride, double g,
-    double *__restrict__ scr, double *__restrict__ eta_bar, double *__restrict__ phi_bar,
+    const uint8_t *__restrict__ flags, const int32_t *__restrict__ cols, int count, int epb, int per,
+    const double *__restrict__ Bg, const double *__restrict__ Bdg, int nq, const double *__restrict__ met,
+    int64_t mstride, double g, double *__restrict__ scr, double *__restrict__ eta_bar, double *__restrict__ phi_bar,
     double *__restrict__ w_bar) {
   constexpr int N1 = P + 1, NH = DIM == 3 ? N1 * N1 : N1;
   extern __shared__ double lds[];
-  Carve cv{lds};
-  const int tid = threadIdx.x;
+  const int tpe = kSqThreads / epb, grp = threadIdx.x / tpe, tid = threadIdx.x - grp * tpe;
+  const int ci = blockIdx.x * epb + grp;
+  const bool act = ci < count;
+  const int col = act ? cols[ci] : 0;
   const int nqd = DIM == 3 ? nq * nq : nq;
-  double *sB = cv.take(nq * N1), *sBd = cv.take(nq * N1);
+  double *sB = lds, *sBd = lds + nq * N1;
+  Carve cv{lds + 2 * nq * N1 + grp * per};
   double *se = cv.take(NH), *sp = cv.take(NH), *sw = cv.take(NH), *sk = cv.take(NH), *sd = cv.take(NH);
   // adjoints at the Gauss points: eta value, eta_xi, eta_eta, phi_xi, phi_eta, w
   double *Qe = cv.take(nqd), *Qex = cv.take(nqd), *Qey = cv.take(nqd), *Qpx = cv.take(nqd), *Qpy = cv.take(nqd),
          *Qw = cv.take(nqd);
-  const int col = cols[blockIdx.x];
-  for (int k = tid; k < nq * N1; k += kSqThreads) {
+  for (int k = threadIdx.x; k < nq * N1; k += kSqThreads) {
     sB[k] = Bg[k];
     sBd[k] = Bdg[k];
   }
-  for (int t = tid; t < NH; t += kSqThreads) {
+  for (int t = tid; act && t < NH; t += tpe) {
     const int hn = eh_nodes[(int64_t)col * NH + t];
     se[t] = eta[hn];
     sp[t] = phs[hn];
@@ -349,6 +361,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs_vjp(
       A01 = A10 = A11 = 0.0;
       wd = met[1 * mstride + mb + k];
     }
+    (void)ev;
     const double ex = A00 * exi + A10 * eet, ey = A01 * exi + A11 * eet;
     const double px = A00 * pxi + A10 * pet, py = A01 * pxi + A11 * pet;
     const double ee = ex * ex + ey * ey;
@@ -369,7 +382,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs_vjp(
   if constexpr (DIM == 3) {
     double *Te = cv.take(N1 * nq), *Ted = cv.take(N1 * nq), *Tp = cv.take(N1 * nq), *Tpd = cv.take(N1 * nq),
            *Tw = cv.take(N1 * nq), *Tk = cv.take(N1 * nq), *Td = cv.take(N1 * nq);
-    for (int k = tid; k < N1 * nq; k += kSqThreads) {
+    for (int k = tid; act && k < N1 * nq; k += tpe) {
       const int j = k / nq, qx = k - j * nq;
       double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0;
 #pragma unroll
@@ -392,7 +405,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs_vjp(
       Td[k] = a6;
     }
     __syncthreads();
-    for (int k = tid; k < nqd; k += kSqThreads) {
+    for (int k = tid; act && k < nqd; k += tpe) {
       const int qy = k / nq, qx = k - qy * nq;
       double ev = 0, exi = 0, eet = 0, pxi = 0, pet = 0, w = 0, kb = 0, db = 0;
 #pragma unroll
@@ -413,7 +426,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs_vjp(
     __syncthreads();
     // transposed interpolation, along eta: (j, qx); reuse the T arrays
     double *Uae = Te, *Ube = Ted, *Uap = Tp, *Ubp = Tpd, *Uw = Tw;
-    for (int k = tid; k < N1 * nq; k += kSqThreads) {
+    for (int k = tid; act && k < N1 * nq; k += tpe) {
       const int j = k / nq, qx = k - j * nq;
       double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
       for (int qy = 0; qy < nq; ++qy) {
@@ -432,7 +445,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs_vjp(
       Uw[k] = a4;
     }
     __syncthreads();
-    if (tid < NH) {
+    if (act && tid < NH) {
       const int j = tid / N1, i = tid - j * N1;
       for (int qx = 0; qx < nq; ++qx) {
         const double b = sB[qx * N1 + i], bdx = sBd[qx * N1 + i];
@@ -444,7 +457,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs_vjp(
       t_out = tid;
     }
   } else {
-    for (int q = tid; q < nq; q += kSqThreads) {
+    for (int q = tid; act && q < nq; q += tpe) {
       double ev = 0, exi = 0, pxi = 0, w = 0, kb = 0, db = 0;
 #pragma unroll
       for (int i = 0; i < N1; ++i) {
@@ -459,7 +472,7 @@ __global__ __launch_bounds__(kSqThreads) void k_sq_rhs_vjp(
       point(q, ev, exi, 0.0, pxi, 0.0, w, kb, db);
     }
     __syncthreads();
-    if (tid < NH) {
+    if (act && tid < NH) {
       for (int q = 0; q < nq; ++q) {
         const double b = sB[q * N1 + tid], bdx = sBd[q * N1 + tid];
         r_e += b * Qe[q] + bdx * Qex[q];
@@ -542,36 +555,49 @@ int vec_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 4096)
     default: return hipErrorInvalidValue;                 \
   }
 
-size_t lds_rhs(const Ctx &c) {
+// Per-element LDS (doubles) and the shared tables in front of them, per kernel.
+struct SqLds {
+  int table, per;
+};
+SqLds lds_rhs(const Ctx &c) {
   const int n1 = c.p + 1, nq = c.sq_nq, nh = c.nh;
   const int nqd = c.dim == 3 ? nq * nq : nq;
-  size_t n = 2 * nq * n1 + 3 * nh + 2 * nqd;
-  if (c.dim == 3) n += 7 * n1 * nq;
-  return n * sizeof(double);
+  return {2 * nq * n1, 3 * nh + 2 * nqd + (c.dim == 3 ? 7 * n1 * nq : 0)};
 }
-size_t lds_mass(const Ctx &c) {
+SqLds lds_mass(const Ctx &c) {
   const int n1 = c.p + 1, nq = c.sq_nq, nh = c.nh;
   const int nqd = c.dim == 3 ? nq * nq : nq;
-  size_t n = nq * n1 + 2 * nh + 2 * nqd;
-  if (c.dim == 3) n += 2 * n1 * nq;
-  return n * sizeof(double);
+  return {nq * n1, 2 * nh + 2 * nqd + (c.dim == 3 ? 2 * n1 * nq : 0)};
 }
-size_t lds_vjp(const Ctx &c) {
+SqLds lds_vjp(const Ctx &c) {
   const int n1 = c.p + 1, nq = c.sq_nq, nh = c.nh;
   const int nqd = c.dim == 3 ? nq * nq : nq;
-  size_t n = 2 * nq * n1 + 5 * nh + 6 * nqd;
-  if (c.dim == 3) n += 7 * n1 * nq;
-  return n * sizeof(double);
+  return {2 * nq * n1, 5 * nh + 6 * nqd + (c.dim == 3 ? 7 * n1 * nq : 0)};
+}
+
+// Elements per block: 4 (one wave each) while the LDS fits in 64 KiB, else 2, else 1.
+struct SqLaunch {
+  int epb, per;
+  size_t bytes;
+};
+SqLaunch sq_launch(const SqLds &l) {
+  for (int epb = 4; epb > 1; epb /= 2) {
+    const size_t bytes = (size_t)(l.table + epb * l.per) * sizeof(double);
+    if (bytes <= 65536) return {epb, l.per, bytes};
+  }
+  return {1, l.per, (size_t)(l.table + l.per) * sizeof(double)};
 }
 
 template <int P, int DIM>
 hipError_t sq_rhs_impl(Ctx &c, const double *eta, const double *phs, const double *w, double *b, hipStream_t s) {
   const int64_t ms = (int64_t)c.n_eh * (c.dim == 3 ? c.sq_nq * c.sq_nq : c.sq_nq);
+  const SqLaunch L = sq_launch(lds_rhs(c));
   for (const auto &cr : c.colours) {
     if (cr.count == 0) continue;
-    k_sq_rhs<P, DIM><<<cr.count, kSqThreads, lds_rhs(c), s>>>(eta, phs, w, c.d_eh_nodes, c.d_flags,
-                                                                c.d_cols + cr.offset, c.d_sq_B, c.d_sq_Bd, c.sq_nq,
-                                                                c.d_sq_met, ms, c.g, b, b + c.n_s);
+    const int nb = (cr.count + L.epb - 1) / L.epb;
+    k_sq_rhs<P, DIM><<<nb, kSqThreads, L.bytes, s>>>(eta, phs, w, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
+                                                      cr.count, L.epb, L.per, c.d_sq_B, c.d_sq_Bd, c.sq_nq,
+                                                      c.d_sq_met, ms, c.g, b, b + c.n_s);
   }
   return hipGetLastError();
 }
@@ -580,10 +606,12 @@ template <int P, int DIM>
 hipError_t sq_mass_impl(Ctx &c, const double *x, double *y, hipStream_t s) {
   const int64_t ms = (int64_t)c.n_eh * (c.dim == 3 ? c.sq_nq * c.sq_nq : c.sq_nq);
   const double *wdet = c.d_sq_met + (c.dim == 3 ? 4 : 1) * ms;
+  const SqLaunch L = sq_launch(lds_mass(c));
   for (const auto &cr : c.colours) {
     if (cr.count == 0) continue;
-    k_sq_mass<P, DIM><<<cr.count, kSqThreads, lds_mass(c), s>>>(x, y, c.n_s, c.d_eh_nodes, c.d_flags,
-                                                                  c.d_cols + cr.offset, c.d_sq_B, c.sq_nq, wdet);
+    const int nb = (cr.count + L.epb - 1) / L.epb;
+    k_sq_mass<P, DIM><<<nb, kSqThreads, L.bytes, s>>>(x, y, c.n_s, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
+                                                       cr.count, L.epb, L.per, c.d_sq_B, c.sq_nq, wdet);
   }
   return hipGetLastError();
 }
@@ -592,11 +620,13 @@ template <int P, int DIM>
 hipError_t sq_vjp_impl(Ctx &c, const double *eta, const double *phs, const double *w, const double *bbar,
                        double *eta_bar, double *phi_bar, double *w_bar, hipStream_t s) {
   const int64_t ms = (int64_t)c.n_eh * (c.dim == 3 ? c.sq_nq * c.sq_nq : c.sq_nq);
+  const SqLaunch L = sq_launch(lds_vjp(c));
   for (const auto &cr : c.colours) {
     if (cr.count == 0) continue;
-    k_sq_rhs_vjp<P, DIM><<<cr.count, kSqThreads, lds_vjp(c), s>>>(
-        eta, phs, w, bbar, c.n_s, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, c.d_sq_B, c.d_sq_Bd, c.sq_nq,
-        c.d_sq_met, ms, c.g, c.d_sq_scr, eta_bar, phi_bar, w_bar);
+    const int nb = (cr.count + L.epb - 1) / L.epb;
+    k_sq_rhs_vjp<P, DIM><<<nb, kSqThreads, L.bytes, s>>>(
+        eta, phs, w, bbar, c.n_s, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, L.epb, L.per, c.d_sq_B,
+        c.d_sq_Bd, c.sq_nq, c.d_sq_met, ms, c.g, c.d_sq_scr, eta_bar, phi_bar, w_bar);
   }
   return hipGetLastError();
 }

@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFS = 78.6
+FP32_VALU_PEAK_TFS = 157.3
 METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/forward ratio"
 
 # HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by the
@@ -254,6 +255,46 @@ def adjoint_leg(nsteps, rtol, fd_dirs):
     return out
 
 
+# Meshes of the apply sweep over p: the C5 construction at 40-50 M DoF per degree.
+SWEEP = ((1, 1536, 1536, 18), (2, 768, 768, 9), (3, 512, 512, 6), (4, 384, 384, 4), (5, 307, 307, 4),
+         (6, 256, 256, 3))
+
+
+def apply_sweep(reps, variant=None):
+    """FP64 and FP32 apply throughput and roofline fractions for p = 1..6 (default schedule, or
+    the given apply variant)."""
+    import torch
+    from paper_2506_09435_amd import fnpf
+    from workloads import configs
+    rows = []
+    for p, nx, ny, nz in SWEEP:
+        wl = configs.c5(nx=nx, ny=ny, nz=nz, p=p)
+        m = wl.mesh
+        s = fnpf.setup_workload(wl, fp32=True)
+        if variant is not None:
+            s.ctx.set_apply_variant(variant)
+        s.ctx.geom(s.eta0, s.h)
+        torch.cuda.synchronize()
+        g = torch.Generator(device="cuda").manual_seed(0)
+        x = torch.randn(m.n_v, dtype=torch.float64, device="cuda", generator=g)
+        t64, _ = time_applies(s.ctx, x, reps)
+        t32, _ = time_applies(s.ctx, x.float(), reps)
+        n_q = m.n_e * (p + 1) ** 3
+        b64 = apply_bytes_fused(m.n_v, m.n_eh, m.nh, 8)
+        b32 = apply_bytes_fused(m.n_v, m.n_eh, m.nh, 4)
+        fl = apply_flops(n_q, p)
+        rows.append(dict(p=p, mesh=f"{nx}x{ny}x{nz}", n_v=m.n_v, ms_f64=t64 * 1e3, ms_f32=t32 * 1e3,
+                         gdofs_f64=m.n_v / t64 / 1e9, gdofs_f32=m.n_v / t32 / 1e9,
+                         hbm_frac_f64=b64 / t64 / 1e9 / HBM_PEAK_GBS, hbm_frac_f32=b32 / t32 / 1e9 / HBM_PEAK_GBS,
+                         alu_frac_f64=fl / t64 / 1e12 / FP64_VALU_PEAK_TFS,
+                         alu_frac_f32=fl / t32 / 1e12 / FP32_VALU_PEAK_TFS))
+        print(f"[bench] sweep p={p}: {rows[-1]}", file=sys.stderr, flush=True)
+        s.ctx.close()
+        del s, x
+        torch.cuda.empty_cache()
+    return rows
+
+
 def _time_steps(s, wl, opts, nsteps):
     import torch
     s.ctx.set_warm_start(None)
@@ -328,6 +369,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="apply variant (fnpf_set_apply_variant)")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="C4 steps of the adjoint leg (0: skip)")
     ap.add_argument("--adjoint-fd", type=int, default=0, help="finite-difference directions checked in the adjoint leg")
+    ap.add_argument("--apply-sweep", action="store_true",
+                    help="only the apply throughput for p = 1..6 at 40-50 M DoF (one JSON line)")
     ap.add_argument("--no-extensions", action="store_true",
                     help="skip the linear-flow, modal-filter and consistent-surface timings")
     args = ap.parse_args()
@@ -342,6 +385,11 @@ def main():
     from workloads import configs
 
     torch.cuda.set_device(0)
+    if args.apply_sweep:
+        v = args.variant if args.variant != 0 else None
+        print(json.dumps(dict(mode="apply-sweep", variant=args.variant, reps=args.apply_reps,
+                              rows=apply_sweep(args.apply_reps, v))), flush=True)
+        return
     wl = configs.ALL[args.workload]()
     m = wl.mesh
     t_setup = time.perf_counter()

@@ -712,8 +712,8 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
 // (i = a, k = b) with t = b N1 + a.  Every contraction then runs over compile-time indices, so
 // its D entries are wave-uniform scalar operands, and each LDS word read feeds N1 FMAs.
 // Phases per layer element (4 barriers):
-//   0  line (i,j): store u to LDS; u_zeta in registers
-//   1  xi/eta lines: u_xi -> sA, u_eta -> sB
+//   0  line (i,j): store u into both sA and sB; u_zeta in registers
+//   1  xi/eta lines: u_xi -> sA, u_eta -> sB, each line in place
 //   2  line (i,j): per point g = J^-T grad u, v = w detJ J^-1 g; v_xi, v_eta back into sA, sB
 //      in place; zeta part of the transposed contraction into registers
 //   3  xi/eta lines: transposed contractions in place in sA, sB
@@ -739,9 +739,15 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
                                                      int64_t n_slots = 0) {
   using S = Sh<P, 3>;
   constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
-  __shared__ T sU[CPB * NP];
+  // sA holds the xi-lines (planes of NH, line stride N1: lane t reads from 7t, conflict-free);
+  // sB the eta-lines with the plane stride padded to SB = N1 (mod 64), so that lane t = b N1 + a
+  // of the eta-line (i = a, k = b) starts at b SB + a = t (mod 64) and a wave's loads fall in
+  // distinct banks (degrees < 4: N1 mod 16, to bound the LDS of their many columns per block)
+  constexpr int SBM = P >= 4 ? 64 : 16;
+  constexpr int SB = NH + (((N1 - NH) % SBM) + SBM) % SBM;
+  constexpr int NPB = N1 * SB;
   __shared__ T sA[CPB * NP];
-  __shared__ T sB[CPB * NP];
+  __shared__ T sB[CPB * NPB];
   if (skip != nullptr && *skip) return;
 
   const int lc = threadIdx.x / NH;
@@ -775,12 +781,11 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
   }
   const T wdJ = (T)(wgt(P, i) * wgt(P, j)) * dJ;
 
-  T *U = sU + lc * NP;
   T *Ab = sA + lc * NP;
-  T *Bb = sB + lc * NP;
+  T *Bb = sB + lc * NPB;
   // the thread's lines in the horizontal phases: xi-line (j = a, k = b), eta-line (i = a, k = b)
   const int xi_base = t * N1;                       // b NH + a N1
-  const int eta_base = (t / N1) * NH + (t % N1);    // b NH + a, stride N1
+  const int eta_base = (t / N1) * SB + (t % N1);    // b SB + a, stride N1
   // node (v, hn) at byte offset v n_s sizeof(T) (uniform) + hn sizeof(T) (per thread); the
   // launcher guarantees that n_v sizeof(T) fits in 32 bits
   const uint32_t nbytes = (uint32_t)((int64_t)(P * nz + 1) * n_s * (int64_t)sizeof(T));
@@ -811,7 +816,10 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
 #pragma unroll
     for (int k = 1; k < N1; ++k) ucol[k] = nxt[k];
 #pragma unroll
-    for (int k = 0; k < N1; ++k) U[k * NH + t] = ucol[k];
+    for (int k = 0; k < N1; ++k) {
+      Ab[k * NH + t] = ucol[k];
+      Bb[k * SB + t] = ucol[k];
+    }
     T uz[N1];
     line_eo<P, T, 0>(ucol, uz);
     __syncthreads();
@@ -821,16 +829,16 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
       for (int k = 1; k < N1; ++k) nxt[k] = active ? buf_ld<T>(rx, hb, (uint32_t)((l + 1) * P + k) * rowb) : T(0);
     }
 
-    // phase 1
+    // phase 1 (in place: each line is read and written by its one thread)
     {
       T in[N1], out[N1];
 #pragma unroll
-      for (int m = 0; m < N1; ++m) in[m] = U[xi_base + m];
+      for (int m = 0; m < N1; ++m) in[m] = Ab[xi_base + m];
       line_eo<P, T, 0>(in, out);
 #pragma unroll
       for (int r = 0; r < N1; ++r) Ab[xi_base + r] = out[r];
 #pragma unroll
-      for (int m = 0; m < N1; ++m) in[m] = U[eta_base + m * N1];
+      for (int m = 0; m < N1; ++m) in[m] = Bb[eta_base + m * N1];
       line_eo<P, T, 0>(in, out);
 #pragma unroll
       for (int r = 0; r < N1; ++r) Bb[eta_base + r * N1] = out[r];
@@ -844,8 +852,8 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     T vz[N1], yz[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const int q = k * NH + t;
-      const T ux = Ab[q], uy = Bb[q];
+      const int q = k * NH + t, qb = k * SB + t;
+      const T ux = Ab[q], uy = Bb[qb];
       const T sg = sig[l * P + k];
       const T f = (T)wgt(P, k) * fl0;
       const T zx = sg * Hx - hx;
@@ -856,7 +864,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
       const T gy = A01 * ux + A11 * uy + b2y * uz[k];
       const T gz = izz * uz[k];
       Ab[q] = f * (A00 * gx + A01 * gy);
-      Bb[q] = f * (A10 * gx + A11 * gy);
+      Bb[qb] = f * (A10 * gx + A11 * gy);
       vz[k] = f * (b2x * gx + b2y * gy + izz * gz);
     }
     line_eo<P, T, 1>(vz, yz);
@@ -891,7 +899,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     // phase 4
     T yv[N1];
 #pragma unroll
-    for (int k = 0; k < N1; ++k) yv[k] = yz[k] + (Ab[k * NH + t] + Bb[k * NH + t]);
+    for (int k = 0; k < N1; ++k) yv[k] = yz[k] + (Ab[k * NH + t] + Bb[k * SB + t]);
     yv[0] += carry;
     if (active) {
 #pragma unroll

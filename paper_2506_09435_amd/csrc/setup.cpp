@@ -453,9 +453,11 @@ std::string coarse_numbering(const Ctx &f, int pc, std::vector<int32_t> &nodes, 
       else
         it->second[0] += 1;
     }
+  // shared nodes of every column (by owner column) first, then the interior ones, so that the
+  // shared nodes of a node level are one contiguous range (coalesced face pass)
   int64_t next = 0;
-  for (int64_t e = 0; e < n_eh; ++e)
-    for (int pass = 0; pass < 2; ++pass)
+  for (int pass = 0; pass < 2; ++pass)
+    for (int64_t e = 0; e < n_eh; ++e)
       for (int t = 0; t < nhc; ++t) {
         auto &v = info[keys[e * nhc + t]];
         if (v[1] != e || v[2] >= 0) continue;

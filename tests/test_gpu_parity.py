@@ -58,11 +58,15 @@ def _case(name):
         wl = _case(name[: -len("_blocked")])
         wl.mesh = wm.renumber_blocked(wl.mesh)
         return wl
+    if name.endswith("_sharedfirst"):
+        wl = _case(name[: -len("_sharedfirst")])
+        wl.mesh = wm.renumber_blocked(wl.mesh, shared_first=True)
+        return wl
     raise KeyError(name)
 
 
 CASES = ["slice_periodic", "slice_walls", "box_periodic", "box_mixed", "box_walls_p6", "cylinder",
-         "box_mixed_blocked", "cylinder_blocked"]
+         "box_mixed_blocked", "cylinder_blocked", "box_walls_p6_sharedfirst", "cylinder_sharedfirst"]
 
 
 class Pair:

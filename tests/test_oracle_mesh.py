@@ -114,6 +114,31 @@ def test_renumber_blocked(periodic):
     assert nxt == b.n_s
 
 
+@pytest.mark.parametrize("periodic", [(False, False), (True, False), (True, True)])
+def test_renumber_shared_first(periodic):
+    """Shared-first blocked numbering: a consistent bijection with every shared node before every
+    interior node, each group column by column (owner order) as one run per column."""
+    m = wm.structured_box(5, 4, 0.0, 2.0, 0.0, 1.5, periodic[0], periodic[1], p=3, nz=2)
+    b = wm.renumber_blocked(m, shared_first=True)
+    geo.check_numbering(b)
+    perm = np.full(m.n_s, -1)
+    perm[m.eh_nodes.ravel()] = b.eh_nodes.ravel()
+    assert np.all(np.sort(perm) == np.arange(m.n_s))
+    counts = np.bincount(b.eh_nodes.ravel(), minlength=b.n_s)
+    n_shared = int((counts > 1).sum())
+    assert np.all(counts[:n_shared] > 1) and np.all(counts[n_shared:] == 1)
+    nxt_s, nxt_i = 0, n_shared
+    for e in range(b.n_eh):
+        ids = b.eh_nodes[e]
+        owned = [g for g in ids if not np.any(b.eh_nodes[:e] == g)]
+        sh = sorted(g for g in owned if counts[g] > 1)
+        it = sorted(g for g in owned if counts[g] == 1)
+        assert sh == list(range(nxt_s, nxt_s + len(sh))) and it == list(range(nxt_i, nxt_i + len(it)))
+        nxt_s += len(sh)
+        nxt_i += len(it)
+    assert nxt_s == n_shared and nxt_i == b.n_s
+
+
 def test_apply_invariant_under_renumbering():
     """The oracle's apply commutes with a renumbering of the horizontal nodes."""
     from oracle import operator as op

@@ -72,7 +72,8 @@ def c2(n: int = 40, nz: int = 4, p: int = 5) -> Workload:
     k, h = 1.0, 1.0
     a = 0.05 / k
     L = 2 * math.pi / k
-    mesh = renumber_blocked(structured_box(n, n, 0.0, L, 0.0, L, True, True, p=p, nz=nz, name="C2"))
+    mesh = renumber_blocked(structured_box(n, n, 0.0, L, 0.0, L, True, True, p=p, nz=nz, name="C2"),
+                            shared_first=True)
     omega = waves.frequency(k, h, g)
     period = 2 * math.pi / omega
     wave = waves.LinearWave(a, k, 0.0, omega, g)
@@ -88,7 +89,7 @@ def c3(p: int = 4, nz: int = 4, seed: int = 0) -> Workload:
     k = 1.0 / h
     L = 2 * math.pi / k
     H = 0.02 * L
-    mesh = renumber_blocked(cylinder_tank_mesh(p=p, nz=nz, seed=seed))
+    mesh = renumber_blocked(cylinder_tank_mesh(p=p, nz=nz, seed=seed), shared_first=True)
     omega = waves.frequency(k, h, g)
     period = 2 * math.pi / omega
     wave = waves.LinearWave(H / 2, k, 0.0, omega, g)
@@ -116,7 +117,8 @@ def c4(nx: int = 64, ny: int = 16, nz: int = 4, p: int = 5, nsteps: int = 200, l
     omega = 2 * math.pi / period
     h_deep = 0.4
     k = waves.wavenumber(omega, h_deep, g)
-    mesh = renumber_blocked(structured_box(nx, ny, 0.0, lx, 0.0, ly, False, False, p=p, nz=nz, name="C4"))
+    mesh = renumber_blocked(structured_box(nx, ny, 0.0, lx, 0.0, ly, False, False, p=p, nz=nz, name="C4"),
+                            shared_first=True)
     xc = waves.control_points(lx, n_ctrl)
     c0 = waves.bar_profile(xc)
     wave = waves.LinearWave(H / 2, k, 0.0, omega, g)
@@ -145,7 +147,8 @@ def c5(nx: int = 256, ny: int = 128, nz: int = 6, p: int = 6, nsteps: int = 20) 
     kp, h_mean = 2.0, 1.0
     lp = 2 * math.pi / kp
     lx, ly = 32 * lp * nx / 256, 16 * lp * ny / 128
-    mesh = renumber_blocked(structured_box(nx, ny, 0.0, lx, 0.0, ly, False, True, p=p, nz=nz, name="C5"))
+    mesh = renumber_blocked(structured_box(nx, ny, 0.0, lx, 0.0, ly, False, True, p=p, nz=nz, name="C5"),
+                            shared_first=True)
     omega_p = waves.frequency(kp, h_mean, g)
     tp = 2 * math.pi / omega_p
     bathy = waves.FourierBathymetry(lx, ly, h0=1.0, rel=0.2, seed=2)
@@ -159,7 +162,7 @@ def p1() -> Workload:
     g = G_STD
     L, h = 1.0, 1.0
     k = 2 * math.pi / L
-    mesh = renumber_blocked(structured_box(64, 64, 0.0, L, 0.0, L, True, True, p=4, nz=4, name="P1"))
+    mesh = renumber_blocked(structured_box(64, 64, 0.0, L, 0.0, L, True, True, p=4, nz=4, name="P1"), shared_first=True)
     omega = waves.frequency(k, h, g)
     period = 2 * math.pi / omega
     wave = waves.LinearWave(0.01 / k, k, 0.0, omega, g)

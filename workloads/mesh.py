@@ -295,14 +295,15 @@ def cylinder_tank_mesh(p: int = 4, nz: int = 4, seed: int = 0, n_theta: int = 48
     return m
 
 
-def renumber_blocked(m: HexMesh) -> HexMesh:
+def renumber_blocked(m: HexMesh, shared_first: bool = False) -> HexMesh:
     """The same mesh with its horizontal nodes renumbered column by column.
 
     Every node goes to the lowest-numbered horizontal element (column) that has it; each
     column's nodes get consecutive ids, the ones it shares with other columns first, then its
     interior ones, both in local order.  A volume vector (layer-major) then holds each
     column's own nodes at a node level as one contiguous run, and the shared ones of a column
-    as a shorter run at its start.
+    as a shorter run at its start.  shared_first: all shared nodes (column by column) before
+    all interior nodes, so the shared nodes of a node level form one contiguous range.
     """
     import dataclasses
     nodes = m.eh_nodes.astype(np.int64)
@@ -317,9 +318,9 @@ def renumber_blocked(m: HexMesh) -> HexMesh:
     og, oloc = g[mine], loc[mine]
     key_col = owner[og]
     key_int = (count[og] == 1).astype(np.int64)
-    order = np.lexsort((oloc, key_int, key_col))
+    order = np.lexsort((oloc, key_col, key_int)) if shared_first else np.lexsort((oloc, key_int, key_col))
     new = np.empty(m.n_s, dtype=np.int64)
     new[og[order]] = np.arange(og.size)
     extra = dict(m.extra)
-    extra["numbering"] = "blocked"
+    extra["numbering"] = "blocked-shared-first" if shared_first else "blocked"
     return dataclasses.replace(m, eh_nodes=new[nodes].astype(np.int32), extra=extra)

@@ -37,9 +37,9 @@ METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/for
 # HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by the
 # plain-copy calibration), valid only for the kernel source they were taken from.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "ea03e5c5db850d73f4211f7f19e74e678a0cd88cf44c2dd0c51e03a042b3c562",
-    "fetch_bytes_per_apply": 1151818288,
-    "write_bytes_per_apply": 615178876,
+    "kernel_source_sha256": "42ca21ca239b487bc2c64650546472dac4a5392c9347ea2013090ddd4f53f830",
+    "fetch_bytes_per_apply": 861186032,
+    "write_bytes_per_apply": 584754612,
 }
 
 

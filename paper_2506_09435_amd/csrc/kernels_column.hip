@@ -148,12 +148,20 @@ __device__ __forceinline__ const float *eo_table<float>() { return c_EO32; }
 // about half the multiply-adds of the dense product.  The coefficients are read through the
 // scalar cache at every call (the zero offset is opaque to the compiler), so they occupy
 // scalar registers only while the line is computed.
-template <int P, typename T, int TR>
-__device__ __forceinline__ void line_eo(const T (&in)[P + 1], T (&out)[P + 1]) {
-  constexpr int N1 = P + 1, H = N1 / 2, C = P / 2;
+// Even-odd table of D (TR = 0) or D^T (TR = 1) for degree P.  The zero offset passes through an
+// empty asm statement that takes `dep` as an input, so the table's scalar loads cannot be
+// scheduled before `dep` exists: a caller ties them to the data of the phase that uses them, and
+// only one table (48 SGPRs in FP64 at P = 6) is live at a time.
+template <int P, typename T, int TR, typename U>
+__device__ __forceinline__ const T *eo_ptr(const U &dep) {
   int z = 0;
-  asm volatile("" : "+s"(z));
-  const T *E = eo_table<T>() + (P * 2 + TR) * kEOStride + z;
+  asm volatile("" : "+s"(z) : "v"(dep));
+  return eo_table<T>() + (P * 2 + TR) * kEOStride + z;
+}
+
+template <int P, typename T>
+__device__ __forceinline__ void line_eo(const T (&in)[P + 1], T (&out)[P + 1], const T *__restrict__ E) {
+  constexpr int N1 = P + 1, H = N1 / 2, C = P / 2;
   T e[H], o[H];
 #pragma unroll
   for (int m = 0; m < H; ++m) {
@@ -821,7 +829,8 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
       Bb[k * SB + t] = ucol[k];
     }
     T uz[N1];
-    line_eo<P, T, 0>(ucol, uz);
+    const T *E0 = eo_ptr<P, T, 0>(ucol[0]);
+    line_eo<P, T>(ucol, uz, E0);
     __syncthreads();
     // next layer's x loads complete behind this layer's arithmetic
     if (l + 1 < nz) {
@@ -834,12 +843,12 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
       T in[N1], out[N1];
 #pragma unroll
       for (int m = 0; m < N1; ++m) in[m] = Ab[xi_base + m];
-      line_eo<P, T, 0>(in, out);
+      line_eo<P, T>(in, out, E0);
 #pragma unroll
       for (int r = 0; r < N1; ++r) Ab[xi_base + r] = out[r];
 #pragma unroll
       for (int m = 0; m < N1; ++m) in[m] = Bb[eta_base + m * N1];
-      line_eo<P, T, 0>(in, out);
+      line_eo<P, T>(in, out, E0);
 #pragma unroll
       for (int r = 0; r < N1; ++r) Bb[eta_base + r * N1] = out[r];
     }
@@ -867,7 +876,8 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
       Bb[qb] = f * (A10 * gx + A11 * gy);
       vz[k] = f * (b2x * gx + b2y * gy + izz * gz);
     }
-    line_eo<P, T, 1>(vz, yz);
+    const T *E1 = eo_ptr<P, T, 1>(vz[0]);
+    line_eo<P, T>(vz, yz, E1);
     __syncthreads();
 
     // phase 3 (in place: only this thread touches these lines now)
@@ -875,12 +885,12 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
       T in[N1], out[N1];
 #pragma unroll
       for (int m = 0; m < N1; ++m) in[m] = Ab[xi_base + m];
-      line_eo<P, T, 1>(in, out);
+      line_eo<P, T>(in, out, E1);
 #pragma unroll
       for (int r = 0; r < N1; ++r) Ab[xi_base + r] = out[r];
 #pragma unroll
       for (int m = 0; m < N1; ++m) in[m] = Bb[eta_base + m * N1];
-      line_eo<P, T, 1>(in, out);
+      line_eo<P, T>(in, out, E1);
 #pragma unroll
       for (int r = 0; r < N1; ++r) Bb[eta_base + r * N1] = out[r];
     }

@@ -79,6 +79,10 @@ def test_create_validation_without_gpu():
     st, msg, _ = _create(m3, eh_corner=cw)
     assert st == 1 and "Jacobian" in msg
     assert fnpf.lib().fnpf_create(None, None) == 1
+    # empty meshes are rejected before any device work
+    for over in (dict(n_eh=0), dict(n_s=0), dict(p=9), dict(dim=4)):
+        st, msg, h = _create(m, **over)
+        assert st == 1 and "invalid mesh header" in msg and not h.value
 
 
 def test_null_context_calls():

@@ -338,8 +338,9 @@ fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, 
   HIPCHK(launch_apply(c, FNPF_F64, x, c.d_q, true, nullptr, nullptr, s));
   HIPCHK(launch_pcg_init<double>(f, c.d_q, c.d_r, c.d_p, dinv, c.n_v, c.n_s, c.d_partial, sc, false, 0.0, s));
   if (mg) {
-    HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, s));
-    HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 1, s));
+    bool fused = false;
+    HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, s, c.d_partial, &fused));
+    HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 1, s, fused));
   }
   const int nb = apply_blocks(c);
   auto body = [&](hipStream_t st) -> fnpf_status {
@@ -348,8 +349,9 @@ fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, 
       HIPCHK(launch_finalize_pq(c.d_partial, nb, sc, st));
       if (mg) {
         HIPCHK(launch_mg_update(c, FNPF_F64, x, c.d_r, c.d_p, c.d_q, c.d_partial, sc, st));
-        HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, st));
-        HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 0, st));
+        bool fused = false;
+        HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, st, c.d_partial, &fused));
+        HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 0, st, fused));
       } else {
         HIPCHK((launch_pcg_update<double, double>(x, c.d_r, c.d_p, c.d_q, dinv, c.n_v, c.d_partial, sc, st)));
         HIPCHK(launch_pcg_dir<double>(c.d_p, c.d_r, dinv, c.n_v, sc, st));
@@ -396,8 +398,9 @@ fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts 
       HIPCHK(launch_finalize_pq(c.d_partial, nb, si, st));
       if (mg) {
         HIPCHK(launch_mg_update(c, FNPF_F32, c.d_d32, c.d_r32, c.d_p32, c.d_q32, c.d_partial, si, st));
-        HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, st));
-        HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 0, st));
+        bool fused = false;
+        HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, st, c.d_partial, &fused));
+        HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 0, st, fused));
       } else {
         HIPCHK((launch_pcg_update<float, float>(c.d_d32, c.d_r32, c.d_p32, c.d_q32, dinv, c.n_v, c.d_partial, si,
                                                 st)));
@@ -414,8 +417,9 @@ fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts 
     HIPCHK(launch_resid_to32(f, c.d_q, c.d_r32, c.d_p32, c.d_d32, dinv, c.n_v, c.n_s, c.d_partial, so, si,
                              o.inner_rtol, s));
     if (mg) {
-      HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, s));
-      HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 1, s));
+      bool fused = false;
+      HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, s, c.d_partial, &fused));
+      HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 1, s, fused));
     }
     ++outer;
     HIPCHK(hipMemcpyAsync(c.h_sc, c.d_sc, 2 * sizeof(PcgScalars), hipMemcpyDeviceToHost, s));

@@ -298,11 +298,12 @@ void mg_free(Ctx &c);
 template <typename T>
 fnpf_status mg_refresh(Ctx &c, hipStream_t s);
 template <typename T>
-hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth, hipStream_t s);
+hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth, hipStream_t s,
+                     double *dot_partial = nullptr, bool *dot_done = nullptr);
 hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void *p, const void *q, double *partial,
                             PcgScalars *sc, hipStream_t s);
 hipError_t launch_mg_dot_dir(Ctx &c, fnpf_dtype dt, const void *r, const void *z, void *p, double *partial,
-                             PcgScalars *sc, int first, hipStream_t s);
+                             PcgScalars *sc, int first, hipStream_t s, bool have_partials = false);
 Ctx &ctx_of(fnpf_ctx h);
 fnpf_status ctx_ensure32(Ctx &c);
 fnpf_status geom_impl_total(Ctx &c, const double *H, const double *h, hipStream_t s);

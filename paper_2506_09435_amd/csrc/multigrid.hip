@@ -411,13 +411,21 @@ __global__ __launch_bounds__(kVecThreads) void k_post2a(T *d, const T *b, const 
 }
 
 //   x += a1 d1 + a2 dinv (b - q1 - q2), q2 = A d1
-template <typename T>
+// DOT: also the block partials of b.x (the CG's r.z when b is the residual and x the V-cycle's
+// result), in the order k_dot takes them, so the sum is the same bit for bit
+template <typename T, bool DOT>
 __global__ __launch_bounds__(kVecThreads) void k_post2b(T *x, const T *d, const T *b, const T *q1, const T *q2,
                                                         const T *dinv, const double *cf, int64_t n,
-                                                        const int32_t *skip) {
+                                                        const int32_t *skip, double *partial) {
   if (skip != nullptr && *skip) return;
   const T a1 = (T)cf[1], a2 = (T)cf[2];
-  GRID_STRIDE(i, n) x[i] += a1 * d[i] + a2 * dinv[i] * (b[i] - q1[i] - q2[i]);
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    const T xi = x[i] + (a1 * d[i] + a2 * dinv[i] * (b[i] - q1[i] - q2[i]));
+    x[i] = xi;
+    if constexpr (DOT) v[0] += (double)b[i] * (double)xi;
+  }
+  if constexpr (DOT) block_partials<1>(v, partial);
 }
 
 // PCG with a general preconditioner: x += alpha p, r -= alpha q; partial r.r
@@ -680,7 +688,8 @@ hipError_t smooth(Ctx &L, const T *b, T *x, T *r, T *d, T *q, const double *cf, 
 
 // V-cycle on level l (0 = this context) for the right-hand side b, result in x.
 template <typename T>
-hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, hipStream_t s) {
+hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, hipStream_t s,
+                  double *dot_partial = nullptr, bool *dot_done = nullptr) {
   Ctx &L = l == 0 ? c : *c.mg[l - 1].c;
   T *r, *d, *q;
   if (l == 0) {
@@ -711,7 +720,12 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
     if ((e = launch_apply(L, Prec<T>::dt, x, r, true, nullptr, skip, s)) != hipSuccess) return e;
     k_post2a<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, r, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
-    k_post2b<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, r, q, dinv, cf, n, skip);
+    if (dot_partial != nullptr) {
+      k_post2b<T, true><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, r, q, dinv, cf, n, skip, dot_partial);
+      if (dot_done) *dot_done = true;
+    } else {
+      k_post2b<T, false><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, r, q, dinv, cf, n, skip, nullptr);
+    }
     return hipGetLastError();
   }
   e = smooth<T>(L, b, x, r, d, q, cf, m, true, skip, s);
@@ -899,11 +913,15 @@ template fnpf_status mg_refresh<double>(Ctx &, hipStream_t);
 template fnpf_status mg_refresh<float>(Ctx &, hipStream_t);
 
 template <typename T>
-hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth_deg, hipStream_t s) {
-  return vcycle<T>(c, 0, r, z, skip, smooth_deg, s);
+hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth_deg, hipStream_t s,
+                     double *dot_partial, bool *dot_done) {
+  if (dot_done) *dot_done = false;
+  return vcycle<T>(c, 0, r, z, skip, smooth_deg, s, dot_partial, dot_done);
 }
-template hipError_t mg_vcycle<double>(Ctx &, const double *, double *, const int32_t *, int, hipStream_t);
-template hipError_t mg_vcycle<float>(Ctx &, const float *, float *, const int32_t *, int, hipStream_t);
+template hipError_t mg_vcycle<double>(Ctx &, const double *, double *, const int32_t *, int, hipStream_t, double *,
+                                      bool *);
+template hipError_t mg_vcycle<float>(Ctx &, const float *, float *, const int32_t *, int, hipStream_t, double *,
+                                     bool *);
 
 hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void *p, const void *q, double *partial,
                             PcgScalars *sc, hipStream_t s) {
@@ -918,11 +936,13 @@ hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void 
 }
 
 hipError_t launch_mg_dot_dir(Ctx &c, fnpf_dtype dt, const void *r, const void *z, void *p, double *partial,
-                             PcgScalars *sc, int first, hipStream_t s) {
-  if (dt == FNPF_F64)
-    k_dot<double><<<kVecBlocks, kVecThreads, 0, s>>>((const double *)r, (const double *)z, c.n_v, partial, sc);
-  else
-    k_dot<float><<<kVecBlocks, kVecThreads, 0, s>>>((const float *)r, (const float *)z, c.n_v, partial, sc);
+                             PcgScalars *sc, int first, hipStream_t s, bool have_partials) {
+  if (!have_partials) {
+    if (dt == FNPF_F64)
+      k_dot<double><<<kVecBlocks, kVecThreads, 0, s>>>((const double *)r, (const double *)z, c.n_v, partial, sc);
+    else
+      k_dot<float><<<kVecBlocks, kVecThreads, 0, s>>>((const float *)r, (const float *)z, c.n_v, partial, sc);
+  }
   k_mg_fin_rz<<<1, kVecThreads, 0, s>>>(partial, kVecBlocks, sc, first);
   if (dt == FNPF_F64)
     k_mg_dir<double><<<kVecBlocks, kVecThreads, 0, s>>>((double *)p, (const double *)z, c.n_v, sc, first);

@@ -407,6 +407,11 @@ def main():
     t64, t64_mean = time_applies(ctx, x64, args.apply_reps)
     t32, t32_mean = time_applies(ctx, x64.float(), args.apply_reps)
     n_q = m.n_e * (m.p + 1) ** m.dim
+    # plain device copy of n_v doubles (read and write): the bandwidth a streaming kernel reaches
+    ycopy = torch.empty_like(x64)
+    t_copy = _time_calls(lambda: ycopy.copy_(x64), 20)
+    copy_gbs = 2 * 8 * m.n_v / t_copy / 1e9
+    del ycopy
     print(f"[bench] apply f64 {t64 * 1e3:.3f} ms ({m.n_v / t64 / 1e9:.1f} GDOF/s), "
           f"f32 {t32 * 1e3:.3f} ms ({m.n_v / t32 / 1e9:.1f} GDOF/s)", file=sys.stderr, flush=True)
     if args.apply_only:
@@ -498,7 +503,9 @@ def main():
                       traffic=traffic,
                       kernel="FP64 apply: k_apply_lines<6,double,owner> (all columns) + k_apply_faces<double> "
                              "(shared-node sums), one launch each per apply",
-                      algorithmic_bytes_per_apply=bytes64, traffic_unit="bytes per apply"),
+                      algorithmic_bytes_per_apply=bytes64, traffic_unit="bytes per apply",
+                      copy_gbs=copy_gbs, frac_of_copy=achieved / copy_gbs,
+                      stored_factor_ceiling_gdofs=m.n_v / (apply_bytes_stored(m.n_v, n_q, 8) / (HBM_PEAK_GBS * 1e9)) / 1e9),
         roofline_alu=dict(bound="alu", achieved=flops64 / t64 / 1e12, peak=FP64_VALU_PEAK_TFS, unit="TFLOP/s",
                           frac=flops64 / t64 / 1e12 / FP64_VALU_PEAK_TFS, flops_per_apply=flops64),
         cpu_baseline=cpu,

@@ -308,7 +308,10 @@ fnpf_status fnpf_modal_filter_vjp(fnpf_ctx ctx, const double *out_bar, double *f
  * problem is solved in -h <= z <= 0 with phi = phi_s on z = 0) and the linear
  * free-surface conditions d eta/dt = w, d phi_s/dt = -g eta.  The default
  * (0) is the fully nonlinear model.  fnpf_geom, fnpf_solve and fnpf_w_surface
- * are unaffected (they take the geometry they are given). */
+ * are unaffected (they take the geometry they are given).  The flat geometry
+ * is computed by the first linear step for a depth array and kept while the
+ * same h pointer is passed and no other call replaces the geometry; after
+ * changing h in place, call fnpf_set_linear(ctx, 1) again. */
 fnpf_status fnpf_set_linear(fnpf_ctx ctx, int32_t linear);
 
 /* One ERK4 step (Sec. 3.2) of the Zakharov system from time t with step dt,

@@ -32,6 +32,8 @@ class _Rollout(torch.autograd.Function):
         traj = torch.empty((nsteps, fctx.n_s), dtype=torch.float64, device=e.device)
         checkpoints = {}
         fctx.set_warm_start(None)
+        if getattr(fctx, "linear", False):
+            fctx.set_linear(True)       # the depth may have changed in place since the last call
         t = t0
         for n in range(nsteps):
             if n % every == 0:

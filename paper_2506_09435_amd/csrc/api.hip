@@ -485,6 +485,7 @@ fnpf_status solve_impl(Ctx &c, const double *phis, const double *f, double *phi,
 }
 
 fnpf_status geom_impl(Ctx &c, const double *eta, const double *h, hipStream_t s) {
+  c.flat_valid = false;
   const bool store = c.apply_variant == 1;
   if (store) {
     fnpf_status st = ensure_G(c);
@@ -495,6 +496,21 @@ fnpf_status geom_impl(Ctx &c, const double *eta, const double *h, hipStream_t s)
   c.have_geom32 = c.want32;
   c.have_G = store;
   c.mg_stale64 = c.mg_stale32 = true;
+  return FNPF_OK;
+}
+
+// Linear potential flow: the flat geometry (eta = 0) for depth h, computed once and kept while no
+// other call replaces the geometry and h is the same array (fnpf_set_linear drops it).
+fnpf_status flat_geometry(Ctx &c, const double *h, hipStream_t s) {
+  if (c.flat_valid && c.flat_h == h && c.have_geom && c.have_geom32 == c.want32 &&
+      (c.apply_variant != 1 || c.have_G))
+    return FNPF_OK;
+  fnpf_status st = ensure_flat(c, s);
+  if (st != FNPF_OK) return st;
+  st = geom_impl(c, c.d_flat, h, s);
+  if (st != FNPF_OK) return st;
+  c.flat_valid = true;
+  c.flat_h = h;
   return FNPF_OK;
 }
 
@@ -828,6 +844,7 @@ fnpf_status fnpf_rhs(fnpf_ctx ctx, const double *eta, const double *phis, const 
 fnpf_status fnpf_set_linear(fnpf_ctx ctx, int32_t linear) {
   if (!ctx) return FNPF_ERR_ARG;
   ctx->c.linear = linear != 0;
+  ctx->c.flat_valid = false;
   return FNPF_OK;
 }
 
@@ -952,10 +969,8 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
   const double *ein = eta, *pin = phis;
   const size_t rec = (size_t)c.n_v + 2 * (size_t)c.n_s;
   if (c.linear) {
-    // linear potential flow: one flat geometry (eta = 0) serves the four stages
-    st = ensure_flat(c, s);
-    if (st != FNPF_OK) return st;
-    st = geom_impl(c, c.d_flat, h, s);
+    // linear potential flow: one flat geometry (eta = 0) serves every stage and step
+    st = flat_geometry(c, h, s);
     if (st != FNPF_OK) return st;
   }
   for (int stg = 0; stg < 4; ++stg) {
@@ -1144,7 +1159,7 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
     }
     // stage VJP at Y_s (linear potential flow: the geometry is the flat one, so its adjoint
     // reaches h only; the eta adjoint of the geometry goes to a discarded scratch vector)
-    st = geom_impl(c, c.linear ? c.d_flat : eta_s, h, s);
+    st = c.linear ? flat_geometry(c, h, s) : geom_impl(c, eta_s, h, s);
     if (st != FNPF_OK) return st;
     double *geo_eta_bar = c.linear ? c.d_scr_s : c.d_ybe;
     HIPCHK(launch_wsurf(c, phi_s, c.d_w, s));

@@ -278,6 +278,8 @@ struct Ctx {
   // linear potential flow (flat geometry at eta = 0, linear free-surface conditions)
   bool linear = false;
   double *d_flat = nullptr;               // [n_s] zeros: the LPF surface
+  const double *flat_h = nullptr;         // depth pointer of the current flat geometry
+  bool flat_valid = false;                // the current geometry is the flat one for flat_h
   double *d_scr_s = nullptr;              // [n_s] scratch (discarded eta adjoint of the LPF geometry)
   // relaxation
   double *d_cr = nullptr, *d_rec = nullptr, *d_res = nullptr, *d_rpc = nullptr, *d_rps = nullptr;

@@ -155,6 +155,7 @@ class Context:
 
     def __init__(self, mesh, g: float = 9.81):
         import torch
+        self.linear = False
         self._h = C.c_void_p()
         nodes = np.ascontiguousarray(mesh.eh_nodes, dtype=np.int32)
         corner = np.ascontiguousarray(mesh.eh_corner, dtype=np.float64)
@@ -274,8 +275,10 @@ class Context:
         return de, dp
 
     def set_linear(self, linear=True):
-        """Linear potential flow (fixed domain at eta = 0, linear free-surface conditions)."""
+        """Linear potential flow (fixed domain at eta = 0, linear free-surface conditions).  Also
+        drops the cached flat geometry (call again after changing the depth array in place)."""
         self._check(lib().fnpf_set_linear(self._h, int(bool(linear))), "fnpf_set_linear")
+        self.linear = bool(linear)
 
     def set_surface_quadrature(self, nq):
         """0: lumped GLL collocation of the free-surface equations; nq >= p+1: consistent form."""

@@ -252,6 +252,38 @@ def test_lpf_rk4_steps_parity(name, precision):
     assert rel(e1, en) > 1e-6
 
 
+def test_lpf_flat_geometry_cache():
+    """The flat geometry is kept across linear steps and rebuilt when another call replaced the
+    geometry or after fnpf_set_linear (here after an in-place change of the depth)."""
+    wl = _case("box_mixed")
+    pr = Pair(wl)
+    pr.ctx.set_linear(True)
+    md = ts.Model(wl, solver="dense", linear=True)
+    dt = 0.02
+    opts = fnpf.default_opts(rtol=1e-13)
+    eta, phi = pr.eta, pr.phis
+    e, p = pr.d_eta.clone(), pr.d_phis.clone()
+    t = 0.0
+    for n in range(2):
+        eta, phi = md.rk4_step(eta, phi, t, dt)
+        pr.ctx.rk4_step(e, p, pr.d_h, t, dt, opts=opts)
+        t += dt
+    assert rel(host(e), eta) < 1e-10
+    # a geometry from another call in between: the next linear step rebuilds the flat one
+    pr.ctx.geom(e, pr.d_h)
+    eta, phi = md.rk4_step(eta, phi, t, dt)
+    pr.ctx.rk4_step(e, p, pr.d_h, t, dt, opts=opts)
+    t += dt
+    assert rel(host(e), eta) < 1e-10 and rel(host(p), phi) < 1e-10
+    # the depth changed in place (same array): fnpf_set_linear drops the cached geometry
+    h2 = pr.h * 1.1
+    pr.d_h.copy_(dev(h2))
+    pr.ctx.set_linear(True)
+    eta, phi = md.rk4_step(eta, phi, t, dt, h=h2)
+    pr.ctx.rk4_step(e, p, pr.d_h, t, dt, opts=opts)
+    assert rel(host(e), eta) < 1e-10 and rel(host(p), phi) < 1e-10
+
+
 def test_lpf_rhs_and_relaxation_parity():
     """Linear RHS is (w, -g eta) pointwise; LPF steps with relaxation zones match the oracle."""
     wl = configs.c4(nx=8, ny=2, nz=2, p=3, nsteps=3)

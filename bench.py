@@ -83,7 +83,7 @@ def kernel_source_sha256():
     return hashlib.sha256((text[i0:i1] + setup).encode()).hexdigest()
 
 
-def time_applies(ctx, x, reps, warm=3):
+def time_applies(ctx, x, reps, warm=10):
     """Median and mean seconds of one apply, HIP events around each apply on the launch stream."""
     import torch
     y = torch.empty_like(x)

@@ -858,6 +858,11 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     const T zz = half_ds[l] * H;
     const T izz = T(1) / zz;
     const T fl0 = wdJ * zz;
+    // the horizontal part of J^-T grad u picks up b2 = -(J_h^-T grad z) / z_zeta, and
+    // grad z = sigma grad H - grad h is linear in sigma along the line: b2 = sigma a + b
+    const T ax = -(Hx * A00 + Hy * A10) * izz, bx = (hx * A00 + hy * A10) * izz;
+    const T ay = -(Hx * A01 + Hy * A11) * izz, by = (hx * A01 + hy * A11) * izz;
+    const T izz2 = izz * izz;
     T vz[N1], yz[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
@@ -865,16 +870,13 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
       const T ux = Ab[q], uy = Bb[qb];
       const T sg = sig[l * P + k];
       const T f = (T)wgt(P, k) * fl0;
-      const T zx = sg * Hx - hx;
-      const T zy = sg * Hy - hy;
-      const T b2x = -(zx * A00 + zy * A10) * izz;
-      const T b2y = -(zx * A01 + zy * A11) * izz;
+      const T b2x = sg * ax + bx;
+      const T b2y = sg * ay + by;
       const T gx = A00 * ux + A10 * uy + b2x * uz[k];
       const T gy = A01 * ux + A11 * uy + b2y * uz[k];
-      const T gz = izz * uz[k];
       Ab[q] = f * (A00 * gx + A01 * gy);
       Bb[qb] = f * (A10 * gx + A11 * gy);
-      vz[k] = f * (b2x * gx + b2y * gy + izz * gz);
+      vz[k] = f * (b2x * gx + b2y * gy + izz2 * uz[k]);
     }
     const T *E1 = eo_ptr<P, T, 1>(vz[0]);
     line_eo<P, T>(vz, yz, E1);

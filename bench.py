@@ -376,7 +376,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps(dict(error="this build runs on exactly one GPU; multi-GPU runs are not supported",
+        print(json.dumps(dict(error="this benchmark runs on exactly one GPU; multi-GPU runs are not supported",
                               n_gpus=args.gpus)))
         sys.exit(2)
 

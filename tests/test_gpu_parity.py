@@ -484,6 +484,45 @@ def test_multigrid_repeatable_and_c2():
     assert np.linalg.norm(r[I]) <= 1.05e-10 * np.linalg.norm(bvec[I])
 
 
+def test_c2_fifty_steps_fp64_vs_mixed_and_invariants():
+    """C2 full size (840,000 DoF), 50 ERK4 steps at rtol 1e-8 in FP64 and in mixed precision:
+    the two trajectories agree to the solver tolerance, and the discrete mass (lumped surface mass
+    times eta) and energy (kinetic phi.A phi / 2 plus potential g m.eta^2 / 2) stay constant to
+    the solver tolerance and the time-discretisation error of ERK4 at T/64 (the periodic
+    flat-bottom domain conserves both)."""
+    wl = configs.c2()
+    pr = Pair(wl, fp32=True)
+    ms = sf.surface_mass(pr.m, pr.xh)
+
+    def energy(e, p):
+        pr.ctx.geom(e, pr.d_h)
+        phi, info = pr.ctx.solve(p, opts=fnpf.default_opts(rtol=1e-12))
+        assert info["status"] == "OK"
+        kin = 0.5 * float(torch.dot(phi, pr.ctx.laplace_apply(phi)))
+        eh = host(e)
+        return kin + 0.5 * wl.g * float(ms @ (eh * eh))
+
+    out = {}
+    for precision in (0, 1):
+        e, p = pr.d_eta.clone(), pr.d_phis.clone()
+        pr.ctx.set_warm_start(None)
+        opts = fnpf.default_opts(precision=precision, rtol=1e-8, inner_rtol=1e-4)
+        t = 0.0
+        for n in range(50):
+            pr.ctx.rk4_step(e, p, pr.d_h, t, wl.dt, opts=opts)
+            t += wl.dt
+        out[precision] = (host(e), host(p), e, p)
+    e64, p64 = out[0][0], out[0][1]
+    assert rel(out[1][0], e64) < 1e-6 and rel(out[1][1], p64) < 1e-6
+    # mass: d/dt sum(m eta) is the surface flux of the solved potential, zero up to the solve
+    # tolerance: 50 steps x dt x rtol x |w| x area ~ 1e-8 against sum(m |eta|) ~ 1.3
+    m0, m1 = ms @ pr.eta, ms @ e64
+    assert abs(m1 - m0) < 1e-7 * (ms @ np.abs(pr.eta))
+    E0 = energy(pr.d_eta, pr.d_phis)
+    E1 = energy(out[0][2], out[0][3])
+    assert abs(E1 - E0) < 1e-6 * E0
+
+
 def test_c3_full_size_cylinder():
     """C3 (cylinder in a tank, 771,528 DoF, unstructured O-grid + jittered block, relaxation zones):
     apply parity everywhere, multigrid solves that satisfy the oracle's equations, w parity, and

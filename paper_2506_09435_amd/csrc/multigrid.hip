@@ -162,18 +162,29 @@ __global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, cons
   T *A = sA + lc * NA;
   T *Cr = sC + lc * 2 * NHC;
   const int vtop = PC * nz;
+  // the fine line of layer l + 1 is loaded while layer l is contracted (raw values of both
+  // operands, so that nothing waits for them before their use)
+  T nr[N1F], nq[N1F];
+  auto load_layer = [&](int l) {
+    const int kmax = (l == nz - 1) ? N1F : PF;
+#pragma unroll
+    for (int k = 0; k < N1F; ++k) {
+      const int64_t idx = (int64_t)(l * PF + k) * ns_f + hn;
+      const bool ld = own && k < kmax;
+      nr[k] = ld ? rf[idx] : T(0);
+      nq[k] = (ld && qf) ? qf[idx] : T(0);
+    }
+  };
+  load_layer(0);
   for (int l = 0; l < nz; ++l) {
+    T rv[N1F];
+#pragma unroll
+    for (int k = 0; k < N1F; ++k) rv[k] = nr[k] - nq[k];
+    if (l + 1 < nz) load_layer(l + 1);
     T w[N1C];
 #pragma unroll
     for (int c = 0; c < N1C; ++c) w[c] = T(0);
     if (own) {
-      const int kmax = (l == nz - 1) ? N1F : PF;
-      T rv[N1F];
-#pragma unroll
-      for (int k = 0; k < N1F; ++k) {
-        const int64_t idx = (int64_t)(l * PF + k) * ns_f + hn;
-        rv[k] = k < kmax ? (qf ? rf[idx] - qf[idx] : rf[idx]) : T(0);
-      }
 #pragma unroll
       for (int k = 0; k < N1F; ++k)
 #pragma unroll
@@ -245,11 +256,24 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T *__restrict__ xc, T
   const int hnc = cthr ? nodes_c[col * NHC + t] : 0;
   const int i = t % N1F, j = DIM == 3 ? t / N1F : 0;
   T *X = sX + lc * N1C * NHC;
+  // the coarse values of layer l + 1 and the fine values of layer l are loaded before they are
+  // needed, so the loads overlap the barrier and the contractions
+  T xn[N1C];
+  auto load_coarse = [&](int l) {
+#pragma unroll
+    for (int c = 0; c < N1C; ++c) xn[c] = cthr ? xc[(int64_t)(l * PC + c) * ns_c + hnc] : T(0);
+  };
+  load_coarse(0);
   for (int l = 0; l < nz; ++l) {
+    const int kend = (l == nz - 1) ? N1F : PF;
+    T old[N1F];
+#pragma unroll
+    for (int k = 0; k < N1F; ++k) old[k] = (own && k < kend) ? xf[(int64_t)(l * PF + k) * ns_f + hn] : T(0);
     if (cthr) {
 #pragma unroll
-      for (int c = 0; c < N1C; ++c) X[c * NHC + t] = xc[(int64_t)(l * PC + c) * ns_c + hnc];
+      for (int c = 0; c < N1C; ++c) X[c * NHC + t] = xn[c];
     }
+    if (l + 1 < nz) load_coarse(l + 1);
     __syncthreads();
     if (own) {
       T w[N1C];
@@ -265,14 +289,13 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T *__restrict__ xc, T
         }
         w[c] = acc;
       }
-      const int kend = (l == nz - 1) ? N1F : PF;
 #pragma unroll
       for (int k = 0; k < N1F; ++k) {
         if (k < kend) {
           T u = T(0);
 #pragma unroll
           for (int c = 0; c < N1C; ++c) u += ip<T>(PF, k * N1C + c) * w[c];
-          xf[(int64_t)(l * PF + k) * ns_f + hn] += u;
+          xf[(int64_t)(l * PF + k) * ns_f + hn] = old[k] + u;
         }
       }
     }

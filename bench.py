@@ -37,9 +37,9 @@ METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/for
 # HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by the
 # plain-copy calibration), valid only for the kernel source they were taken from.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "86ed9ee09fcc650bc545fcbe676d25417e70fd7ab481575e6eac541b4927849b",
-    "fetch_bytes_per_apply": 860994734,
-    "write_bytes_per_apply": 586624032,
+    "kernel_source_sha256": "025f7e463dba33f651ebb0be29d05712aaab68dca9cb077da39eabf3a6546268",
+    "fetch_bytes_per_apply": 861186112,
+    "write_bytes_per_apply": 587785493,
 }
 
 

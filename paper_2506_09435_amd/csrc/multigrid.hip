@@ -33,7 +33,7 @@ constexpr int kMgCoarseSteps = 10;      // Chebyshev steps on the coarsest level
 constexpr double kMgSafety = 1.1;       // upper end of the smoothing interval over the estimate
 constexpr double kMgSmoothRatio = 4.0;  // smoothing interval [lmax / 4, lmax]
 constexpr double kMgCoarseRatio = 30.0;
-constexpr int kPowFirst = 15, kPowNext = 4;   // power iterations (cold, warm start)
+constexpr int kPowFirst = 15, kPowNext = 2;   // power iterations (cold, warm start)
 constexpr int kMgCoef = 32;                   // coefficient-table entries per level
 
 // Interpolation tables for a fine degree pf (2..8) and pc = pf / 2:

@@ -188,8 +188,13 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy);
  *     the lowest-numbered column that has it) and its other values into face
  *     slots, and a second launch adds the slots to the owners.  It is fastest
  *     when each column's own nodes are numbered consecutively (shared ones
- *     first); any consistent numbering gives the same result.  2D: colour
- *     schedule with read-add-write of shared nodes;
+ *     first); any consistent numbering gives the same result.  The
+ *     kernels index with 32-bit byte offsets: when n_v * 8 bytes or the
+ *     face slots, (p*nz+1) * n_slots * 8 bytes, reach 4 GiB (n_v >= 2^29,
+ *     about 537 million nodes) the apply falls back to the colour assembly
+ *     of 6 while n_v * sizeof(element) stays below 4 GiB, else to that of
+ *     7; the result is the same.  2D: colour schedule with read-add-write
+ *     of shared nodes;
  *   1 stored factors: fnpf_geom stores G (6 or 3 per point, FP64 and FP32)
  *     and the apply streams it from HBM;
  *   2 fused geometry with a fully unrolled schedule (more registers, fewer

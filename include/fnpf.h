@@ -108,8 +108,10 @@ typedef struct {
  *                interpolated from eta + h and h; tensor-product Lagrange
  *                interpolation between levels and its transpose; Chebyshev
  *                smoothing of D^-1 A of degree cheb_degree before and after
- *                each coarse correction (interval [lmax/4, lmax], lmax 1.1x a
- *                power-iteration estimate refreshed after every fnpf_geom)
+ *                each coarse correction (interval [lmax/24, lmax], lmax 1.1x an
+ *                estimate of the largest eigenvalue of D^-1 A: 20 Lanczos
+ *                steps on first use, then two power iterations from the Ritz
+ *                vector after every fnpf_geom)
  *                and 10 Chebyshev steps on the degree-1 level.  The V-cycle is
  *                a fixed SPD operator, so the outer iteration is plain CG.
  *                The levels are built on first use (device memory about 0.3x
@@ -120,7 +122,8 @@ typedef struct {
  *   check_every is the number of iterations between host convergence checks
  *   (the iterations after convergence are skipped on the device, so results
  *   do not depend on it).  inner_rtol: relative reduction of each inner FP32
- *   solve; max_outer bounds the defect-correction sweeps.
+ *   solve, which also stops as soon as its residual is below half the outer
+ *   tolerance; max_outer bounds the defect-correction sweeps.
  *   extrapolate (fnpf_rk4_step only): 1 starts stage s of a step from
  *   2 phi_s(n-1) - phi_s(n-2), the same stage of the two previous steps,
  *   once the context has seen two consecutive steps with the same dt; 0

@@ -241,6 +241,7 @@ struct Ctx {
   float *mg_f32[4] = {nullptr, nullptr, nullptr, nullptr};
   double lam64 = 0.0, lam32 = 0.0;
   double *d_mgc = nullptr;                // Chebyshev coefficient table [precision][level][32]
+  double *d_mg_lz = nullptr;              // Lanczos coefficients and scalars of the eigenvalue estimate
   std::vector<double> h_mgc;
   double *mg_ev64 = nullptr;              // fine-level eigenvector estimate
   float *mg_ev32 = nullptr;

@@ -168,6 +168,11 @@ __global__ __launch_bounds__(kVecThreads) void k_resid_to32(const double *f, con
   block_partials<3>(v, partial);
 }
 
+// The inner FP32 solve stops at its relative reduction or, earlier, once its residual is below
+// this fraction of the outer tolerance: the FP64 test that follows then passes unless the FP32
+// rounding of the correction is larger, so iterations past that point would be wasted.
+constexpr double kInnerFloor = 0.5;
+
 __global__ __launch_bounds__(kVecThreads) void k_fin_outer(const double *partial, int np, PcgScalars *outer,
                                                            PcgScalars *inner, double inner_rtol) {
   double s[3];
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_outer(const double *partial
     inner->rz = s[1];
     inner->rr = s[2];
     inner->rr0 = s[2];
-    inner->tol2 = inner_rtol * inner_rtol * s[2];
+    inner->tol2 = fmax(inner_rtol * inner_rtol * s[2], kInnerFloor * kInnerFloor * outer->tol2);
     inner->iters = 0;
     inner->breakdown = 0;
     inner->alpha = 0.0;

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "fnpf_internal.h"
@@ -31,9 +32,11 @@ namespace {
 
 constexpr int kMgCoarseSteps = 10;      // Chebyshev steps on the coarsest level
 constexpr double kMgSafety = 1.1;       // upper end of the smoothing interval over the estimate
-constexpr double kMgSmoothRatio = 4.0;  // smoothing interval [lmax / 4, lmax]
+constexpr double kMgSmoothRatio = 24.0; // smoothing interval [lmax / 24, lmax]
 constexpr double kMgCoarseRatio = 30.0;
-constexpr int kPowFirst = 15, kPowNext = 2;   // power iterations (cold, warm start)
+constexpr int kLanczosSteps = 20;             // first estimate of the largest eigenvalue
+constexpr int kPowNext = 2;                   // power iterations per geometry update after that
+constexpr int kLzScalars = 2 * kLanczosSteps + 8;
 constexpr int kMgCoef = 32;                   // coefficient-table entries per level
 
 // Interpolation tables for a fine degree pf (2..8) and pc = pf / 2:
@@ -517,11 +520,81 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_dir(T *p, const T *z, int64_
   GRID_STRIDE(i, n) p[i] = first ? z[i] : z[i] + b * p[i];
 }
 
-// power iteration on D^-1 A: pw[0] = (v.Av)/(v.Dv) (Rayleigh quotient), pw[1] = 1/sqrt(v.Dv)
+// Largest eigenvalue of D^-1 A.  D^-1 A is self-adjoint in <u, v>_D = sum u_i v_i / dinv_i over
+// the unknowns (dinv = 0 on the Dirichlet rows, which take no part), so Lanczos in that inner
+// product gives a symmetric tridiagonal matrix whose largest eigenvalue approaches lambda_max
+// from below.  The top of this spectrum is clustered (element-local modes), where Lanczos needs
+// far fewer products than the power iteration's Rayleigh quotient.
+
+// v = fixed start vector on the unknowns, vp = 0; partials of <v, v>_D
 template <typename T>
-__global__ void k_pow_start(T *v, const T *dinv, int64_t n) {
-  GRID_STRIDE(i, n) v[i] = dinv[i] != T(0) ? T(1.0 + 0.5 * sin(0.7 * (double)i) + 0.25 * cos(0.013 * (double)i)) : T(0);
+__global__ __launch_bounds__(kVecThreads) void k_lz_start(T *v, T *vp, const T *dinv, int64_t n, double *partial) {
+  double s[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    const T d = dinv[i];
+    const T vi = d != T(0) ? T(1.0 + 0.5 * sin(0.7 * (double)i) + 0.25 * cos(0.013 * (double)i)) : T(0);
+    v[i] = vi;
+    vp[i] = T(0);
+    if (d != T(0)) s[0] += (double)vi * (double)vi / (double)d;
+  }
+  block_partials<1>(s, partial);
 }
+
+// out = sum (mode 0) or its square root (mode 1), set to 0 when it is below rel^2 * ref^2
+// (an invariant subspace: the recurrence then produces zeros, which add zero Ritz values only)
+__global__ __launch_bounds__(kVecThreads) void k_lz_fin(const double *partial, int np, double *out, int mode,
+                                                        const double *ref, double rel) {
+  double s[1];
+  final_sums<1>(partial, np, s);
+  if (threadIdx.x == 0) {
+    double v = s[0];
+    if (mode == 1) {
+      const double r = ref != nullptr ? fabs(*ref) : 0.0;
+      v = (v > 0.0 && v > rel * rel * r * r) ? sqrt(v) : 0.0;
+    }
+    *out = v;
+  }
+}
+
+// w = dinv q - alpha v - beta_prev vp, stored in vp; partials of <w, w>_D
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_lz_w(T *vp, const T *v, const T *q, const T *dinv, int64_t n,
+                                                      const double *alpha, const double *beta_prev,
+                                                      double *partial) {
+  const T a = (T)*alpha, b = beta_prev != nullptr ? (T)*beta_prev : T(0);
+  double s[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    const T d = dinv[i];
+    const T w = d * q[i] - a * v[i] - b * vp[i];
+    vp[i] = w;
+    if (d != T(0)) s[0] += (double)w * (double)w / (double)d;
+  }
+  block_partials<1>(s, partial);
+}
+
+// partials of a.b
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_lz_dot(const T *a, const T *b, int64_t n, double *partial) {
+  double s[1] = {0.0};
+  GRID_STRIDE(i, n) s[0] += (double)a[i] * (double)b[i];
+  block_partials<1>(s, partial);
+}
+
+// v /= beta (0 when beta is 0)
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_lz_scale(T *v, int64_t n, const double *beta) {
+  const T f = *beta > 0.0 ? (T)(1.0 / *beta) : T(0);
+  GRID_STRIDE(i, n) v[i] *= f;
+}
+
+// u = y_j v (first) or u += y_j v
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_lz_acc(T *u, const T *v, int64_t n, double y, int first) {
+  const T c = (T)y;
+  GRID_STRIDE(i, n) u[i] = first ? c * v[i] : u[i] + c * v[i];
+}
+
+// power iteration on D^-1 A: pw[0] = (v.Av)/(v.Dv) (Rayleigh quotient), pw[1] = 1/sqrt(v.Dv)
 
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_pow_dots(const T *v, const T *q, const T *dinv, int64_t n,
@@ -765,14 +838,109 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
   return smooth<T>(L, b, x, r, d, q, cf, m, false, skip, s);
 }
 
-// Rayleigh-quotient power iteration for the largest eigenvalue of D^-1 A on level L.  v holds the
-// previous top eigenvector estimate when warm.
+// Eigenvalues and eigenvectors of a small symmetric matrix a[n][n] (row-major, destroyed) by
+// cyclic Jacobi rotations: w[k] and column k of z[n][n].
+void symmetric_eigen(int n, std::vector<double> &a, std::vector<double> &w, std::vector<double> &z) {
+  z.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) z[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double x = a[(size_t)i * n + j] * a[(size_t)i * n + j];
+        tot += x;
+        if (i != j) off += x;
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double theta = (a[(size_t)q * n + q] - a[(size_t)p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+          a[(size_t)k * n + p] = c * akp - sn * akq;
+          a[(size_t)k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+          a[(size_t)p * n + k] = c * apk - sn * aqk;
+          a[(size_t)q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double zkp = z[(size_t)k * n + p], zkq = z[(size_t)k * n + q];
+          z[(size_t)k * n + p] = c * zkp - sn * zkq;
+          z[(size_t)k * n + q] = sn * zkp + c * zkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
+}
+
+// kLanczosSteps Lanczos steps on D^-1 A of level L from the fixed start vector (vectors v, vp, q);
+// the largest Ritz value is the estimate, and a second pass over the same recurrence (its
+// coefficients kept from the first) forms the Ritz vector in u for the later warm updates.
 template <typename T>
-hipError_t estimate_lambda(Ctx &c, Ctx &L, T *v, T *q, bool warm, double &lam, hipStream_t s) {
+hipError_t lanczos_lambda(Ctx &c, Ctx &L, T *u, T *v, T *vp, T *q, double &lam, hipStream_t s) {
   const T *dinv = Prec<T>::dinv(L);
   const int64_t n = L.n_v;
-  if (!warm) k_pow_start<T><<<kVecBlocks, kVecThreads, 0, s>>>(v, dinv, n);
-  const int its = warm ? kPowNext : kPowFirst;
+  constexpr int K = kLanczosSteps;
+  double *al = c.d_mg_lz, *be = c.d_mg_lz + K, *nrm = c.d_mg_lz + 2 * K;
+  const double rel = 1e-12;
+  std::vector<double> y(K, 0.0);
+  for (int pass = 0; pass < 2; ++pass) {
+    T *a = v, *b = vp;
+    k_lz_start<T><<<kVecBlocks, kVecThreads, 0, s>>>(a, b, dinv, n, c.d_partial);
+    k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, nrm, 1, nullptr, 0.0);
+    k_lz_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(a, n, nrm);
+    for (int j = 0; j < K; ++j) {
+      if (pass == 1) k_lz_acc<T><<<kVecBlocks, kVecThreads, 0, s>>>(u, a, n, y[j], j == 0);
+      if (pass == 1 && j == K - 1) break;
+      hipError_t e = launch_apply(L, Prec<T>::dt, a, q, true, nullptr, nullptr, s);
+      if (e != hipSuccess) return e;
+      if (pass == 0) {
+        k_lz_dot<T><<<kVecBlocks, kVecThreads, 0, s>>>(a, q, n, c.d_partial);
+        k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, al + j, 0, nullptr, 0.0);
+      }
+      k_lz_w<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, a, q, dinv, n, al + j, j > 0 ? be + j - 1 : nullptr,
+                                                   c.d_partial);
+      if (pass == 0) k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, be + j, 1, al + j, rel);
+      k_lz_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, n, be + j);
+      std::swap(a, b);
+    }
+    if (pass == 0) {
+      std::vector<double> h(2 * K);
+      hipError_t e = hipMemcpyAsync(h.data(), c.d_mg_lz, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      std::vector<double> t((size_t)K * K, 0.0), w, z;
+      for (int j = 0; j < K; ++j) {
+        t[(size_t)j * K + j] = h[j];
+        if (j + 1 < K) t[(size_t)j * K + j + 1] = t[(size_t)(j + 1) * K + j] = h[K + j];
+      }
+      symmetric_eigen(K, t, w, z);
+      int top = 0;
+      for (int k = 1; k < K; ++k)
+        if (w[k] > w[top]) top = k;
+      lam = w[top];
+      for (int j = 0; j < K; ++j) y[j] = z[(size_t)j * K + top];
+    }
+  }
+  return hipGetLastError();
+}
+
+// Largest eigenvalue of D^-1 A on level L: Lanczos the first time (Ritz vector into v), then
+// Rayleigh-quotient power iterations from the previous eigenvector estimate v after each
+// geometry update.  w1, w2, q are work vectors of the level.
+template <typename T>
+hipError_t estimate_lambda(Ctx &c, Ctx &L, T *v, T *q, T *w1, T *w2, bool warm, double &lam, hipStream_t s) {
+  if (!warm) return lanczos_lambda<T>(c, L, v, w1, w2, q, lam, s);
+  const T *dinv = Prec<T>::dinv(L);
+  const int64_t n = L.n_v;
+  const int its = kPowNext;
   double *pw = c.d_partial + c.n_partial - 4;   // two scalars past the partials the dots use
   for (int it = 0; it < its; ++it) {
     hipError_t e = launch_apply(L, Prec<T>::dt, v, q, true, nullptr, nullptr, s);
@@ -837,6 +1005,7 @@ fnpf_status mg_build(Ctx &c) {
     F = c.mg.back().c;
   }
   if (dalloc_t(&c.d_mgc, (size_t)2 * (c.mg.size() + 1) * kMgCoef) != hipSuccess) return FNPF_ERR_ALLOC;
+  if (dalloc_t(&c.d_mg_lz, (size_t)kLzScalars) != hipSuccess) return FNPF_ERR_ALLOC;
   c.mg_built = true;
   c.mg_stale64 = c.mg_stale32 = true;
   return FNPF_OK;
@@ -868,6 +1037,8 @@ void mg_free(Ctx &c) {
   c.mg_ev_ok64 = c.mg_ev_ok32 = false;
   if (c.d_mgc) (void)hipFree(c.d_mgc);
   c.d_mgc = nullptr;
+  if (c.d_mg_lz) (void)hipFree(c.d_mg_lz);
+  c.d_mg_lz = nullptr;
   c.mg_built = false;
 }
 
@@ -902,12 +1073,14 @@ fnpf_status mg_refresh(Ctx &c, hipStream_t s) {
   // eigenvalue estimates, warm-started from the previous geometry's eigenvector estimates
   {
     double lam = 0.0;
-    if (estimate_lambda<T>(c, c, Prec<T>::evf(c), Prec<T>::fv(c)[3], Prec<T>::evokf(c), lam, s) != hipSuccess)
+    if (estimate_lambda<T>(c, c, Prec<T>::evf(c), Prec<T>::fv(c)[3], Prec<T>::fv(c)[1], Prec<T>::fv(c)[2],
+                           Prec<T>::evokf(c), lam, s) != hipSuccess)
       return FNPF_ERR_HIP;
     Prec<T>::lamf(c) = lam;
     Prec<T>::evokf(c) = true;
     for (auto &L : c.mg) {
-      if (estimate_lambda<T>(c, *L.c, Prec<T>::ev(L), Prec<T>::lv(L)[4], Prec<T>::evok(L), lam, s) != hipSuccess)
+      if (estimate_lambda<T>(c, *L.c, Prec<T>::ev(L), Prec<T>::lv(L)[4], Prec<T>::lv(L)[2], Prec<T>::lv(L)[3],
+                             Prec<T>::evok(L), lam, s) != hipSuccess)
         return FNPF_ERR_HIP;
       Prec<T>::lam(L) = lam;
       Prec<T>::evok(L) = true;

@@ -514,10 +514,14 @@ def test_c2_fifty_steps_fp64_vs_mixed_and_invariants():
         out[precision] = (host(e), host(p), e, p)
     e64, p64 = out[0][0], out[0][1]
     assert rel(out[1][0], e64) < 1e-6 and rel(out[1][1], p64) < 1e-6
-    # mass: d/dt sum(m eta) is the surface flux of the solved potential, zero up to the solve
-    # tolerance: 50 steps x dt x rtol x |w| x area ~ 1e-8 against sum(m |eta|) ~ 1.3
+    # mass: d/dt sum(m eta) is the surface flux of the solved potential.  A annihilates constants,
+    # so the total flux is minus the sum of the solve residual over the unknowns, at most
+    # sqrt(n_I) ||r|| <= sqrt(n_I) rtol ||b|| per stage: zero only up to the solve tolerance, with a
+    # constant that depends on how coherent the final residual is (measured: 2e-7 of
+    # sum(m |eta|) ~ 1.3 at rtol 1e-8 with the multigrid CG).  An error in the kinematic condition
+    # or the w recovery moves it by ~1e-2.
     m0, m1 = ms @ pr.eta, ms @ e64
-    assert abs(m1 - m0) < 1e-7 * (ms @ np.abs(pr.eta))
+    assert abs(m1 - m0) < 1e-6 * (ms @ np.abs(pr.eta))
     E0 = energy(pr.d_eta, pr.d_phis)
     E1 = energy(out[0][2], out[0][3])
     assert abs(E1 - E0) < 1e-6 * E0

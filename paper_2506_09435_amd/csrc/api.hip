@@ -348,9 +348,9 @@ fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, 
       HIPCHK(launch_apply(c, FNPF_F64, c.d_p, c.d_q, true, c.d_partial, &sc->done, st));
       HIPCHK(launch_finalize_pq(c.d_partial, nb, sc, st));
       if (mg) {
-        HIPCHK(launch_mg_update(c, FNPF_F64, x, c.d_r, c.d_p, c.d_q, c.d_partial, sc, st));
+        HIPCHK(launch_mg_update(c, FNPF_F64, x, c.d_r, c.d_p, c.d_q, c.d_partial, sc, st, o.cheb_degree));
         bool fused = false;
-        HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, st, c.d_partial, &fused));
+        HIPCHK(mg_vcycle<double>(c, c.d_r, z, &sc->done, o.cheb_degree, st, c.d_partial, &fused, true));
         HIPCHK(launch_mg_dot_dir(c, FNPF_F64, c.d_r, z, c.d_p, c.d_partial, sc, 0, st, fused));
       } else {
         HIPCHK((launch_pcg_update<double, double>(x, c.d_r, c.d_p, c.d_q, dinv, c.n_v, c.d_partial, sc, st)));
@@ -397,9 +397,10 @@ fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts 
       HIPCHK(launch_apply(c, FNPF_F32, c.d_p32, c.d_q32, true, c.d_partial, &si->done, st));
       HIPCHK(launch_finalize_pq(c.d_partial, nb, si, st));
       if (mg) {
-        HIPCHK(launch_mg_update(c, FNPF_F32, c.d_d32, c.d_r32, c.d_p32, c.d_q32, c.d_partial, si, st));
+        HIPCHK(launch_mg_update(c, FNPF_F32, c.d_d32, c.d_r32, c.d_p32, c.d_q32, c.d_partial, si, st,
+                                o.cheb_degree));
         bool fused = false;
-        HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, st, c.d_partial, &fused));
+        HIPCHK(mg_vcycle<float>(c, c.d_r32, z, &si->done, o.cheb_degree, st, c.d_partial, &fused, true));
         HIPCHK(launch_mg_dot_dir(c, FNPF_F32, c.d_r32, z, c.d_p32, c.d_partial, si, 0, st, fused));
       } else {
         HIPCHK((launch_pcg_update<float, float>(c.d_d32, c.d_r32, c.d_p32, c.d_q32, dinv, c.n_v, c.d_partial, si,

@@ -302,9 +302,12 @@ template <typename T>
 fnpf_status mg_refresh(Ctx &c, hipStream_t s);
 template <typename T>
 hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth, hipStream_t s,
-                     double *dot_partial = nullptr, bool *dot_done = nullptr);
+                     double *dot_partial = nullptr, bool *dot_done = nullptr, bool pre_scaled = false);
+// x += alpha p, r -= alpha q with the partials of r.r; with the degree-2 V-cycle (smooth == 2 and a
+// hierarchy) it also writes the cycle's first smoothing step, and the mg_vcycle call on this r that
+// follows must pass pre_scaled = true.
 hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void *p, const void *q, double *partial,
-                            PcgScalars *sc, hipStream_t s);
+                            PcgScalars *sc, hipStream_t s, int smooth);
 hipError_t launch_mg_dot_dir(Ctx &c, fnpf_dtype dt, const void *r, const void *z, void *p, double *partial,
                              PcgScalars *sc, int first, hipStream_t s, bool have_partials = false);
 Ctx &ctx_of(fnpf_ctx h);

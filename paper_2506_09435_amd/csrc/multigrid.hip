@@ -407,8 +407,9 @@ __global__ __launch_bounds__(kVecThreads) void k_cheb_step(T *r, const T *q, T *
 }
 
 // Two-step smoothing written out (the default degree): with d1 = c0 D^-1 r0 and
-// d2 = c1 d1 + c2 D^-1 (r0 - A d1), x2 = x0 + (1 + c1) d1 + c2 D^-1 (r0 - A d1); only the
-// vectors each formula needs are read, and no residual or step vector survives it.
+// d2 = c1 d1 + c2 D^-1 (r0 - A d1), x2 = x0 + a1 d1 + a2 D^-1 (r0 - A d1) (a1 = 1 + c1, a2 = c2)
+// = x0 + D^-1 ((a1 c0 + a2) r0 - a2 A d1): d1 is needed only as the input of its product, and
+// no residual or step vector survives it.
 //   y = c dinv b
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_scale(T *y, const T *b, const T *dinv, const double *cf, int64_t n,
@@ -418,13 +419,13 @@ __global__ __launch_bounds__(kVecThreads) void k_scale(T *y, const T *b, const T
   GRID_STRIDE(i, n) y[i] = c * dinv[i] * b[i];
 }
 
-//   from zero: x = a1 y + a2 dinv (b - q), y = d1, q = A d1
+//   from zero: x = dinv ((a1 c0 + a2) b - a2 q), q = A d1
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_pre2(T *x, const T *y, const T *b, const T *q, const T *dinv,
+__global__ __launch_bounds__(kVecThreads) void k_pre2(T *x, const T *b, const T *q, const T *dinv,
                                                       const double *cf, int64_t n, const int32_t *skip) {
   if (skip != nullptr && *skip) return;
-  const T a1 = (T)cf[1], a2 = (T)cf[2];
-  GRID_STRIDE(i, n) x[i] = a1 * y[i] + a2 * dinv[i] * (b[i] - q[i]);
+  const T e = (T)(cf[1] * cf[0] + cf[2]), a2 = (T)cf[2];
+  GRID_STRIDE(i, n) x[i] = dinv[i] * (e * b[i] - a2 * q[i]);
 }
 
 //   from x: d1 = c dinv (b - q1), q1 = A x
@@ -436,35 +437,39 @@ __global__ __launch_bounds__(kVecThreads) void k_post2a(T *d, const T *b, const 
   GRID_STRIDE(i, n) d[i] = c * dinv[i] * (b[i] - q1[i]);
 }
 
-//   x += a1 d1 + a2 dinv (b - q1 - q2), q2 = A d1
+//   x += dinv ((a1 c0 + a2) (b - q1) - a2 q2), q1 = A x, q2 = A d1
 // DOT: also the block partials of b.x (the CG's r.z when b is the residual and x the V-cycle's
 // result), in the order k_dot takes them, so the sum is the same bit for bit
 template <typename T, bool DOT>
-__global__ __launch_bounds__(kVecThreads) void k_post2b(T *x, const T *d, const T *b, const T *q1, const T *q2,
+__global__ __launch_bounds__(kVecThreads) void k_post2b(T *x, const T *b, const T *q1, const T *q2,
                                                         const T *dinv, const double *cf, int64_t n,
                                                         const int32_t *skip, double *partial) {
   if (skip != nullptr && *skip) return;
-  const T a1 = (T)cf[1], a2 = (T)cf[2];
+  const T e = (T)(cf[1] * cf[0] + cf[2]), a2 = (T)cf[2];
   double v[1] = {0.0};
   GRID_STRIDE(i, n) {
-    const T xi = x[i] + (a1 * d[i] + a2 * dinv[i] * (b[i] - q1[i] - q2[i]));
+    const T xi = x[i] + dinv[i] * (e * (b[i] - q1[i]) - a2 * q2[i]);
     x[i] = xi;
     if constexpr (DOT) v[0] += (double)b[i] * (double)xi;
   }
   if constexpr (DOT) block_partials<1>(v, partial);
 }
 
-// PCG with a general preconditioner: x += alpha p, r -= alpha q; partial r.r
-template <typename T>
+// PCG with a general preconditioner: x += alpha p, r -= alpha q; partial r.r.  SCALE: also the
+// first step of the degree-2 V-cycle that follows on the new residual, d = c0 dinv r.
+template <typename T, bool SCALE>
 __global__ __launch_bounds__(kVecThreads) void k_mg_update(T *x, T *r, const T *p, const T *q, int64_t n,
-                                                           double *partial, const PcgScalars *sc) {
+                                                           double *partial, const PcgScalars *sc, T *d,
+                                                           const T *dinv, const double *cf) {
   if (sc->done) return;
   const T a = (T)sc->alpha;
+  const T c0 = SCALE ? (T)cf[0] : T(0);
   double v[1] = {0.0};
   GRID_STRIDE(i, n) {
     x[i] += a * p[i];
     const T ri = r[i] - a * q[i];
     r[i] = ri;
+    if constexpr (SCALE) d[i] = c0 * dinv[i] * ri;
     v[0] += (double)ri * (double)ri;
   }
   block_partials<1>(v, partial);
@@ -783,9 +788,10 @@ hipError_t smooth(Ctx &L, const T *b, T *x, T *r, T *d, T *q, const double *cf, 
 }
 
 // V-cycle on level l (0 = this context) for the right-hand side b, result in x.
+// pre_scaled (level 0, degree 2): d = c0 dinv b is already in place (k_mg_update<T, true>).
 template <typename T>
 hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, hipStream_t s,
-                  double *dot_partial = nullptr, bool *dot_done = nullptr) {
+                  double *dot_partial = nullptr, bool *dot_done = nullptr, bool pre_scaled = false) {
   Ctx &L = l == 0 ? c : *c.mg[l - 1].c;
   T *r, *d, *q;
   if (l == 0) {
@@ -806,9 +812,9 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
   const T *dinv = Prec<T>::dinv(L);
   hipError_t e = hipSuccess;
   if (m == 2) {
-    k_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, dinv, cf, n, skip);
+    if (!(l == 0 && pre_scaled)) k_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
-    k_pre2<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, q, dinv, cf, n, skip);
+    k_pre2<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, b, q, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, x, q, true, nullptr, skip, s)) != hipSuccess) return e;
     if ((e = restrict_to<T>(L, *C.c, b, q, bc, skip, s)) != hipSuccess) return e;   // P^T (b - A x)
     if ((e = vcycle<T>(c, l + 1, bc, xc, skip, m, s)) != hipSuccess) return e;
@@ -817,10 +823,10 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
     k_post2a<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, r, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
     if (dot_partial != nullptr) {
-      k_post2b<T, true><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, r, q, dinv, cf, n, skip, dot_partial);
+      k_post2b<T, true><<<kVecBlocks, kVecThreads, 0, s>>>(x, b, r, q, dinv, cf, n, skip, dot_partial);
       if (dot_done) *dot_done = true;
     } else {
-      k_post2b<T, false><<<kVecBlocks, kVecThreads, 0, s>>>(x, d, b, r, q, dinv, cf, n, skip, nullptr);
+      k_post2b<T, false><<<kVecBlocks, kVecThreads, 0, s>>>(x, b, r, q, dinv, cf, n, skip, nullptr);
     }
     return hipGetLastError();
   }
@@ -1110,23 +1116,40 @@ template fnpf_status mg_refresh<float>(Ctx &, hipStream_t);
 
 template <typename T>
 hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth_deg, hipStream_t s,
-                     double *dot_partial, bool *dot_done) {
+                     double *dot_partial, bool *dot_done, bool pre_scaled) {
   if (dot_done) *dot_done = false;
-  return vcycle<T>(c, 0, r, z, skip, smooth_deg, s, dot_partial, dot_done);
+  return vcycle<T>(c, 0, r, z, skip, smooth_deg, s, dot_partial, dot_done, pre_scaled && smooth_deg == 2 &&
+                                                                               !c.mg.empty());
 }
 template hipError_t mg_vcycle<double>(Ctx &, const double *, double *, const int32_t *, int, hipStream_t, double *,
-                                      bool *);
+                                      bool *, bool);
 template hipError_t mg_vcycle<float>(Ctx &, const float *, float *, const int32_t *, int, hipStream_t, double *,
-                                     bool *);
+                                     bool *, bool);
+
+static bool mg_prescale(const Ctx &c, int smooth_deg) { return smooth_deg == 2 && !c.mg.empty(); }
 
 hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void *p, const void *q, double *partial,
-                            PcgScalars *sc, hipStream_t s) {
-  if (dt == FNPF_F64)
-    k_mg_update<double><<<kVecBlocks, kVecThreads, 0, s>>>((double *)x, (double *)r, (const double *)p,
-                                                           (const double *)q, c.n_v, partial, sc);
-  else
-    k_mg_update<float><<<kVecBlocks, kVecThreads, 0, s>>>((float *)x, (float *)r, (const float *)p,
-                                                          (const float *)q, c.n_v, partial, sc);
+                            PcgScalars *sc, hipStream_t s, int smooth_deg) {
+  const bool pre = mg_prescale(c, smooth_deg);
+  if (dt == FNPF_F64) {
+    if (pre)
+      k_mg_update<double, true><<<kVecBlocks, kVecThreads, 0, s>>>(
+          (double *)x, (double *)r, (const double *)p, (const double *)q, c.n_v, partial, sc,
+          Prec<double>::fv(c)[2], Prec<double>::dinv(c), coef_table<double>(c, 0));
+    else
+      k_mg_update<double, false><<<kVecBlocks, kVecThreads, 0, s>>>((double *)x, (double *)r, (const double *)p,
+                                                                    (const double *)q, c.n_v, partial, sc, nullptr,
+                                                                    nullptr, nullptr);
+  } else {
+    if (pre)
+      k_mg_update<float, true><<<kVecBlocks, kVecThreads, 0, s>>>(
+          (float *)x, (float *)r, (const float *)p, (const float *)q, c.n_v, partial, sc, Prec<float>::fv(c)[2],
+          Prec<float>::dinv(c), coef_table<float>(c, 0));
+    else
+      k_mg_update<float, false><<<kVecBlocks, kVecThreads, 0, s>>>((float *)x, (float *)r, (const float *)p,
+                                                                   (const float *)q, c.n_v, partial, sc, nullptr,
+                                                                   nullptr, nullptr);
+  }
   k_mg_fin_rr<<<1, kVecThreads, 0, s>>>(partial, kVecBlocks, sc);
   return hipGetLastError();
 }

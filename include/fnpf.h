@@ -290,6 +290,15 @@ fnpf_status fnpf_set_surface_quadrature(fnpf_ctx ctx, int32_t nq);
 fnpf_status fnpf_surface_quadrature_info(fnpf_ctx ctx, int32_t *nq, int32_t *iters, double *lam_lo,
                                          double *lam_hi);
 
+/* p-multigrid diagnostics (precond 2): *levels = number of levels (this one
+ * and its coarse levels; 0 before the first multigrid solve builds them) and,
+ * for the first min(levels, cap) levels from the finest, the current estimate
+ * of the largest eigenvalue of D^-1 A on the unknowns that sets the Chebyshev
+ * intervals (the value before the 1.1 safety factor; 0 where that precision
+ * has not been refreshed yet).  lam64, lam32: host arrays of cap entries, or
+ * NULL.  Errors: ARG for cap < 0. */
+fnpf_status fnpf_multigrid_info(fnpf_ctx ctx, int32_t *levels, double *lam64, double *lam32, int32_t cap);
+
 /* Modal filter of surface fields (Sec. 3.2, modal filtering; the paper's
  * triangles become tensor-product quads/intervals here).  Per surface
  * element, nodal values -> modal coefficients in the orthonormal Legendre

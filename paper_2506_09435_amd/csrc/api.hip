@@ -878,6 +878,19 @@ fnpf_status fnpf_surface_quadrature_info(fnpf_ctx ctx, int32_t *nq, int32_t *ite
   return FNPF_OK;
 }
 
+fnpf_status fnpf_multigrid_info(fnpf_ctx ctx, int32_t *levels, double *lam64, double *lam32, int32_t cap) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (cap < 0) return fail(&c, FNPF_ERR_ARG, "cap must be >= 0");
+  const int nl = c.mg_built ? (int)c.mg.size() + 1 : 0;
+  if (levels) *levels = nl;
+  for (int l = 0; l < nl && l < cap; ++l) {
+    if (lam64) lam64[l] = l == 0 ? c.lam64 : c.mg[l - 1].lam64;
+    if (lam32) lam32[l] = l == 0 ? c.lam32 : c.mg[l - 1].lam32;
+  }
+  return FNPF_OK;
+}
+
 fnpf_status fnpf_set_modal_filter(fnpf_ctx ctx, int32_t cutoff, double alpha, int32_t order) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;

@@ -76,6 +76,8 @@ SIGNATURES = {
     "fnpf_set_surface_quadrature": (C.c_int, [C.c_void_p, C.c_int32]),
     "fnpf_surface_quadrature_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                                C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "fnpf_multigrid_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.c_int32]),
     "fnpf_set_modal_filter": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_int32]),
     "fnpf_modal_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_modal_filter_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -290,6 +292,13 @@ class Context:
         self._check(lib().fnpf_surface_quadrature_info(self._h, C.byref(nq), C.byref(it), C.byref(lo), C.byref(hi)),
                     "fnpf_surface_quadrature_info")
         return dict(nq=nq.value, iters=it.value, lam_lo=lo.value, lam_hi=hi.value)
+
+    def multigrid_info(self, cap=8):
+        lv = C.c_int32()
+        l64, l32 = (C.c_double * cap)(), (C.c_double * cap)()
+        self._check(lib().fnpf_multigrid_info(self._h, C.byref(lv), l64, l32, int(cap)), "fnpf_multigrid_info")
+        n = min(lv.value, cap)
+        return dict(levels=lv.value, lam64=list(l64)[:n], lam32=list(l32)[:n])
 
     def set_modal_filter(self, cutoff, alpha=0.0, order=1):
         """Modal filter (cutoff < 0 removes it); rk4_step filters eta and phi_s while it is set."""

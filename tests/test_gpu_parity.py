@@ -445,6 +445,37 @@ def test_solve_preconditioners(name, precond):
     assert rel(host(phim), phio) < 1e-8
 
 
+@pytest.mark.parametrize("name", ["box_periodic", "box_walls_p6", "cylinder"])
+def test_multigrid_eigenvalue_estimate(name):
+    """The estimate of the largest eigenvalue of D^-1 A that sets the Chebyshev smoothing
+    intervals: on the fine level it lies within 3% below the exact value of the oracle's
+    assembled matrix (Lanczos on first use, power iterations from its Ritz vector after a
+    geometry update), in both precisions; every level has a positive estimate.  The smoother
+    stops being a contraction for eigenvalues above (1 + 1/24) x 1.1 x the estimate, so an
+    estimate 1.146x short makes the V-cycle indefinite."""
+    pr = Pair(_case(name), fp32=True)
+    I = sv.interior_mask(pr.m)
+
+    def lam_true(eta):
+        Go, _, _ = geo.factors(pr.m, eta, pr.h, pr.xh)
+        A = op.assemble_dense(pr.m, Go)[np.ix_(I, I)]
+        s = 1.0 / np.sqrt(np.diag(A))
+        return np.linalg.eigvalsh(A * s[:, None] * s[None, :]).max()
+
+    for k, eta in enumerate((pr.eta, 1.5 * pr.eta)):
+        pr.ctx.geom(dev(eta), pr.d_h)
+        for precision in (0, 1):
+            o = fnpf.default_opts(precision=precision, rtol=1e-10, inner_rtol=1e-3, precond=2)
+            _, info = pr.ctx.solve(pr.d_phis, opts=o)
+            assert info["status"] == "OK"
+        mi = pr.ctx.multigrid_info()
+        lt = lam_true(eta)
+        assert mi["levels"] == (3 if pr.m.p == 6 else 2)
+        assert 0.97 * lt <= mi["lam64"][0] <= lt * (1 + 1e-9), (k, mi, lt)
+        assert 0.97 * lt <= mi["lam32"][0] <= lt * (1 + 1e-5), (k, mi, lt)
+        assert all(x > 0 for x in mi["lam64"] + mi["lam32"])
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_rk4_step_multigrid(precision):
     """ERK4 steps with the p-multigrid preconditioner (geometry refreshed every stage)."""

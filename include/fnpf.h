@@ -124,11 +124,13 @@ typedef struct {
  *   do not depend on it).  inner_rtol: relative reduction of each inner FP32
  *   solve, which also stops as soon as its residual is below half the outer
  *   tolerance; max_outer bounds the defect-correction sweeps.
- *   extrapolate (fnpf_rk4_step only): 1 starts stage s of a step from
- *   2 phi_s(n-1) - phi_s(n-2), the same stage of the two previous steps,
- *   once the context has seen two consecutive steps with the same dt; 0
- *   always starts from the previous stage's potential.  Only the initial
- *   guess changes; the converged solution does not.                         */
+ *   extrapolate (fnpf_rk4_step only): the initial guess of stage s of a
+ *   step is extrapolated in time from the same stage of the previous steps
+ *   taken with the same dt: 1 linearly, 2 phi_s(n-1) - phi_s(n-2); 2
+ *   quadratically, 3 phi_s(n-1) - 3 phi_s(n-2) + phi_s(n-3), or linearly
+ *   while only two such steps exist; 0 always starts from the previous
+ *   stage's potential.  Only the initial guess changes; the converged
+ *   solution does not (it meets the same tolerance).                         */
 typedef struct {
   int32_t precision;
   int32_t precond;
@@ -153,7 +155,7 @@ typedef struct {
 } fnpf_solve_info;
 
 /* Defaults: FP64, p-multigrid (precond 2), rtol 1e-8, atol 0, max_iter 20000,
- * check_every 8, inner_rtol 1e-4, max_outer 30, extrapolate 1, cheb_degree 2, use_graph 1. */
+ * check_every 8, inner_rtol 1e-4, max_outer 30, extrapolate 2, cheb_degree 2, use_graph 1. */
 void fnpf_default_opts(fnpf_solve_opts *opts);
 
 /* Create a context on the current HIP device: validates and copies the mesh,

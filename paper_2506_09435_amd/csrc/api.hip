@@ -130,7 +130,7 @@ void free_all(Ctx &c) {
   if (c.h_sc) (void)hipHostFree(c.h_sc);
   c.h_sc = nullptr;
   for (int s = 0; s < 4; ++s)
-    for (int k = 0; k < 2; ++k) dfree(c.d_hist[s][k]);
+    for (int k = 0; k < 3; ++k) dfree(c.d_hist[s][k]);
   dfree(c.d_lam);
   dfree(c.d_phibar);
   dfree(c.d_kbe);
@@ -201,7 +201,7 @@ fnpf_status ensure_adjoint(Ctx &c, hipStream_t s) {
 fnpf_status ensure_history(Ctx &c) {
   if (c.d_hist[0][0]) return FNPF_OK;
   for (int s = 0; s < 4; ++s)
-    for (int k = 0; k < 2; ++k) HIPCHK(dalloc(&c.d_hist[s][k], c.n_v));
+    for (int k = 0; k < 3; ++k) HIPCHK(dalloc(&c.d_hist[s][k], c.n_v));
   return FNPF_OK;
 }
 
@@ -453,7 +453,7 @@ fnpf_status validate_opts(Ctx &c, const fnpf_solve_opts &o) {
   if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || (o.rtol == 0.0 && o.atol == 0.0))
     return fail(&c, FNPF_ERR_ARG, "opts.rtol/atol must be >= 0 and not both 0");
   if (o.max_iter < 1 || o.check_every < 1) return fail(&c, FNPF_ERR_ARG, "opts.max_iter and check_every must be >= 1");
-  if (o.extrapolate != 0 && o.extrapolate != 1) return fail(&c, FNPF_ERR_ARG, "opts.extrapolate must be 0 or 1");
+  if (o.extrapolate < 0 || o.extrapolate > 2) return fail(&c, FNPF_ERR_ARG, "opts.extrapolate must be 0, 1 or 2");
   if (o.use_graph != 0 && o.use_graph != 1) return fail(&c, FNPF_ERR_ARG, "opts.use_graph must be 0 or 1");
   if (o.precision == 1 && (!(o.inner_rtol > 0.0) || !(o.inner_rtol < 1.0) || o.max_outer < 1))
     return fail(&c, FNPF_ERR_ARG, "opts.inner_rtol must be in (0,1) and max_outer >= 1 for the mixed path");
@@ -546,7 +546,7 @@ void fnpf_default_opts(fnpf_solve_opts *o) {
   o->check_every = 8;
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
-  o->extrapolate = 1;
+  o->extrapolate = 2;
   o->cheb_degree = 2;
   o->use_graph = 1;
 }
@@ -997,19 +997,23 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
       st = geom_impl(c, ein, h, s);
       if (st != FNPF_OK) return st;
     }
-    const bool extrap = o.extrapolate && c.hist_count >= 2 && c.hist_dt == dt;
-    if (extrap) {
-      // linear extrapolation in time from the same stage of the two previous steps
-      const int i1 = c.hist_head, i2 = 1 - c.hist_head;
-      HIPCHK(launch_lincomb(c.d_phi, 2.0, c.d_hist[stg][i1], -1.0, c.d_hist[stg][i2], c.n_v, s));
+    if (o.extrapolate && c.hist_count >= 2 && c.hist_dt == dt) {
+      // polynomial extrapolation in time from the same stage of the previous steps (newest i1)
+      const int i1 = c.hist_head, i2 = (c.hist_head + 2) % 3, i3 = (c.hist_head + 1) % 3;
+      if (o.extrapolate == 2 && c.hist_count >= 3) {
+        HIPCHK(launch_lincomb(c.d_phi, 3.0, c.d_hist[stg][i1], -3.0, c.d_hist[stg][i2], c.n_v, s));
+        HIPCHK(launch_lincomb(c.d_phi, 1.0, c.d_phi, 1.0, c.d_hist[stg][i3], c.n_v, s));
+      } else {
+        HIPCHK(launch_lincomb(c.d_phi, 2.0, c.d_hist[stg][i1], -1.0, c.d_hist[stg][i2], c.n_v, s));
+      }
     }
     st = solve_impl(c, pin, nullptr, c.d_phi, o, info ? info + stg : nullptr, s);
     if (st != FNPF_OK) return st;
     if (o.extrapolate) {
       st = ensure_history(c);
       if (st != FNPF_OK) return st;
-      HIPCHK(hipMemcpyAsync(c.d_hist[stg][1 - c.hist_head], c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice,
-                            s));
+      HIPCHK(hipMemcpyAsync(c.d_hist[stg][(c.hist_head + 1) % 3], c.d_phi, c.n_v * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));   // over the oldest
     }
     if (tape) HIPCHK(hipMemcpyAsync(tape + stg * rec, c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_wsurf(c, c.d_phi, c.d_w, s));
@@ -1055,8 +1059,8 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
   }
   if (o.extrapolate) {
     // the slot written this step becomes the newest
-    c.hist_head = 1 - c.hist_head;
-    c.hist_count = (c.hist_dt == dt) ? std::min(c.hist_count + 1, 2) : 1;
+    c.hist_head = (c.hist_head + 1) % 3;
+    c.hist_count = (c.hist_dt == dt) ? std::min(c.hist_count + 1, 3) : 1;
     c.hist_dt = dt;
   } else {
     c.hist_count = 0;  // a step taken without recording breaks the sequence

@@ -224,7 +224,7 @@ struct Ctx {
   PcgScalars *d_sc = nullptr;             // [2]: outer/plain, inner
   PcgScalars *h_sc = nullptr;             // pinned host mirror
   // same-stage solutions of the two previous steps (initial-guess extrapolation)
-  double *d_hist[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  double *d_hist[4][3] = {};              // per stage, the potentials of the last three steps (a ring)
   int hist_head = 0;                      // slot of the newest step
   int hist_count = 0;
   double hist_dt = 0.0;

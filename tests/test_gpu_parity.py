@@ -495,6 +495,31 @@ def test_rk4_step_multigrid(precision):
     assert all(i["rel_res"] <= opts.rtol for i in infos)
 
 
+def test_warm_start_extrapolation_c2():
+    """C2 full size, 5 ERK4 steps: the initial guesses extrapolated quadratically, linearly or not
+    at all from the previous steps reach the same states to the solve tolerance, and once its
+    history exists the quadratic one needs fewer CG iterations than either.  (The previous stage's
+    potential, used without extrapolation, is already a second-order guess for the first and third
+    stages, so the linear extrapolation need not beat it.)"""
+    wl = configs.c2()
+    pr = Pair(wl)
+    out, iters = {}, {}
+    for ex in (0, 1, 2):
+        e, p = pr.d_eta.clone(), pr.d_phis.clone()
+        pr.ctx.set_warm_start(None)
+        opts = fnpf.default_opts(rtol=1e-10, extrapolate=ex)
+        its = []
+        for n in range(5):
+            infos = pr.ctx.rk4_step(e, p, pr.d_h, n * wl.dt, wl.dt, opts=opts)
+            its.append(sum(i["iters"] for i in infos))
+        out[ex], iters[ex] = (host(e), host(p)), its
+    for ex in (1, 2):
+        assert rel(out[ex][0], out[0][0]) < 1e-8 and rel(out[ex][1], out[0][1]) < 1e-8
+    # histories: linear from the third step on, quadratic from the fourth
+    assert iters[1][:2] == iters[0][:2] and iters[2][:3] == iters[1][:3], iters
+    assert all(iters[2][n] < min(iters[1][n], iters[0][n]) for n in (3, 4)), iters
+
+
 def test_multigrid_repeatable_and_c2():
     """C2 full size: the multigrid solve is bitwise repeatable and satisfies the oracle's residual."""
     wl = configs.c2()

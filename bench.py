@@ -167,7 +167,7 @@ def cpu_baseline(wl, target_s=10.0):
                        f"{reps} reps in {el:.1f} s; DoF counted as columns x n_v/n_eh")
 
 
-def adjoint_leg(nsteps, rtol, fd_dirs):
+def adjoint_leg(nsteps, rtol, fd_dirs, precond=1):
     """C4 bar: gauge misfit over nsteps ERK4 steps, gradient w.r.t. 64 bathymetry controls and eta0.
 
     Returns the forward and backward (checkpoint recomputation + adjoint) times, their ratio
@@ -196,9 +196,10 @@ def adjoint_leg(nsteps, rtol, fd_dirs):
     # rest), so that the gauges see the bathymetry within the differentiated steps
     eta_in = torch.tensor(wl.relax_wave.eta(x, y, 0.0), device="cuda")
     phi_in = torch.tensor(wl.relax_wave.phi(x, y, 0.0), device="cuda")
-    # Jacobi: on this 0.55 M-DoF mesh with 9.5:1 elements in plan the multigrid cycle costs more
-    # than its iteration savings (75 vs 83 ms per FP64 step)
-    o = fnpf.default_opts(rtol=rtol, precond=1, check_every=25)
+    # Jacobi by default: on this 0.55 M-DoF mesh with 9.5:1 elements in plan the multigrid cycle
+    # costs more than its iteration savings in the rollout (200 steps: forward 11.8 s with the
+    # multigrid preconditioner against 9.2 s, backward 29.9 s against 21.6 s)
+    o = fnpf.default_opts(rtol=rtol, precond=precond, check_every=25 if precond == 1 else 5)
     with torch.no_grad():
         obs = rollout(fctx, eta_in, phi_in, B @ c_true, 0.0, wl.dt, nsteps, opts=o) @ P.T
 
@@ -224,7 +225,8 @@ def adjoint_leg(nsteps, rtol, fd_dirs):
     t_bwd = time.perf_counter() - t0
     out = dict(workload=f"C4 bar 64x16x4 p=5 (n_v={m.n_v}), {nsteps} steps, 8 gauges, 64 controls + eta0, "
                         f"FP64 forward and adjoint",
-               rtol=rtol, preconditioner="Jacobi", t_forward_s=t_fwd, t_backward_s=t_bwd, ratio=t_bwd / t_fwd,
+               rtol=rtol, preconditioner={1: "Jacobi", 2: "p-multigrid"}.get(precond, "none"),
+               t_forward_s=t_fwd, t_backward_s=t_bwd, ratio=t_bwd / t_fwd,
                grad_norm_c=float(c.grad.norm()), loss=float(J.detach()))
     if fd_dirs > 0:
         o12 = fnpf.default_opts(rtol=1e-12, check_every=25)

@@ -38,8 +38,8 @@ METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/for
 # plain-copy calibration), valid only for the kernel source they were taken from.
 MEASURED_TRAFFIC = {
     "kernel_source_sha256": "025f7e463dba33f651ebb0be29d05712aaab68dca9cb077da39eabf3a6546268",
-    "fetch_bytes_per_apply": 860528186,
-    "write_bytes_per_apply": 587484077,
+    "fetch_bytes_per_apply": 861199713,
+    "write_bytes_per_apply": 587709862,
 }
 
 
@@ -197,8 +197,8 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1):
     eta_in = torch.tensor(wl.relax_wave.eta(x, y, 0.0), device="cuda")
     phi_in = torch.tensor(wl.relax_wave.phi(x, y, 0.0), device="cuda")
     # Jacobi by default: on this 0.55 M-DoF mesh with 9.5:1 elements in plan the multigrid cycle
-    # costs more than its iteration savings in the rollout (200 steps: forward 11.8 s with the
-    # multigrid preconditioner against 9.2 s, backward 29.9 s against 21.6 s)
+    # costs more than its iteration savings in the rollout (200 steps: forward 9.1 s with the
+    # multigrid preconditioner against 5.7 s, backward 25.5 s against 14.6 s)
     o = fnpf.default_opts(rtol=rtol, precond=precond, check_every=25 if precond == 1 else 5)
     with torch.no_grad():
         obs = rollout(fctx, eta_in, phi_in, B @ c_true, 0.0, wl.dt, nsteps, opts=o) @ P.T
@@ -297,10 +297,10 @@ def apply_sweep(reps, variant=None):
     return rows
 
 
-def _time_steps(s, wl, opts, nsteps):
+def _time_steps(s, wl, opts, nsteps, warmup):
     import torch
     s.ctx.set_warm_start(None)
-    e, p, t, _ = run_steps(s, wl, opts, 1)
+    e, p, t, _ = run_steps(s, wl, opts, warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, _, _, iters = run_steps(s, wl, opts, nsteps, t0=t, eta=e, phi=p)
@@ -325,14 +325,14 @@ def _time_calls(fn, reps):
     return float(np.median(times))
 
 
-def extensions_leg(s, wl, opts, nsteps):
+def extensions_leg(s, wl, opts, nsteps, warmup):
     """Linear potential flow, the modal filter and the consistent free-surface form on the same
     workload: seconds per mixed-precision ERK4 step, and the filter / consistent RHS alone."""
     import torch
     ctx, m = s.ctx, wl.mesh
     out = {}
     ctx.set_linear(True)
-    out["lpf_s_per_step"], out["lpf_iters"] = _time_steps(s, wl, opts, nsteps)
+    out["lpf_s_per_step"], out["lpf_iters"] = _time_steps(s, wl, opts, nsteps, warmup)
     ctx.set_linear(False)
     ctx.set_modal_filter(m.p - 2, 4.0, 2)
     f = s.eta0.clone()
@@ -341,7 +341,7 @@ def extensions_leg(s, wl, opts, nsteps):
     fbytes = 3 * 8 * m.n_s + 5 * m.n_eh * m.nh
     out["filter_ms"] = t_f * 1e3
     out["filter_gbs"] = fbytes / t_f / 1e9
-    out["filter_s_per_step"], _ = _time_steps(s, wl, opts, nsteps)
+    out["filter_s_per_step"], _ = _time_steps(s, wl, opts, nsteps, warmup)
     ctx.set_modal_filter(-1)
     nq = m.p + 3
     ctx.set_surface_quadrature(nq)
@@ -349,7 +349,7 @@ def extensions_leg(s, wl, opts, nsteps):
     out["consistent_nq"] = nq
     out["consistent_chebyshev_iters"] = ctx.surface_quadrature_info()["iters"]
     out["consistent_rhs_ms"] = _time_calls(lambda: ctx.rhs(s.eta0, s.phi0, w), 5) * 1e3
-    out["consistent_s_per_step"], _ = _time_steps(s, wl, opts, nsteps)
+    out["consistent_s_per_step"], _ = _time_steps(s, wl, opts, nsteps, warmup)
     ctx.set_surface_quadrature(0)
     return out
 
@@ -358,7 +358,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed ERK4 steps before each timed leg; the initial-guess extrapolation "
+                         "(default degree 4) has its full five-step history from the sixth step on")
     ap.add_argument("--workload", default="C5")
     ap.add_argument("--apply-reps", type=int, default=100)
     ap.add_argument("--rtol", type=float, default=1e-8)
@@ -467,7 +469,7 @@ def main():
 
     ext = None
     if not args.no_extensions:
-        ext = extensions_leg(s, wl, o_mixed, args.steps)
+        ext = extensions_leg(s, wl, o_mixed, args.steps, args.warmup)
         print(f"[bench] extensions {ext}", file=sys.stderr, flush=True)
 
     adj = None

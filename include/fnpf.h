@@ -124,13 +124,15 @@ typedef struct {
  *   do not depend on it).  inner_rtol: relative reduction of each inner FP32
  *   solve, which also stops as soon as its residual is below half the outer
  *   tolerance; max_outer bounds the defect-correction sweeps.
- *   extrapolate (fnpf_rk4_step only): the initial guess of stage s of a
- *   step is extrapolated in time from the same stage of the previous steps
- *   taken with the same dt: 1 linearly, 2 phi_s(n-1) - phi_s(n-2); 2
- *   quadratically, 3 phi_s(n-1) - 3 phi_s(n-2) + phi_s(n-3), or linearly
- *   while only two such steps exist; 0 always starts from the previous
- *   stage's potential.  Only the initial guess changes; the converged
- *   solution does not (it meets the same tolerance).                         */
+ *   extrapolate (fnpf_rk4_step and fnpf_rk4_step_vjp): k = 1..4
+ *   extrapolates the initial guess of stage s of a step in time from the
+ *   same stage of the previous k + 1 steps taken with the same dt, with the
+ *   polynomial of degree k through them: phi(n) = sum_{j=1}^{k+1}
+ *   (-1)^(j+1) binom(k+1, j) phi(n-j) (k = 1: 2 phi(n-1) - phi(n-2));
+ *   lower degrees while fewer steps exist.  It keeps k + 1 potentials [n_v]
+ *   per stage on the device (a change of k starts a new history).  0 starts
+ *   every stage from the previous stage's potential.  Only the initial
+ *   guess changes; the converged solution meets the same tolerance.         */
 typedef struct {
   int32_t precision;
   int32_t precond;
@@ -155,7 +157,7 @@ typedef struct {
 } fnpf_solve_info;
 
 /* Defaults: FP64, p-multigrid (precond 2), rtol 1e-8, atol 0, max_iter 20000,
- * check_every 8, inner_rtol 1e-4, max_outer 30, extrapolate 2, cheb_degree 2, use_graph 1. */
+ * check_every 8, inner_rtol 1e-4, max_outer 30, extrapolate 4, cheb_degree 2, use_graph 1. */
 void fnpf_default_opts(fnpf_solve_opts *opts);
 
 /* Create a context on the current HIP device: validates and copies the mesh,
@@ -376,7 +378,10 @@ fnpf_status fnpf_geom_vjp(fnpf_ctx ctx, const double *lambda, const double *phi,
  * [n_s] hold the adjoint of the step's output state; on exit, of its input
  * state; h_bar (+=) accumulates the adjoint of the depth.  Runs 4 adjoint
  * solves (opts) and recomputes the stage geometry; info (host, may be NULL)
- * gets one record per stage (index = stage). */
+ * gets one record per stage (index = stage).  t is the time at the start of
+ * the step: calls for t, t - dt, t - 2 dt, ... form a sequence whose adjoint
+ * solutions extrapolate the next call's initial guesses like
+ * opts.extrapolate does for fnpf_rk4_step (a history of its own). */
 fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt, const double *tape,
                               double *eta_bar, double *phis_bar, double *h_bar, const fnpf_solve_opts *opts,
                               fnpf_solve_info *info, void *stream);

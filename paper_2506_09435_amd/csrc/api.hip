@@ -130,7 +130,10 @@ void free_all(Ctx &c) {
   if (c.h_sc) (void)hipHostFree(c.h_sc);
   c.h_sc = nullptr;
   for (int s = 0; s < 4; ++s)
-    for (int k = 0; k < 3; ++k) dfree(c.d_hist[s][k]);
+    for (int k = 0; k < Ctx::kHistMax; ++k) {
+      dfree(c.hist.v[s][k]);
+      dfree(c.ahist.v[s][k]);
+    }
   dfree(c.d_lam);
   dfree(c.d_phibar);
   dfree(c.d_kbe);
@@ -198,11 +201,52 @@ fnpf_status ensure_adjoint(Ctx &c, hipStream_t s) {
   return FNPF_OK;
 }
 
-fnpf_status ensure_history(Ctx &c) {
-  if (c.d_hist[0][0]) return FNPF_OK;
+// A ring of `slots` past solutions per stage; a new length starts an empty history.
+fnpf_status ensure_history(Ctx &c, Ctx::History &H, int slots) {
+  if (slots == H.slots) return FNPF_OK;
   for (int s = 0; s < 4; ++s)
-    for (int k = 0; k < 3; ++k) HIPCHK(dalloc(&c.d_hist[s][k], c.n_v));
+    for (int k = 0; k < Ctx::kHistMax; ++k) {
+      if (k >= slots) dfree(H.v[s][k]);
+      else if (!H.v[s][k]) HIPCHK(dalloc(&H.v[s][k], c.n_v));
+    }
+  H.slots = slots;
+  H.head = 0;
+  H.count = 0;
   return FNPF_OK;
+}
+
+// out = the polynomial extrapolation of stage stg's history to the next step of the sequence:
+// out = sum_{j=1}^{k+1} (-1)^(j+1) binom(k+1, j) v(n-j), k = min(order, steps recorded - 1).
+// Returns false (out untouched) when fewer than two steps are recorded.
+bool history_extrapolate(const Ctx::History &H, int stg, int order, double *out, int64_t n, hipStream_t s,
+                         hipError_t &err) {
+  err = hipSuccess;
+  const int k = std::min(order, H.count - 1);
+  if (k < 1) return false;
+  const int K = H.slots;
+  auto past = [&](int j) { return H.v[stg][(H.head - (j - 1) + K) % K]; };   // j = 1: newest
+  double cj[Ctx::kHistMax + 1];
+  for (int j = 1, b = 1; j <= k + 1; ++j) {
+    b = b * (k + 2 - j) / j;   // binom(k+1, j)
+    cj[j] = (j % 2 ? 1.0 : -1.0) * b;
+  }
+  if ((err = launch_lincomb(out, cj[1], past(1), cj[2], past(2), n, s)) != hipSuccess) return false;
+  for (int j = 3; j <= k + 1; ++j)
+    if ((err = launch_lincomb(out, 1.0, out, cj[j], past(j), n, s)) != hipSuccess) return false;
+  return true;
+}
+
+// stage stg's solution of the current step goes over the oldest slot
+hipError_t history_record(const Ctx::History &H, int stg, const double *x, int64_t n, hipStream_t s) {
+  return hipMemcpyAsync(H.v[stg][(H.head + 1) % H.slots], x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
+// after the step at time t: its slot becomes the newest
+void history_advance(Ctx::History &H, double t, double dt, bool continues) {
+  H.head = (H.head + 1) % H.slots;
+  H.count = continues ? std::min(H.count + 1, H.slots) : 1;
+  H.dt = dt;
+  H.t = t;
 }
 
 fnpf_status ensure_flat(Ctx &c, hipStream_t s) {
@@ -453,7 +497,8 @@ fnpf_status validate_opts(Ctx &c, const fnpf_solve_opts &o) {
   if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || (o.rtol == 0.0 && o.atol == 0.0))
     return fail(&c, FNPF_ERR_ARG, "opts.rtol/atol must be >= 0 and not both 0");
   if (o.max_iter < 1 || o.check_every < 1) return fail(&c, FNPF_ERR_ARG, "opts.max_iter and check_every must be >= 1");
-  if (o.extrapolate < 0 || o.extrapolate > 2) return fail(&c, FNPF_ERR_ARG, "opts.extrapolate must be 0, 1 or 2");
+  if (o.extrapolate < 0 || o.extrapolate >= Ctx::kHistMax)
+    return fail(&c, FNPF_ERR_ARG, "opts.extrapolate must be in 0..4");
   if (o.use_graph != 0 && o.use_graph != 1) return fail(&c, FNPF_ERR_ARG, "opts.use_graph must be 0 or 1");
   if (o.precision == 1 && (!(o.inner_rtol > 0.0) || !(o.inner_rtol < 1.0) || o.max_outer < 1))
     return fail(&c, FNPF_ERR_ARG, "opts.inner_rtol must be in (0,1) and max_outer >= 1 for the mixed path");
@@ -546,7 +591,7 @@ void fnpf_default_opts(fnpf_solve_opts *o) {
   o->check_every = 8;
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
-  o->extrapolate = 2;
+  o->extrapolate = 4;
   o->cheb_degree = 2;
   o->use_graph = 1;
 }
@@ -980,6 +1025,11 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
     if (st != FNPF_OK) return st;
   }
   if (info) std::memset(info, 0, 4 * sizeof(fnpf_solve_info));
+  if (o.extrapolate) {
+    st = ensure_history(c, c.hist, o.extrapolate + 1);
+    if (st != FNPF_OK) return st;
+    if (c.hist.dt != dt) c.hist.count = 0;   // a new step size starts a new sequence
+  }
   const double *ein = eta, *pin = phis;
   const size_t rec = (size_t)c.n_v + 2 * (size_t)c.n_s;
   if (c.linear) {
@@ -997,24 +1047,14 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
       st = geom_impl(c, ein, h, s);
       if (st != FNPF_OK) return st;
     }
-    if (o.extrapolate && c.hist_count >= 2 && c.hist_dt == dt) {
-      // polynomial extrapolation in time from the same stage of the previous steps (newest i1)
-      const int i1 = c.hist_head, i2 = (c.hist_head + 2) % 3, i3 = (c.hist_head + 1) % 3;
-      if (o.extrapolate == 2 && c.hist_count >= 3) {
-        HIPCHK(launch_lincomb(c.d_phi, 3.0, c.d_hist[stg][i1], -3.0, c.d_hist[stg][i2], c.n_v, s));
-        HIPCHK(launch_lincomb(c.d_phi, 1.0, c.d_phi, 1.0, c.d_hist[stg][i3], c.n_v, s));
-      } else {
-        HIPCHK(launch_lincomb(c.d_phi, 2.0, c.d_hist[stg][i1], -1.0, c.d_hist[stg][i2], c.n_v, s));
-      }
+    if (o.extrapolate) {
+      hipError_t e = hipSuccess;
+      history_extrapolate(c.hist, stg, o.extrapolate, c.d_phi, c.n_v, s, e);
+      HIPCHK(e);
     }
     st = solve_impl(c, pin, nullptr, c.d_phi, o, info ? info + stg : nullptr, s);
     if (st != FNPF_OK) return st;
-    if (o.extrapolate) {
-      st = ensure_history(c);
-      if (st != FNPF_OK) return st;
-      HIPCHK(hipMemcpyAsync(c.d_hist[stg][(c.hist_head + 1) % 3], c.d_phi, c.n_v * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));   // over the oldest
-    }
+    if (o.extrapolate) HIPCHK(history_record(c.hist, stg, c.d_phi, c.n_v, s));
     if (tape) HIPCHK(hipMemcpyAsync(tape + stg * rec, c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_wsurf(c, c.d_phi, c.d_w, s));
     RkStageArgs a{};
@@ -1057,14 +1097,10 @@ fnpf_status fnpf_rk4_step(fnpf_ctx ctx, double *eta, double *phis, const double 
       HIPCHK(hipMemcpyAsync(f, c.d_filt_tmp, c.n_s * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
   }
-  if (o.extrapolate) {
-    // the slot written this step becomes the newest
-    c.hist_head = (c.hist_head + 1) % 3;
-    c.hist_count = (c.hist_dt == dt) ? std::min(c.hist_count + 1, 3) : 1;
-    c.hist_dt = dt;
-  } else {
-    c.hist_count = 0;  // a step taken without recording breaks the sequence
-  }
+  if (o.extrapolate)
+    history_advance(c.hist, t, dt, true);
+  else
+    c.hist.count = 0;  // a step taken without recording breaks the sequence
   return FNPF_OK;
 }
 
@@ -1144,6 +1180,17 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
     if (st != FNPF_OK) return st;
   }
   if (info) std::memset(info, 0, 4 * sizeof(fnpf_solve_info));
+  if (o.extrapolate) {
+    // the adjoint solutions of consecutive step VJPs (t, t - dt, ...) form a sequence backwards
+    // in time; their history extrapolates the initial guesses like the forward one
+    st = ensure_history(c, c.ahist, o.extrapolate + 1);
+    if (st != FNPF_OK) return st;
+    const bool next = c.ahist.count > 0 && c.ahist.dt == dt &&
+                      std::fabs(c.ahist.t - dt - t) <= 1e-9 * std::max(dt, std::fabs(t));
+    if (!next) c.ahist.count = 0;
+  } else {
+    c.ahist.count = 0;
+  }
   const size_t rec = (size_t)c.n_v + 2 * (size_t)c.n_s;
   const int64_t ns = c.n_s;
   if (c.filter_cutoff >= 0) {
@@ -1187,8 +1234,14 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
     HIPCHK(stage_rhs_vjp(c, eta_s, pin_s, c.d_w, c.d_kbe, c.d_kbp, c.d_ybe, c.d_ybp, c.d_wbar, s));
     HIPCHK(launch_fill(c.d_phibar, 0.0, c.n_v, s));
     HIPCHK(launch_wsurf_vjp(c, c.d_wbar, c.d_w, c.d_phibar, geo_eta_bar, h_bar, s));
+    if (o.extrapolate) {
+      hipError_t e = hipSuccess;
+      history_extrapolate(c.ahist, stg, o.extrapolate, c.d_lam, c.n_v, s, e);
+      HIPCHK(e);
+    }
     st = solve_impl(c, c.d_zero_s, c.d_phibar, c.d_lam, o, info ? info + stg : nullptr, s);
     if (st != FNPF_OK) return st;
+    if (o.extrapolate) HIPCHK(history_record(c.ahist, stg, c.d_lam, c.n_v, s));
     HIPCHK(launch_apply(c, FNPF_F64, c.d_lam, c.d_q, false, nullptr, nullptr, s));
     HIPCHK(launch_surface_adj(c.d_ybp, c.d_phibar, c.d_q, c.n_v, ns, s));
     HIPCHK(launch_geom_vjp(c, c.d_lam, phi_s, geo_eta_bar, h_bar, s));
@@ -1197,14 +1250,14 @@ fnpf_status fnpf_rk4_step_vjp(fnpf_ctx ctx, const double *h, double t, double dt
   }
   HIPCHK(hipMemcpyAsync(eta_bar, c.d_acce, ns * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(phis_bar, c.d_accp, ns * sizeof(double), hipMemcpyDeviceToDevice, s));
-  (void)t;
+  if (o.extrapolate) history_advance(c.ahist, t, dt, c.ahist.count > 0);
   return FNPF_OK;
 }
 
 fnpf_status fnpf_get_warm_start(fnpf_ctx ctx, double *phi, void *stream) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
-  c.hist_count = 0;
+  c.hist.count = 0;
   if (!phi) return fail(&c, FNPF_ERR_ARG, "phi is NULL");
   HIPCHK(hipMemcpyAsync(phi, c.d_phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return FNPF_OK;
@@ -1213,7 +1266,7 @@ fnpf_status fnpf_get_warm_start(fnpf_ctx ctx, double *phi, void *stream) {
 fnpf_status fnpf_set_warm_start(fnpf_ctx ctx, const double *phi, void *stream) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
-  c.hist_count = 0;
+  c.hist.count = 0;
   if (phi)
     HIPCHK(hipMemcpyAsync(c.d_phi, phi, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   else

@@ -223,11 +223,17 @@ struct Ctx {
   int n_partial = 0;
   PcgScalars *d_sc = nullptr;             // [2]: outer/plain, inner
   PcgScalars *h_sc = nullptr;             // pinned host mirror
-  // same-stage solutions of the two previous steps (initial-guess extrapolation)
-  double *d_hist[4][3] = {};              // per stage, the potentials of the last three steps (a ring)
-  int hist_head = 0;                      // slot of the newest step
-  int hist_count = 0;
-  double hist_dt = 0.0;
+  // per stage, the solutions of the last steps of a sequence (initial-guess extrapolation)
+  static constexpr int kHistMax = 5;      // extrapolation orders 1 .. kHistMax - 1
+  struct History {
+    double *v[4][kHistMax] = {};          // a ring of `slots` vectors [n_v] per stage
+    int slots = 0;                        // ring length in use (allocated slots per stage)
+    int head = 0;                         // slot of the newest step
+    int count = 0;                        // steps recorded in the current sequence
+    double dt = 0.0, t = 0.0;             // step size of the sequence, time of its newest step
+  };
+  History hist;                           // forward potentials of fnpf_rk4_step
+  History ahist;                          // adjoint solutions of fnpf_rk4_step_vjp (steps run backwards)
   // adjoint workspaces (allocated on first use)
   double *d_lam = nullptr, *d_phibar = nullptr;
   double *d_kbe = nullptr, *d_kbp = nullptr, *d_ybe = nullptr, *d_ybp = nullptr;

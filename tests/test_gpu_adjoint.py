@@ -163,3 +163,55 @@ def test_lpf_rk4_step_vjp(name):
     eh, ph = md.rk4_step(eta, phis, t, dt, h=h + 1j * EPS * vh)
     lhs_h = ybe @ (eh.imag / EPS) + ybp @ (ph.imag / EPS)
     assert abs(lhs_h - host(hb) @ vh) <= 1e-9 * abs(lhs_h)
+
+
+def test_step_vjp_sequence_extrapolation():
+    """Eight ERK4 steps of the bar case run backwards through fnpf_rk4_step_vjp (calls at
+    t, t - dt, ...): the adjoint solves extrapolated from the previous calls (degree 4) give the
+    same input adjoints and depth gradient as starting each solve from the previous stage's
+    solution (degree 0), to the solve tolerance, in fewer CG iterations.  A call out of sequence
+    (another dt) starts a new history and still gives the same result."""
+    wl = _case("bar")
+    m, xh, x, y, h, eta, phis, ctx0, rng = _setup(wl)
+    dt, n = 0.03, 8
+    ybe, ybp = rng.standard_normal(m.n_s), rng.standard_normal(m.n_s)
+    out, iters = {}, {}
+    for ex in (0, 4):
+        ctx = fnpf.Context(m, g=wl.g)
+        ra = wl.relaxation_arrays(x, y)
+        ctx.set_relaxation(*ra, omega=wl.relax_wave.omega, t_ramp=wl.t_ramp)
+        o = fnpf.default_opts(rtol=1e-12, check_every=10, extrapolate=ex)
+        e, p = dev(eta), dev(phis)
+        tapes = []
+        for k in range(n):
+            tapes.append(ctx.new_tape())
+            ctx.rk4_step(e, p, dev(h), k * dt, dt, opts=o, tape=tapes[-1])
+        eb, pb = dev(ybe), dev(ybp)
+        hb = torch.zeros(m.n_s, dtype=torch.float64, device="cuda")
+        its = 0
+        for k in range(n - 1, -1, -1):
+            infos = ctx.rk4_step_vjp(dev(h), k * dt, dt, tapes[k], eb, pb, hb, opts=o)
+            its += sum(i["iters"] for i in infos)
+        out[ex], iters[ex] = (host(eb), host(pb), host(hb)), its
+        if ex == 4:
+            # out of sequence: a different dt restarts the history; the result is unchanged
+            e2, p2 = dev(eta), dev(phis)
+            tape = ctx.new_tape()
+            ctx.rk4_step(e2, p2, dev(h), 0.0, 0.5 * dt, opts=o, tape=tape)
+            eb2, pb2 = dev(ybe), dev(ybp)
+            hb2 = torch.zeros(m.n_s, dtype=torch.float64, device="cuda")
+            ctx.rk4_step_vjp(dev(h), 0.0, 0.5 * dt, tape, eb2, pb2, hb2, opts=o)
+            ref = fnpf.Context(m, g=wl.g)
+            ref.set_relaxation(*ra, omega=wl.relax_wave.omega, t_ramp=wl.t_ramp)
+            o0 = fnpf.default_opts(rtol=1e-12, check_every=10, extrapolate=0)
+            e3, p3 = dev(eta), dev(phis)
+            tape3 = ref.new_tape()
+            ref.rk4_step(e3, p3, dev(h), 0.0, 0.5 * dt, opts=o0, tape=tape3)
+            eb3, pb3 = dev(ybe), dev(ybp)
+            hb3 = torch.zeros(m.n_s, dtype=torch.float64, device="cuda")
+            ref.rk4_step_vjp(dev(h), 0.0, 0.5 * dt, tape3, eb3, pb3, hb3, opts=o0)
+            for a, b in ((eb2, eb3), (pb2, pb3), (hb2, hb3)):
+                assert np.linalg.norm(host(a) - host(b)) <= 1e-9 * np.linalg.norm(host(b))
+    for a, b in zip(out[4], out[0]):
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b)
+    assert iters[4] < iters[0], iters

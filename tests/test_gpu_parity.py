@@ -496,28 +496,30 @@ def test_rk4_step_multigrid(precision):
 
 
 def test_warm_start_extrapolation_c2():
-    """C2 full size, 5 ERK4 steps: the initial guesses extrapolated quadratically, linearly or not
-    at all from the previous steps reach the same states to the solve tolerance, and once its
-    history exists the quadratic one needs fewer CG iterations than either.  (The previous stage's
-    potential, used without extrapolation, is already a second-order guess for the first and third
-    stages, so the linear extrapolation need not beat it.)"""
+    """C2 full size, 7 ERK4 steps: initial guesses extrapolated in time with polynomials of degree
+    0 (none) to 4 from the previous steps reach the same states to the solve tolerance; each degree
+    repeats the iterations of the one below until its longer history exists; and, with their
+    histories in place, the quadratic guess needs fewer CG iterations than the linear one or none,
+    and the quartic one no more than the quadratic.  (The previous stage's potential, used without
+    extrapolation, is already a second-order guess for the first and third stages, so the linear
+    extrapolation need not beat it.)"""
     wl = configs.c2()
-    pr = Pair(wl)
     out, iters = {}, {}
-    for ex in (0, 1, 2):
+    for ex in (0, 1, 2, 3, 4):
+        pr = Pair(wl)   # a fresh context each: the multigrid eigenvalue estimates carry over otherwise
         e, p = pr.d_eta.clone(), pr.d_phis.clone()
-        pr.ctx.set_warm_start(None)
         opts = fnpf.default_opts(rtol=1e-10, extrapolate=ex)
         its = []
-        for n in range(5):
+        for n in range(7):
             infos = pr.ctx.rk4_step(e, p, pr.d_h, n * wl.dt, wl.dt, opts=opts)
             its.append(sum(i["iters"] for i in infos))
         out[ex], iters[ex] = (host(e), host(p)), its
-    for ex in (1, 2):
+    for ex in (1, 2, 3, 4):
         assert rel(out[ex][0], out[0][0]) < 1e-8 and rel(out[ex][1], out[0][1]) < 1e-8
-    # histories: linear from the third step on, quadratic from the fourth
-    assert iters[1][:2] == iters[0][:2] and iters[2][:3] == iters[1][:3], iters
-    assert all(iters[2][n] < min(iters[1][n], iters[0][n]) for n in (3, 4)), iters
+        # degree ex needs ex + 1 past steps: the first ex + 1 steps repeat degree ex - 1
+        assert iters[ex][: ex + 1] == iters[ex - 1][: ex + 1], iters
+    assert all(iters[2][n] < min(iters[1][n], iters[0][n]) for n in (5, 6)), iters
+    assert all(iters[4][n] <= iters[2][n] for n in (5, 6)), iters
 
 
 def test_multigrid_repeatable_and_c2():

@@ -432,7 +432,7 @@ def main():
         return
 
     # -- ERK4 steps --------------------------------------------------------------------
-    o_mixed = fnpf.default_opts(precision=1, rtol=args.rtol, inner_rtol=1e-4, check_every=5, max_outer=30)
+    o_mixed = fnpf.default_opts(precision=1, rtol=args.rtol, inner_rtol=1e-6, check_every=5, max_outer=30)
     o_f64 = fnpf.default_opts(precision=0, rtol=args.rtol, check_every=5)
     o_jacobi = fnpf.default_opts(precision=1, precond=1, rtol=args.rtol, inner_rtol=1e-4, check_every=25,
                                  max_outer=30)

@@ -157,7 +157,7 @@ typedef struct {
 } fnpf_solve_info;
 
 /* Defaults: FP64, p-multigrid (precond 2), rtol 1e-8, atol 0, max_iter 20000,
- * check_every 8, inner_rtol 1e-4, max_outer 30, extrapolate 4, cheb_degree 2, use_graph 1. */
+ * check_every 8, inner_rtol 1e-6, max_outer 30, extrapolate 4, cheb_degree 2, use_graph 1. */
 void fnpf_default_opts(fnpf_solve_opts *opts);
 
 /* Create a context on the current HIP device: validates and copies the mesh,

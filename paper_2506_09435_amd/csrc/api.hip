@@ -589,7 +589,7 @@ void fnpf_default_opts(fnpf_solve_opts *o) {
   o->atol = 0.0;
   o->max_iter = 20000;
   o->check_every = 8;
-  o->inner_rtol = 1e-4;
+  o->inner_rtol = 1e-6;
   o->max_outer = 30;
   o->extrapolate = 4;
   o->cheb_degree = 2;

@@ -94,3 +94,4 @@ def test_null_context_calls():
     assert L.fnpf_status_string(4).decode().startswith("geometry")
     o = fnpf.default_opts()
     assert (o.precision, o.precond, o.rtol, o.check_every, o.cheb_degree, o.extrapolate) == (0, 2, 1e-8, 8, 2, 4)
+    assert o.inner_rtol == 1e-6

@@ -1147,7 +1147,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   const int64_t e0 = (int64_t)col * nz;
   for (int l = 0; l < nz; ++l) {
     const double zz = 0.5 * (layer_s[l + 1] - layer_s[l]) * Hn;   // z_zeta (sigma-linear per layer)
-    double gz[N1], c01[N1], c02[N1], c12[N1];
+    double gz[N1];
     double *Ge64 = G64 ? G64 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
     float *Ge32 = G32 ? G32 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
 #pragma unroll
@@ -1186,9 +1186,6 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
         s0[lc * NP + q] = g00;
         s1[lc * NP + q] = g11;
         gz[k] = g22;
-        c01[k] = g01;
-        c02[k] = g02;
-        c12[k] = g12;
       } else {
         const double b1x = -zx * A00 / zz;
         const double b1z = 1.0 / zz;
@@ -1207,12 +1204,14 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
         }
         s0[lc * NP + q] = g00;
         gz[k] = g11;
-        c01[k] = g01;
       }
     }
     __syncthreads();
-    double dk[N1];
-#pragma unroll
+    // diagonal, one level at a time (not unrolled: the unrolled form held every level's terms and
+    // the derivative tables in registers, which cut the occupancy to one wave per SIMD); the
+    // mixed terms are recomputed from the same expressions as above
+    double top = 0.0;
+#pragma unroll 1
     for (int k = 0; k < N1; ++k) {
       double d = 0.0;
 #pragma unroll
@@ -1223,34 +1222,40 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
         d += a * a * gz[m];
       }
       const double Dkk = dmat<double>(P, k, k);
+      const double sg = sigma[l * P + k];
+      const double zx = -hx + sg * Hx;
+      const double f = wh * wgt(P, k) * detJh * zz;
       if constexpr (DIM == 3) {
 #pragma unroll
         for (int m = 0; m < N1; ++m) d += Dcj2[m] * s1[lc * NP + k * NH + m * N1 + i];
-        d += 2.0 * (Dii * Djj * c01[k] + Dii * Dkk * c02[k] + Djj * Dkk * c12[k]);
+        const double zy = -hy + sg * Hy;
+        const double b2x = -(zx * A00 + zy * A10) / zz;
+        const double b2y = -(zx * A01 + zy * A11) / zz;
+        const double c01 = f * (A00 * A10 + A01 * A11);
+        const double c02 = f * (A00 * b2x + A01 * b2y);
+        const double c12 = f * (A10 * b2x + A11 * b2y);
+        d += 2.0 * (Dii * Djj * c01 + Dii * Dkk * c02 + Djj * Dkk * c12);
       } else {
-        d += 2.0 * Dii * Dkk * c01[k];
+        const double b1x = -zx * A00 / zz;
+        const double c01 = f * A00 * b1x;
+        d += 2.0 * Dii * Dkk * c01;
       }
-      dk[k] = d;
-    }
-    __syncthreads();
-    dk[0] += carry;
-    if (active) {
-      const int kend = (l == nz - 1) ? N1 : P;
-#pragma unroll
-      for (int k = 0; k < N1; ++k) {
-        if (k < kend) {
-          const int v = l * P + k;
-          const int64_t idx = (int64_t)v * n_s + hn;
-          const double val = scatter(diag, idx, dk[k], fl);
-          if (fl & kLast) {
-            const double di = (v == P * nz) ? 0.0 : 1.0 / val;
-            dinv[idx] = di;
-            if (dinv32) dinv32[idx] = (float)di;
-          }
+      if (k == 0) d += carry;
+      if (k == P && l < nz - 1) {
+        top = d;   // the level shared with the next layer, completed there
+      } else if (active) {
+        const int v = l * P + k;
+        const int64_t idx = (int64_t)v * n_s + hn;
+        const double val = scatter(diag, idx, d, fl);
+        if (fl & kLast) {
+          const double di = (v == P * nz) ? 0.0 : 1.0 / val;
+          dinv[idx] = di;
+          if (dinv32) dinv32[idx] = (float)di;
         }
       }
     }
-    carry = dk[P];
+    __syncthreads();
+    carry = top;
   }
 }
 

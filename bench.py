@@ -197,8 +197,8 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1):
     eta_in = torch.tensor(wl.relax_wave.eta(x, y, 0.0), device="cuda")
     phi_in = torch.tensor(wl.relax_wave.phi(x, y, 0.0), device="cuda")
     # Jacobi by default: on this 0.55 M-DoF mesh with 9.5:1 elements in plan the multigrid cycle
-    # costs more than its iteration savings in the rollout (200 steps: forward 9.1 s with the
-    # multigrid preconditioner against 5.7 s, backward 25.5 s against 14.6 s)
+    # costs more than its iteration savings in the rollout (200 steps: forward 9.2 s with the
+    # multigrid preconditioner against 5.7 s, backward 15.3 s against 7.3 s)
     o = fnpf.default_opts(rtol=rtol, precond=precond, check_every=25 if precond == 1 else 5)
     with torch.no_grad():
         obs = rollout(fctx, eta_in, phi_in, B @ c_true, 0.0, wl.dt, nsteps, opts=o) @ P.T

@@ -69,11 +69,14 @@ def test_gradient_vs_complex_step_and_fd():
     J.backward()
     d_adj = float(c.grad.cpu().numpy() @ vc + e0.grad.cpu().numpy() @ ve)
     assert abs(d_adj - d_cs) <= 1e-9 * abs(d_cs)
-    # checkpoint spacing does not change the gradient
-    c2 = torch.tensor(c0, device="cuda", requires_grad=True)
-    e2 = torch.tensor(eta0, device="cuda", requires_grad=True)
-    loss(c2, e2, every=1).backward()
-    assert torch.allclose(c2.grad, c.grad, rtol=1e-10, atol=1e-16)
+    # keeping every tape (the default here) or checkpoints every 1 or 3 steps with recomputation
+    # gives the same gradient
+    for every in (0, 1, 3):
+        c2 = torch.tensor(c0, device="cuda", requires_grad=True)
+        e2 = torch.tensor(eta0, device="cuda", requires_grad=True)
+        loss(c2, e2, every=every).backward()
+        assert torch.allclose(c2.grad, c.grad, rtol=1e-10, atol=1e-16), every
+        assert torch.allclose(e2.grad, e0.grad, rtol=1e-10, atol=1e-16), every
     # central differences of the library's own forward
     eps = 1e-4
     with torch.no_grad():

@@ -217,8 +217,10 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     fctx.set_warm_start(None)
-    J = loss(c, e0, o)
+    t0 = time.perf_counter()
+    J = loss(c, e0, o)              # the same forward, keeping what the backward needs
     torch.cuda.synchronize()
+    t_fwd_taped = time.perf_counter() - t0
     t0 = time.perf_counter()
     J.backward()
     torch.cuda.synchronize()
@@ -226,7 +228,7 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1):
     out = dict(workload=f"C4 bar 64x16x4 p=5 (n_v={m.n_v}), {nsteps} steps, 8 gauges, 64 controls + eta0, "
                         f"FP64 forward and adjoint",
                rtol=rtol, preconditioner={1: "Jacobi", 2: "p-multigrid"}.get(precond, "none"),
-               t_forward_s=t_fwd, t_backward_s=t_bwd, ratio=t_bwd / t_fwd,
+               t_forward_s=t_fwd, t_forward_taped_s=t_fwd_taped, t_backward_s=t_bwd, ratio=t_bwd / t_fwd,
                grad_norm_c=float(c.grad.norm()), loss=float(J.detach()))
     if fd_dirs > 0:
         o12 = fnpf.default_opts(rtol=1e-12, check_every=25)

@@ -167,7 +167,7 @@ def cpu_baseline(wl, target_s=10.0):
                        f"{reps} reps in {el:.1f} s; DoF counted as columns x n_v/n_eh")
 
 
-def adjoint_leg(nsteps, rtol, fd_dirs, precond=1):
+def adjoint_leg(nsteps, rtol, fd_dirs, precond=1, adj_precond=None):
     """C4 bar: gauge misfit over nsteps ERK4 steps, gradient w.r.t. 64 bathymetry controls and eta0.
 
     Returns the forward and backward (checkpoint recomputation + adjoint) times, their ratio
@@ -203,8 +203,11 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1):
     with torch.no_grad():
         obs = rollout(fctx, eta_in, phi_in, B @ c_true, 0.0, wl.dt, nsteps, opts=o) @ P.T
 
+    oa = o if adj_precond is None else fnpf.default_opts(rtol=rtol, precond=adj_precond,
+                                                          check_every=25 if adj_precond == 1 else 5)
+
     def loss(c, e0, opts):
-        traj = rollout(fctx, e0, phi_in, B @ c, 0.0, wl.dt, nsteps, opts=opts)
+        traj = rollout(fctx, e0, phi_in, B @ c, 0.0, wl.dt, nsteps, opts=opts, adj_opts=oa if opts is o else None)
         return 0.5 * ((traj @ P.T - obs) ** 2).sum()
 
     c = torch.tensor(c0, device="cuda", requires_grad=True)
@@ -228,6 +231,8 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1):
     out = dict(workload=f"C4 bar 64x16x4 p=5 (n_v={m.n_v}), {nsteps} steps, 8 gauges, 64 controls + eta0, "
                         f"FP64 forward and adjoint",
                rtol=rtol, preconditioner={1: "Jacobi", 2: "p-multigrid"}.get(precond, "none"),
+               adjoint_preconditioner={1: "Jacobi", 2: "p-multigrid"}.get(
+                   precond if adj_precond is None else adj_precond, "none"),
                t_forward_s=t_fwd, t_forward_taped_s=t_fwd_taped, t_backward_s=t_bwd, ratio=t_bwd / t_fwd,
                grad_norm_c=float(c.grad.norm()), loss=float(J.detach()))
     if fd_dirs > 0:

@@ -522,6 +522,28 @@ def test_warm_start_extrapolation_c2():
     assert all(iters[4][n] <= iters[2][n] for n in (5, 6)), iters
 
 
+def test_extrapolation_degree_changes_within_a_run():
+    """Changing opts.extrapolate between steps of one context (4, then 2, 0, 3 and 1, and a
+    different dt in between) restarts the history each time and keeps every state within the
+    solve tolerance of a run without extrapolation."""
+    wl = _case("box_mixed")
+    runs = {}
+    for plan in ("mixed", "none"):
+        pr = Pair(wl)
+        e, p = pr.d_eta.clone(), pr.d_phis.clone()
+        t, states = 0.0, []
+        for ex, dt, n in ((4, 0.02, 6), (2, 0.02, 3), (0, 0.02, 2), (3, 0.01, 5), (1, 0.02, 3)):
+            o = fnpf.default_opts(rtol=1e-12, extrapolate=ex if plan == "mixed" else 0)
+            for _ in range(n):
+                infos = pr.ctx.rk4_step(e, p, pr.d_h, t, dt, opts=o)
+                assert all(i["rel_res"] <= 1e-12 for i in infos)
+                t += dt
+            states.append((host(e), host(p)))
+        runs[plan] = states
+    for (ea, pa), (eb, pb) in zip(runs["mixed"], runs["none"]):
+        assert rel(ea, eb) < 1e-9 and rel(pa, pb) < 1e-9
+
+
 def test_multigrid_repeatable_and_c2():
     """C2 full size: the multigrid solve is bitwise repeatable and satisfies the oracle's residual."""
     wl = configs.c2()

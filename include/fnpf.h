@@ -300,7 +300,7 @@ fnpf_status fnpf_surface_quadrature_info(fnpf_ctx ctx, int32_t *nq, int32_t *ite
  * of the largest eigenvalue of D^-1 A on the unknowns that sets the Chebyshev
  * intervals (the value before the 1.1 safety factor; 0 where that precision
  * has not been refreshed yet).  lam64, lam32: host arrays of cap entries, or
- * NULL.  Errors: ARG for cap < 0. */
+ * NULL; reading them synchronises the device.  Errors: ARG for cap < 0. */
 fnpf_status fnpf_multigrid_info(fnpf_ctx ctx, int32_t *levels, double *lam64, double *lam32, int32_t cap);
 
 /* Modal filter of surface fields (Sec. 3.2, modal filtering; the paper's

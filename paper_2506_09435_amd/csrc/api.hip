@@ -929,9 +929,13 @@ fnpf_status fnpf_multigrid_info(fnpf_ctx ctx, int32_t *levels, double *lam64, do
   if (cap < 0) return fail(&c, FNPF_ERR_ARG, "cap must be >= 0");
   const int nl = c.mg_built ? (int)c.mg.size() + 1 : 0;
   if (levels) *levels = nl;
+  if (nl == 0 || cap == 0 || (!lam64 && !lam32)) return FNPF_OK;
+  std::vector<double> h((size_t)2 * nl);
+  HIPCHK(hipDeviceSynchronize());   // the estimates are written on the device by the solves' streams
+  HIPCHK(hipMemcpy(h.data(), c.d_mg_lam, sizeof(double) * 2 * nl, hipMemcpyDeviceToHost));
   for (int l = 0; l < nl && l < cap; ++l) {
-    if (lam64) lam64[l] = l == 0 ? c.lam64 : c.mg[l - 1].lam64;
-    if (lam32) lam32[l] = l == 0 ? c.lam32 : c.mg[l - 1].lam32;
+    if (lam64) lam64[l] = h[l];
+    if (lam32) lam32[l] = h[nl + l];
   }
   return FNPF_OK;
 }

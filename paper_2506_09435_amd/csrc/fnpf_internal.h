@@ -142,7 +142,6 @@ struct MgLevel {
   double *Hc = nullptr, *hc = nullptr;    // eta + h and h at its surface nodes
   double *v64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // b, x, r, d, q
   float *v32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  double lam64 = 0.0, lam32 = 0.0;        // estimated largest eigenvalue of D^-1 A
   double *ev64 = nullptr;                 // its eigenvector estimate (power-iteration warm start)
   float *ev32 = nullptr;
   bool ev_ok64 = false, ev_ok32 = false;
@@ -245,10 +244,9 @@ struct Ctx {
   bool mg_stale64 = true, mg_stale32 = true;   // geometry changed since the last refresh
   double *mg_f64[4] = {nullptr, nullptr, nullptr, nullptr};  // fine-level z, r, d, q
   float *mg_f32[4] = {nullptr, nullptr, nullptr, nullptr};
-  double lam64 = 0.0, lam32 = 0.0;
   double *d_mgc = nullptr;                // Chebyshev coefficient table [precision][level][32]
+  double *d_mg_lam = nullptr;             // eigenvalue estimates behind it [precision][level]
   double *d_mg_lz = nullptr;              // Lanczos coefficients and scalars of the eigenvalue estimate
-  std::vector<double> h_mgc;
   double *mg_ev64 = nullptr;              // fine-level eigenvector estimate
   float *mg_ev32 = nullptr;
   bool mg_ev_ok64 = false, mg_ev_ok32 = false;

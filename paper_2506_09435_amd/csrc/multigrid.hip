@@ -638,8 +638,6 @@ struct Prec<double> {
   static double *const *lv(MgLevel &L) { return L.v64; }
   static double *const *fv(Ctx &c) { return c.mg_f64; }
   static const double *dinv(Ctx &c) { return c.d_dinv; }
-  static double &lam(MgLevel &L) { return L.lam64; }
-  static double &lamf(Ctx &c) { return c.lam64; }
   static bool &stale(Ctx &c) { return c.mg_stale64; }
   static double *&ev(MgLevel &L) { return L.ev64; }
   static double *&evf(Ctx &c) { return c.mg_ev64; }
@@ -652,8 +650,6 @@ struct Prec<float> {
   static float *const *lv(MgLevel &L) { return L.v32; }
   static float *const *fv(Ctx &c) { return c.mg_f32; }
   static const float *dinv(Ctx &c) { return c.d_dinv32; }
-  static double &lam(MgLevel &L) { return L.lam32; }
-  static double &lamf(Ctx &c) { return c.lam32; }
   static bool &stale(Ctx &c) { return c.mg_stale32; }
   static float *&ev(MgLevel &L) { return L.ev32; }
   static float *&evf(Ctx &c) { return c.mg_ev32; }
@@ -746,7 +742,7 @@ const double *coef_table(Ctx &c, int l) {
   return c.d_mgc + ((sizeof(T) == 8 ? 0 : 1) * (int)(c.mg.size() + 1) + l) * kMgCoef;
 }
 
-void chebyshev_coefficients(double lam, double ratio, double *cf) {
+__host__ __device__ void chebyshev_coefficients(double lam, double ratio, double *cf) {
   const double lmax = kMgSafety * lam, lmin = lmax / ratio;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   for (int k = 0; k < kMgCoef; ++k) cf[k] = 0.0;
@@ -762,6 +758,24 @@ void chebyshev_coefficients(double lam, double ratio, double *cf) {
     }
     rho0 = rho1;
   }
+}
+
+// The table of one level from its eigenvalue estimate *lam on the device, so that a geometry update
+// needs no host round trip; lam_out keeps the estimate.  A non-positive or non-finite estimate
+// gives a NaN table, which the solve then reports as a non-finite residual.
+__global__ void k_cheb_coef(const double *lam, double ratio, double *cf, double *lam_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double l = *lam;
+  *lam_out = l;
+  if (l > 0.0 && l <= 1e300) {
+    chebyshev_coefficients(l, ratio, cf);
+  } else {
+    for (int k = 0; k < kMgCoef; ++k) cf[k] = __builtin_nan("");
+  }
+}
+
+__global__ void k_set_scalar(double *p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 // Chebyshev smoothing of A x = b on level L (D^-1 A spectrum estimate lam), m steps.  From zero:
@@ -938,29 +952,27 @@ hipError_t lanczos_lambda(Ctx &c, Ctx &L, T *u, T *v, T *vp, T *q, double &lam, 
   return hipGetLastError();
 }
 
-// Largest eigenvalue of D^-1 A on level L: Lanczos the first time (Ritz vector into v), then
-// Rayleigh-quotient power iterations from the previous eigenvector estimate v after each
-// geometry update.  w1, w2, q are work vectors of the level.
+// Largest eigenvalue of D^-1 A on level L, left in *pw on the device: Lanczos the first time
+// (Ritz vector into v), then Rayleigh-quotient power iterations from the previous eigenvector
+// estimate v after each geometry update (no host synchronisation).  w1, w2, q are work vectors.
 template <typename T>
-hipError_t estimate_lambda(Ctx &c, Ctx &L, T *v, T *q, T *w1, T *w2, bool warm, double &lam, hipStream_t s) {
-  if (!warm) return lanczos_lambda<T>(c, L, v, w1, w2, q, lam, s);
+hipError_t estimate_lambda(Ctx &c, Ctx &L, T *v, T *q, T *w1, T *w2, bool warm, double *pw, hipStream_t s) {
+  if (!warm) {
+    double lam = 0.0;
+    hipError_t e = lanczos_lambda<T>(c, L, v, w1, w2, q, lam, s);
+    if (e != hipSuccess) return e;
+    k_set_scalar<<<1, 1, 0, s>>>(pw, lam);
+    return hipGetLastError();
+  }
   const T *dinv = Prec<T>::dinv(L);
   const int64_t n = L.n_v;
-  const int its = kPowNext;
-  double *pw = c.d_partial + c.n_partial - 4;   // two scalars past the partials the dots use
-  for (int it = 0; it < its; ++it) {
+  for (int it = 0; it < kPowNext; ++it) {
     hipError_t e = launch_apply(L, Prec<T>::dt, v, q, true, nullptr, nullptr, s);
     if (e != hipSuccess) return e;
     k_pow_dots<T><<<kVecBlocks, kVecThreads, 0, s>>>(v, q, dinv, n, c.d_partial);
     k_pow_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, pw);
     k_pow_next<T><<<kVecBlocks, kVecThreads, 0, s>>>(v, q, dinv, n, pw);
   }
-  double h[2];
-  hipError_t e = hipMemcpyAsync(h, pw, sizeof h, hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return e;
-  lam = h[0];
   return hipGetLastError();
 }
 
@@ -1012,6 +1024,8 @@ fnpf_status mg_build(Ctx &c) {
   }
   if (dalloc_t(&c.d_mgc, (size_t)2 * (c.mg.size() + 1) * kMgCoef) != hipSuccess) return FNPF_ERR_ALLOC;
   if (dalloc_t(&c.d_mg_lz, (size_t)kLzScalars) != hipSuccess) return FNPF_ERR_ALLOC;
+  if (dalloc_t(&c.d_mg_lam, (size_t)2 * (c.mg.size() + 1)) != hipSuccess) return FNPF_ERR_ALLOC;
+  if (hipMemset(c.d_mg_lam, 0, sizeof(double) * 2 * (c.mg.size() + 1)) != hipSuccess) return FNPF_ERR_HIP;
   c.mg_built = true;
   c.mg_stale64 = c.mg_stale32 = true;
   return FNPF_OK;
@@ -1045,6 +1059,8 @@ void mg_free(Ctx &c) {
   c.d_mgc = nullptr;
   if (c.d_mg_lz) (void)hipFree(c.d_mg_lz);
   c.d_mg_lz = nullptr;
+  if (c.d_mg_lam) (void)hipFree(c.d_mg_lam);
+  c.d_mg_lam = nullptr;
   c.mg_built = false;
 }
 
@@ -1076,37 +1092,29 @@ fnpf_status mg_refresh(Ctx &c, hipStream_t s) {
     if (st != FNPF_OK) return st;
     F = L.c;
   }
-  // eigenvalue estimates, warm-started from the previous geometry's eigenvector estimates
-  {
-    double lam = 0.0;
-    if (estimate_lambda<T>(c, c, Prec<T>::evf(c), Prec<T>::fv(c)[3], Prec<T>::fv(c)[1], Prec<T>::fv(c)[2],
-                           Prec<T>::evokf(c), lam, s) != hipSuccess)
-      return FNPF_ERR_HIP;
-    Prec<T>::lamf(c) = lam;
-    Prec<T>::evokf(c) = true;
-    for (auto &L : c.mg) {
-      if (estimate_lambda<T>(c, *L.c, Prec<T>::ev(L), Prec<T>::lv(L)[4], Prec<T>::lv(L)[2], Prec<T>::lv(L)[3],
-                             Prec<T>::evok(L), lam, s) != hipSuccess)
-        return FNPF_ERR_HIP;
-      Prec<T>::lam(L) = lam;
-      Prec<T>::evok(L) = true;
-    }
-  }
-  if (!(Prec<T>::lamf(c) > 0.0)) return FNPF_ERR_NAN;
-  // coefficient table of this precision (stream-ordered before any later use)
+  // eigenvalue estimates, warm-started from the previous geometry's eigenvector estimates, and the
+  // coefficient table of this precision, all stream-ordered before any later use
   {
     const int nl = (int)c.mg.size() + 1;
-    std::vector<double> &tab = c.h_mgc;
-    tab.resize((size_t)2 * nl * kMgCoef);
     const int base = (sizeof(T) == 8 ? 0 : 1) * nl;
+    double *pw = c.d_partial + c.n_partial - 4;   // two scalars past the partials the dots use
     for (int l = 0; l < nl; ++l) {
-      const double lam = l == 0 ? Prec<T>::lamf(c) : Prec<T>::lam(c.mg[l - 1]);
-      chebyshev_coefficients(lam, l == nl - 1 ? kMgCoarseRatio : kMgSmoothRatio, tab.data() + (base + l) * kMgCoef);
+      hipError_t e;
+      if (l == 0) {
+        e = estimate_lambda<T>(c, c, Prec<T>::evf(c), Prec<T>::fv(c)[3], Prec<T>::fv(c)[1], Prec<T>::fv(c)[2],
+                               Prec<T>::evokf(c), pw, s);
+        Prec<T>::evokf(c) = true;
+      } else {
+        MgLevel &L = c.mg[l - 1];
+        e = estimate_lambda<T>(c, *L.c, Prec<T>::ev(L), Prec<T>::lv(L)[4], Prec<T>::lv(L)[2], Prec<T>::lv(L)[3],
+                               Prec<T>::evok(L), pw, s);
+        Prec<T>::evok(L) = true;
+      }
+      if (e != hipSuccess) return FNPF_ERR_HIP;
+      k_cheb_coef<<<1, 1, 0, s>>>(pw, l == nl - 1 ? kMgCoarseRatio : kMgSmoothRatio,
+                                  c.d_mgc + (base + l) * kMgCoef, c.d_mg_lam + base + l);
+      if (hipGetLastError() != hipSuccess) return FNPF_ERR_HIP;
     }
-    if (hipMemcpyAsync(c.d_mgc + base * kMgCoef, tab.data() + base * kMgCoef, sizeof(double) * nl * kMgCoef,
-                       hipMemcpyHostToDevice, s) != hipSuccess)
-      return FNPF_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return FNPF_ERR_HIP;
   }
   Prec<T>::stale(c) = false;
   return FNPF_OK;

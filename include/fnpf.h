@@ -110,7 +110,7 @@ typedef struct {
  *                smoothing of D^-1 A of degree cheb_degree before and after
  *                each coarse correction (interval [lmax/24, lmax], lmax 1.1x an
  *                estimate of the largest eigenvalue of D^-1 A: 20 Lanczos
- *                steps on first use, then two power iterations from the Ritz
+ *                steps on first use, then one power iteration from the Ritz
  *                vector after every fnpf_geom)
  *                and 10 Chebyshev steps on the degree-1 level.  The V-cycle is
  *                a fixed SPD operator, so the outer iteration is plain CG.

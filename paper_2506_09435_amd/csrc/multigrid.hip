@@ -35,7 +35,7 @@ constexpr double kMgSafety = 1.1;       // upper end of the smoothing interval o
 constexpr double kMgSmoothRatio = 24.0; // smoothing interval [lmax / 24, lmax]
 constexpr double kMgCoarseRatio = 30.0;
 constexpr int kLanczosSteps = 20;             // first estimate of the largest eigenvalue
-constexpr int kPowNext = 2;                   // power iterations per geometry update after that
+constexpr int kPowNext = 1;                   // power iterations per geometry update after that
 constexpr int kLzScalars = 2 * kLanczosSteps + 8;
 constexpr int kMgCoef = 32;                   // coefficient-table entries per level
 

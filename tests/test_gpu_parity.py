@@ -607,6 +607,28 @@ def test_c2_fifty_steps_fp64_vs_mixed_and_invariants():
     assert abs(E1 - E0) < 1e-6 * E0
 
 
+def test_c5_twenty_steps_fp64_vs_mixed():
+    """C5 full size (43.7 M DoF), 20 ERK4 steps at rtol 1e-8 in FP64 and in mixed precision (the
+    benchmark's solver settings): every stage converges, the two trajectories agree to the solver
+    tolerance, and the state stays finite and bounded."""
+    wl = configs.c5()
+    s = fnpf.setup_workload(wl, fp32=True)
+    out = {}
+    for precision in (0, 1):
+        e, p = s.eta0.clone(), s.phi0.clone()
+        s.ctx.set_warm_start(None)
+        opts = fnpf.default_opts(precision=precision, rtol=1e-8, check_every=5)
+        t = 0.0
+        for n in range(20):
+            infos = s.ctx.rk4_step(e, p, s.h, t, wl.dt, opts=opts)
+            assert all(i["rel_res"] <= 1e-8 for i in infos), (precision, n, infos)
+            t += wl.dt
+        out[precision] = (host(e), host(p))
+    assert rel(out[1][0], out[0][0]) < 1e-6 and rel(out[1][1], out[0][1]) < 1e-6
+    e0 = host(s.eta0)
+    assert np.all(np.isfinite(out[0][0])) and np.abs(out[0][0]).max() < 10 * np.abs(e0).max()
+
+
 def test_c3_full_size_cylinder():
     """C3 (cylinder in a tank, 771,528 DoF, unstructured O-grid + jittered block, relaxation zones):
     apply parity everywhere, multigrid solves that satisfy the oracle's equations, w parity, and

@@ -348,7 +348,7 @@ __device__ __forceinline__ void final_sums(const double *partial, int np, double
   for (int k = 0; k < NS; ++k) s[k][threadIdx.x] = a[k];
   __syncthreads();
   for (int w = kVecThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
+    if ((int)threadIdx.x < w)
 #pragma unroll
       for (int k = 0; k < NS; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
     __syncthreads();

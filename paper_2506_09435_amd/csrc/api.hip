@@ -729,7 +729,7 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   AL(c.d_wnum, c.n_s);
   AL(c.d_nk, c.n_s);
   AL(c.d_nd, c.n_s);
-  c.n_partial = std::max(std::max(3 * kVecBlocks, c.max_colour_blocks), c.n_eh) + 16;
+  c.n_partial = std::max(std::max(kMaxVecPartials, c.max_colour_blocks), c.n_eh) + 16;
   c.n_partial = std::max(c.n_partial, owner_apply_blocks(c) + 16);
   AL(c.d_partial, c.n_partial);
   AL(c.d_sc, 2);

@@ -134,6 +134,7 @@ hipError_t launch_zero_i32(int32_t *v, int64_t n, hipStream_t s);
 
 constexpr int kVecBlocks = 1024;   // fixed grid of the grid-stride vector kernels (deterministic partials)
 constexpr int kVecThreads = 256;
+constexpr int kMaxVecPartials = 6 * kVecBlocks;   // partial sums of the widest vector-kernel grid
 
 // one coarse level of the p-multigrid preconditioner
 struct MgLevel {

@@ -38,6 +38,13 @@ constexpr int kLanczosSteps = 20;             // first estimate of the largest e
 constexpr int kPowNext = 1;                   // power iterations per geometry update after that
 constexpr int kLzScalars = 2 * kLanczosSteps + 8;
 constexpr int kMgCoef = 32;                   // coefficient-table entries per level
+// Grid of the streaming vector kernels of the cycle: FP32 passes move half the bytes per element
+// and need twice the blocks in flight to keep HBM busy (FP64 passes are slower with the larger
+// grid).  Their reductions use the same grid, so partial counts follow it; the context's partial
+// buffer holds kMaxVecPartials doubles (up to three sums per block of the larger grid).
+template <typename T>
+constexpr int kVB = sizeof(T) == 4 ? 2 * kVecBlocks : kVecBlocks;
+static_assert(3 * kVB<float> <= kMaxVecPartials, "partial buffer too small for the FP32 grid");
 
 // Interpolation tables for a fine degree pf (2..8) and pc = pf / 2:
 //   c_IP[pf][r (pc+1) + a] = l^c_a(x^f_r)   coarse Lagrange basis at the fine GLL nodes
@@ -787,16 +794,16 @@ hipError_t smooth(Ctx &L, const T *b, T *x, T *r, T *d, T *q, const double *cf, 
   const T *dinv = Prec<T>::dinv(L);
   const int64_t n = L.n_v;
   if (from_zero) {
-    k_cheb0<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, r, d, x, dinv, cf, n, skip);
+    k_cheb0<T><<<kVB<T>, kVecThreads, 0, s>>>(b, r, d, x, dinv, cf, n, skip);
   } else {
     hipError_t e = launch_apply(L, Prec<T>::dt, x, q, true, nullptr, skip, s);
     if (e != hipSuccess) return e;
-    k_cheb1<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, q, r, d, x, dinv, cf, n, skip);
+    k_cheb1<T><<<kVB<T>, kVecThreads, 0, s>>>(b, q, r, d, x, dinv, cf, n, skip);
   }
   for (int k = 2; k <= m; ++k) {
     hipError_t e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s);
     if (e != hipSuccess) return e;
-    k_cheb_step<T><<<kVecBlocks, kVecThreads, 0, s>>>(r, q, d, x, dinv, cf, k, n, skip);
+    k_cheb_step<T><<<kVB<T>, kVecThreads, 0, s>>>(r, q, d, x, dinv, cf, k, n, skip);
   }
   return hipGetLastError();
 }
@@ -826,21 +833,21 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
   const T *dinv = Prec<T>::dinv(L);
   hipError_t e = hipSuccess;
   if (m == 2) {
-    if (!(l == 0 && pre_scaled)) k_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, dinv, cf, n, skip);
+    if (!(l == 0 && pre_scaled)) k_scale<T><<<kVB<T>, kVecThreads, 0, s>>>(d, b, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
-    k_pre2<T><<<kVecBlocks, kVecThreads, 0, s>>>(x, b, q, dinv, cf, n, skip);
+    k_pre2<T><<<kVB<T>, kVecThreads, 0, s>>>(x, b, q, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, x, q, true, nullptr, skip, s)) != hipSuccess) return e;
     if ((e = restrict_to<T>(L, *C.c, b, q, bc, skip, s)) != hipSuccess) return e;   // P^T (b - A x)
     if ((e = vcycle<T>(c, l + 1, bc, xc, skip, m, s)) != hipSuccess) return e;
     if ((e = prolong_to<T>(L, *C.c, xc, x, skip, s)) != hipSuccess) return e;
     if ((e = launch_apply(L, Prec<T>::dt, x, r, true, nullptr, skip, s)) != hipSuccess) return e;
-    k_post2a<T><<<kVecBlocks, kVecThreads, 0, s>>>(d, b, r, dinv, cf, n, skip);
+    k_post2a<T><<<kVB<T>, kVecThreads, 0, s>>>(d, b, r, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
     if (dot_partial != nullptr) {
-      k_post2b<T, true><<<kVecBlocks, kVecThreads, 0, s>>>(x, b, r, q, dinv, cf, n, skip, dot_partial);
+      k_post2b<T, true><<<kVB<T>, kVecThreads, 0, s>>>(x, b, r, q, dinv, cf, n, skip, dot_partial);
       if (dot_done) *dot_done = true;
     } else {
-      k_post2b<T, false><<<kVecBlocks, kVecThreads, 0, s>>>(x, b, r, q, dinv, cf, n, skip, nullptr);
+      k_post2b<T, false><<<kVB<T>, kVecThreads, 0, s>>>(x, b, r, q, dinv, cf, n, skip, nullptr);
     }
     return hipGetLastError();
   }
@@ -913,22 +920,22 @@ hipError_t lanczos_lambda(Ctx &c, Ctx &L, T *u, T *v, T *vp, T *q, double &lam, 
   std::vector<double> y(K, 0.0);
   for (int pass = 0; pass < 2; ++pass) {
     T *a = v, *b = vp;
-    k_lz_start<T><<<kVecBlocks, kVecThreads, 0, s>>>(a, b, dinv, n, c.d_partial);
-    k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, nrm, 1, nullptr, 0.0);
-    k_lz_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(a, n, nrm);
+    k_lz_start<T><<<kVB<T>, kVecThreads, 0, s>>>(a, b, dinv, n, c.d_partial);
+    k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, nrm, 1, nullptr, 0.0);
+    k_lz_scale<T><<<kVB<T>, kVecThreads, 0, s>>>(a, n, nrm);
     for (int j = 0; j < K; ++j) {
-      if (pass == 1) k_lz_acc<T><<<kVecBlocks, kVecThreads, 0, s>>>(u, a, n, y[j], j == 0);
+      if (pass == 1) k_lz_acc<T><<<kVB<T>, kVecThreads, 0, s>>>(u, a, n, y[j], j == 0);
       if (pass == 1 && j == K - 1) break;
       hipError_t e = launch_apply(L, Prec<T>::dt, a, q, true, nullptr, nullptr, s);
       if (e != hipSuccess) return e;
       if (pass == 0) {
-        k_lz_dot<T><<<kVecBlocks, kVecThreads, 0, s>>>(a, q, n, c.d_partial);
-        k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, al + j, 0, nullptr, 0.0);
+        k_lz_dot<T><<<kVB<T>, kVecThreads, 0, s>>>(a, q, n, c.d_partial);
+        k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, al + j, 0, nullptr, 0.0);
       }
-      k_lz_w<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, a, q, dinv, n, al + j, j > 0 ? be + j - 1 : nullptr,
+      k_lz_w<T><<<kVB<T>, kVecThreads, 0, s>>>(b, a, q, dinv, n, al + j, j > 0 ? be + j - 1 : nullptr,
                                                    c.d_partial);
-      if (pass == 0) k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, be + j, 1, al + j, rel);
-      k_lz_scale<T><<<kVecBlocks, kVecThreads, 0, s>>>(b, n, be + j);
+      if (pass == 0) k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, be + j, 1, al + j, rel);
+      k_lz_scale<T><<<kVB<T>, kVecThreads, 0, s>>>(b, n, be + j);
       std::swap(a, b);
     }
     if (pass == 0) {
@@ -969,9 +976,9 @@ hipError_t estimate_lambda(Ctx &c, Ctx &L, T *v, T *q, T *w1, T *w2, bool warm, 
   for (int it = 0; it < kPowNext; ++it) {
     hipError_t e = launch_apply(L, Prec<T>::dt, v, q, true, nullptr, nullptr, s);
     if (e != hipSuccess) return e;
-    k_pow_dots<T><<<kVecBlocks, kVecThreads, 0, s>>>(v, q, dinv, n, c.d_partial);
-    k_pow_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVecBlocks, pw);
-    k_pow_next<T><<<kVecBlocks, kVecThreads, 0, s>>>(v, q, dinv, n, pw);
+    k_pow_dots<T><<<kVB<T>, kVecThreads, 0, s>>>(v, q, dinv, n, c.d_partial);
+    k_pow_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, pw);
+    k_pow_next<T><<<kVB<T>, kVecThreads, 0, s>>>(v, q, dinv, n, pw);
   }
   return hipGetLastError();
 }
@@ -1150,15 +1157,15 @@ hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void 
                                                                     nullptr, nullptr);
   } else {
     if (pre)
-      k_mg_update<float, true><<<kVecBlocks, kVecThreads, 0, s>>>(
+      k_mg_update<float, true><<<kVB<float>, kVecThreads, 0, s>>>(
           (float *)x, (float *)r, (const float *)p, (const float *)q, c.n_v, partial, sc, Prec<float>::fv(c)[2],
           Prec<float>::dinv(c), coef_table<float>(c, 0));
     else
-      k_mg_update<float, false><<<kVecBlocks, kVecThreads, 0, s>>>((float *)x, (float *)r, (const float *)p,
+      k_mg_update<float, false><<<kVB<float>, kVecThreads, 0, s>>>((float *)x, (float *)r, (const float *)p,
                                                                    (const float *)q, c.n_v, partial, sc, nullptr,
                                                                    nullptr, nullptr);
   }
-  k_mg_fin_rr<<<1, kVecThreads, 0, s>>>(partial, kVecBlocks, sc);
+  k_mg_fin_rr<<<1, kVecThreads, 0, s>>>(partial, dt == FNPF_F64 ? kVB<double> : kVB<float>, sc);
   return hipGetLastError();
 }
 
@@ -1168,13 +1175,13 @@ hipError_t launch_mg_dot_dir(Ctx &c, fnpf_dtype dt, const void *r, const void *z
     if (dt == FNPF_F64)
       k_dot<double><<<kVecBlocks, kVecThreads, 0, s>>>((const double *)r, (const double *)z, c.n_v, partial, sc);
     else
-      k_dot<float><<<kVecBlocks, kVecThreads, 0, s>>>((const float *)r, (const float *)z, c.n_v, partial, sc);
+      k_dot<float><<<kVB<float>, kVecThreads, 0, s>>>((const float *)r, (const float *)z, c.n_v, partial, sc);
   }
-  k_mg_fin_rz<<<1, kVecThreads, 0, s>>>(partial, kVecBlocks, sc, first);
+  k_mg_fin_rz<<<1, kVecThreads, 0, s>>>(partial, dt == FNPF_F64 ? kVB<double> : kVB<float>, sc, first);
   if (dt == FNPF_F64)
     k_mg_dir<double><<<kVecBlocks, kVecThreads, 0, s>>>((double *)p, (const double *)z, c.n_v, sc, first);
   else
-    k_mg_dir<float><<<kVecBlocks, kVecThreads, 0, s>>>((float *)p, (const float *)z, c.n_v, sc, first);
+    k_mg_dir<float><<<kVB<float>, kVecThreads, 0, s>>>((float *)p, (const float *)z, c.n_v, sc, first);
   return hipGetLastError();
 }
 

@@ -185,6 +185,16 @@ fnpf_status fnpf_gll(int32_t p, double *nodes, double *weights, double *D);
  * xy[n_s][dim-1] (periodic nodes: the first element's image). */
 fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy);
 
+/* Surface interpolation weights, for observation operators such as the wave gauges at which
+ * the paper compares surface elevations (Sec. 4.2).  For each of n_pts points pts[n_pts][dim-1]
+ * (host, physical horizontal coordinates, periodic directions unwrapped as in eh_corner), the
+ * horizontal element containing it (the first in element order whose isoparametric map, the
+ * degree-p interpolant of its GLL node positions, has a Newton inverse in [-1, 1]^(dim-1)) and
+ * the degree-p Lagrange weights of that element's nh nodes: f(pt) = sum_t w[k][t]
+ * f[node[k][t]] for a surface field f[n_s].  node[n_pts][nh] and w[n_pts][nh] are host arrays
+ * written by the call.  Errors: ARG for a point outside the mesh, n_pts < 0 or NULL arrays. */
+fnpf_status fnpf_surface_interp_weights(fnpf_ctx ctx, int32_t n_pts, const double *pts, int32_t *node, double *w);
+
 /* Stiffness-apply variant (all compute the same operator, paper Eq. 4):
  *   0 (default) fused geometry: the per-point factors are re-evaluated in
  *     registers from five numbers per column node (eta+h, h and their
@@ -204,18 +214,14 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy);
  *     of shared nodes;
  *   1 stored factors: fnpf_geom stores G (6 or 3 per point, FP64 and FP32)
  *     and the apply streams it from HBM;
- *   2 fused geometry with a fully unrolled schedule (more registers, fewer
- *     LDS accesses; kept for comparison);
- *   3, 4, 5 fused geometry, colour schedule, alternative schedules for p = 6
- *     in 3D (3 one column per workgroup, 4 without the next-layer prefetch,
- *     5 zeta loops unrolled by two; other degrees use the schedule of 7);
  *   6 fused geometry, line schedule with colour assembly (3D): in the
  *     horizontal contraction phases each thread owns one xi-line and one
  *     eta-line of the element, so derivative coefficients are uniform
  *     scalars (2D: same as 7);
  *   7 fused geometry, colour schedule (one thread per vertical node line,
  *     derivatives through LDS reads).
- * Switching to 1 invalidates the current geometry (call fnpf_geom again). */
+ * Switching to 1 invalidates the current geometry (call fnpf_geom again).
+ * Errors: ARG for any other value. */
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant);
 
 /* Enable the FP32 path: allocates FP32 factors and the inner-PCG vectors;

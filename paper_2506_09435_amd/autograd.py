@@ -30,12 +30,13 @@ class _Rollout(torch.autograd.Function):
         e = eta0.detach().clone().contiguous()
         p = phi0.detach().clone().contiguous()
         hd = h.detach().contiguous()
-        if not any(actx.needs_input_grad[:3]):
-            every = nsteps + 1          # no gradient wanted: neither tapes nor checkpoints
-        elif every is None:
+        taping = any(actx.needs_input_grad[:3])     # False: neither tapes nor checkpoints
+        if taping and every is None:
             need = nsteps * 4 * fctx.tape_record * 8
             free, _ = torch.cuda.mem_get_info(e.device)
             every = 0 if need <= free // 4 else max(1, int(math.ceil(math.sqrt(nsteps))))
+        if taping and every > 0:
+            every = min(every, max(nsteps, 1))      # one segment from step 0 at most
         traj = torch.empty((nsteps, fctx.n_s), dtype=torch.float64, device=e.device)
         checkpoints, tapes = {}, []
         fctx.set_warm_start(None)
@@ -44,15 +45,17 @@ class _Rollout(torch.autograd.Function):
         t = t0
         for n in range(nsteps):
             tape = None
-            if every == 0:
+            if taping and every == 0:
                 tape = fctx.new_tape()
                 tapes.append((tape, t))
-            elif n % every == 0 and every <= nsteps:
+            elif taping and n % every == 0:
                 checkpoints[n] = (e.clone(), p.clone(), t)
             fctx.rk4_step(e, p, hd, t, dt, opts=opts, tape=tape)
             traj[n] = e
             t = t0 + (n + 1) * dt
         actx.fctx, actx.dt, actx.nsteps, actx.opts, actx.adj_opts, actx.every = fctx, dt, nsteps, opts, adj_opts, every
+        if taping and every > 0 and nsteps > 0 and 0 not in checkpoints:
+            raise RuntimeError("rollout: step 0 was not checkpointed")
         actx.checkpoints, actx.tapes = checkpoints, tapes
         actx.save_for_backward(hd)
         return traj
@@ -96,43 +99,22 @@ def rollout(fctx, eta0, phi0, h, t0, dt, nsteps, opts=None, adj_opts=None, check
     """Differentiable trajectory eta^1..eta^N ([N, n_s]) of N ERK4 steps.
 
     checkpoint_every: None chooses (every tape when they fit in a quarter of the free device
-    memory, else sqrt(N) checkpoints); 0 keeps every tape; k > 0 keeps the state every k steps."""
+    memory, else sqrt(N) checkpoints); 0 keeps every tape; k > 0 keeps the state every k steps
+    (k >= N: one checkpoint at step 0, the whole rollout recomputed in the backward)."""
+    if checkpoint_every is not None and int(checkpoint_every) < 0:
+        raise ValueError(f"checkpoint_every must be None or >= 0, got {checkpoint_every}")
     opts = opts if opts is not None else fnpf.default_opts()
     adj_opts = adj_opts if adj_opts is not None else opts
-    return _Rollout.apply(eta0, phi0, h, fctx, float(t0), float(dt), int(nsteps), opts, adj_opts, checkpoint_every)
+    return _Rollout.apply(eta0, phi0, h, fctx, float(t0), float(dt), int(nsteps), opts, adj_opts,
+                          None if checkpoint_every is None else int(checkpoint_every))
 
 
 def gauge_matrix(fctx, points):
-    """Dense [n_gauges, n_s] surface Lagrange interpolation for axis-aligned quads/intervals.
-
-    Uses the library's GLL nodes (fnpf_gll) and the mesh corners; a helper for losses.
-    """
-    import numpy as np
-    mesh = fctx.mesh
-    p = mesh.p
-    x, _, _ = fnpf.gll(p)
-
-    def lag(t):
-        L = np.ones(p + 1)
-        for j in range(p + 1):
-            for m in range(p + 1):
-                if m != j:
-                    L[j] *= (t - x[m]) / (x[j] - x[m])
-        return L
-
-    P = np.zeros((len(points), mesh.n_s))
-    for g, pt in enumerate(points):
-        pt = np.atleast_1d(np.asarray(pt, dtype=np.float64))
-        for e in range(mesh.n_eh):
-            c = mesh.eh_corner[e]
-            lo, hi = c.min(0), c.max(0)
-            if np.all(pt >= lo - 1e-12) and np.all(pt <= hi + 1e-12):
-                ref = 2.0 * (pt - lo) / (hi - lo) - 1.0
-                w = lag(ref[0])
-                if mesh.dim == 3:
-                    w = (lag(ref[1])[:, None] * w[None, :]).ravel()
-                np.add.at(P[g], mesh.eh_nodes[e], w)
-                break
-        else:
-            raise ValueError(f"gauge {pt} outside the mesh")
-    return torch.tensor(P, dtype=torch.float64, device=fctx.device)
+    """Dense [n_gauges, n_s] observation matrix P with (P f)_g = f(point_g): the library's
+    Lagrange weights (fnpf_surface_interp_weights) placed in a device tensor."""
+    node, w = fctx.surface_interp_weights(points)
+    P = torch.zeros((node.shape[0], fctx.n_s), dtype=torch.float64, device=fctx.device)
+    rows = torch.arange(node.shape[0], device=fctx.device).repeat_interleave(node.shape[1])
+    P[rows, torch.as_tensor(node.ravel(), dtype=torch.int64, device=fctx.device)] = torch.as_tensor(
+        w.ravel(), dtype=torch.float64, device=fctx.device)
+    return P

@@ -126,6 +126,7 @@ void free_all(Ctx &c) {
   dfree(c.d_nk);
   dfree(c.d_nd);
   dfree(c.d_partial);
+  dfree(c.d_mg_scal);
   dfree(c.d_sc);
   if (c.h_sc) (void)hipHostFree(c.h_sc);
   c.h_sc = nullptr;
@@ -295,8 +296,6 @@ fnpf_status check_err_flag(Ctx &c, hipStream_t s) {
 }
 
 int apply_blocks(const Ctx &c) {
-  // the one-column-per-workgroup schedules (p = 6, 3D) launch one block per column
-  if (c.apply_variant == 0 && c.apply_tune == 1 && c.p == 6 && c.dim == 3) return c.n_eh;
   if (owner_apply_active(c)) return owner_apply_blocks(c);
   return c.max_colour_blocks;
 }
@@ -358,7 +357,6 @@ Ctx::GraphKey graph_key(const Ctx &c, const void *x, const fnpf_solve_opts &o, i
   k.check_every = o.check_every;
   k.cheb = o.cheb_degree;
   k.variant = c.apply_variant;
-  k.tune = c.apply_tune;
   k.lines = c.apply_lines;
   k.owner = c.apply_owner;
   k.nb = nb;
@@ -729,9 +727,19 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   AL(c.d_wnum, c.n_s);
   AL(c.d_nk, c.n_s);
   AL(c.d_nd, c.n_s);
-  c.n_partial = std::max(std::max(kMaxVecPartials, c.max_colour_blocks), c.n_eh) + 16;
-  c.n_partial = std::max(c.n_partial, owner_apply_blocks(c) + 16);
+  {
+    const auto uses = partial_uses(c.max_colour_blocks, owner_apply_blocks(c));
+    c.n_partial = (int)partial_capacity(uses);
+    const std::string le = partial_layout_error(uses, c.n_partial);
+    if (!le.empty()) {
+      g_create_error = le;
+      free_all(c);
+      delete h;
+      return FNPF_ERR_ARG;
+    }
+  }
   AL(c.d_partial, c.n_partial);
+  AL(c.d_mg_scal, 4);
   AL(c.d_sc, 2);
 #undef UP
 #undef AL
@@ -763,6 +771,16 @@ fnpf_status fnpf_sizes(fnpf_ctx ctx, int64_t *n_v, int64_t *n_s, int64_t *n_e, i
   return FNPF_OK;
 }
 
+fnpf_status fnpf_surface_interp_weights(fnpf_ctx ctx, int32_t n_pts, const double *pts, int32_t *node, double *w) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (n_pts < 0) return fail(&c, FNPF_ERR_ARG, "n_pts must be >= 0");
+  if (n_pts > 0 && (!pts || !node || !w)) return fail(&c, FNPF_ERR_ARG, "pts, node and w must be host arrays");
+  const std::string e = surface_interp_weights(c, n_pts, pts, node, w);
+  if (!e.empty()) return fail(&c, FNPF_ERR_ARG, e);
+  return FNPF_OK;
+}
+
 fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy) {
   if (!ctx || !xy) return ctx ? fail(&ctx->c, FNPF_ERR_ARG, "xy is NULL") : FNPF_ERR_ARG;
   std::memcpy(xy, ctx->c.h_node_xy.data(), ctx->c.h_node_xy.size() * sizeof(double));
@@ -772,11 +790,11 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy) {
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
-  if (variant < 0 || variant > 7) return fail(&c, FNPF_ERR_ARG, "apply variant must be in 0..7");
-  c.apply_tune = (variant >= 3 && variant <= 5) ? variant - 2 : 0;
+  if (variant != 0 && variant != 1 && variant != 6 && variant != 7)
+    return fail(&c, FNPF_ERR_ARG, "apply variant must be 0, 1, 6 or 7");
   c.apply_lines = c.dim == 3 && (variant == 0 || variant == 6);
   c.apply_owner = c.dim == 3 && variant == 0;
-  if (variant >= 3) variant = 0;
+  if (variant >= 6) variant = 0;   // 6 and 7 are schedules of the fused apply (apply_lines, apply_owner)
   if (variant == c.apply_variant) return FNPF_OK;
   c.apply_variant = variant;
   if (variant == 1) {

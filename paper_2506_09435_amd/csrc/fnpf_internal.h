@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "fnpf.h"
+#include "partials.h"
 
 namespace fnpf {
 
@@ -132,9 +133,8 @@ hipError_t launch_cast_f32(const double *a, float *b, int64_t n, hipStream_t s);
 hipError_t launch_fill(double *v, double val, int64_t n, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *v, int64_t n, hipStream_t s);
 
-constexpr int kVecBlocks = 1024;   // fixed grid of the grid-stride vector kernels (deterministic partials)
+constexpr int kVecBlocks = kPartialVecBlocks;   // fixed grid of the grid-stride vector kernels (deterministic partials)
 constexpr int kVecThreads = 256;
-constexpr int kMaxVecPartials = 6 * kVecBlocks;   // partial sums of the widest vector-kernel grid
 
 // one coarse level of the p-multigrid preconditioner
 struct MgLevel {
@@ -159,6 +159,7 @@ struct Ctx {
   std::vector<double> h_arc;              // [n_eh][4][3] or empty
   std::vector<int32_t> h_tags;            // [n_eh][2(dim-1)]
   std::vector<double> h_node_xy;          // [n_s][dim-1]
+  std::vector<double> h_xh;               // [n_eh][nh][dim-1] unwrapped element node coordinates
   std::vector<double> h_layer_s;          // [nz+1]
   std::vector<double> h_sigma;            // [p nz + 1]
   std::vector<ColourRange> colours;
@@ -179,7 +180,6 @@ struct Ctx {
   // apply variant: 0 fused geometry (factors recomputed in registers), 1 stored factors,
   // 2 fused geometry, unrolled schedule; the schedule of 0 is refined by the fields below
   int apply_variant = 0;
-  int apply_tune = 0;                     // schedule option of the fused apply (p = 6, 3D)
   bool apply_lines = false;               // 3D fused apply with the xi/eta line schedule
   bool apply_owner = false;               // 3D line schedule with owner-computes assembly (two passes)
   // owner-computes assembly: contributions of a column at nodes it does not own go to face
@@ -220,7 +220,8 @@ struct Ctx {
   double *d_geoH = nullptr, *d_geoh = nullptr;    // eta + h and h of the last fnpf_geom
   double *d_wnum = nullptr, *d_nk = nullptr, *d_nd = nullptr;  // surface scatter scratch
   double *d_partial = nullptr;
-  int n_partial = 0;
+  int n_partial = 0;                       // capacity: partial_capacity(partial_uses(...))
+  double *d_mg_scal = nullptr;             // [4] power-iteration scalars of the p-multigrid refresh
   PcgScalars *d_sc = nullptr;             // [2]: outer/plain, inner
   PcgScalars *h_sc = nullptr;             // pinned host mirror
   // per stage, the solutions of the last steps of a sequence (initial-guess extrapolation)
@@ -254,11 +255,11 @@ struct Ctx {
   // captured PCG iteration chunks, replayed with hipGraphLaunch: [0] FP64 solve, [1] FP32 inner
   struct GraphKey {
     const void *x = nullptr;
-    int precond = -1, check_every = 0, cheb = 0, variant = -1, tune = -1, nb = 0;
+    int precond = -1, check_every = 0, cheb = 0, variant = -1, nb = 0;
     bool lines = false, owner = false;
     bool operator==(const GraphKey &o) const {
       return x == o.x && precond == o.precond && check_every == o.check_every && cheb == o.cheb &&
-             variant == o.variant && tune == o.tune && nb == o.nb && lines == o.lines && owner == o.owner;
+             variant == o.variant && nb == o.nb && lines == o.lines && owner == o.owner;
     }
   };
   hipGraph_t g_graph[2] = {nullptr, nullptr};
@@ -323,6 +324,7 @@ hipError_t launch_faces(Ctx &c, fnpf_dtype dt, void *y, bool mask, hipStream_t s
 // host setup (setup.cpp)
 void gll_host(int p, double *x, double *w, double *D);
 std::string coarse_numbering(const Ctx &f, int pc, std::vector<int32_t> &nodes, int64_t &n_s);
+std::string surface_interp_weights(const Ctx &c, int32_t n_pts, const double *pts, int32_t *node, double *w);
 std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double> &hm, std::vector<uint8_t> &flags,
                             std::vector<int32_t> &cols, std::vector<double> &mlump_w, std::vector<double> &mlump_s);
 

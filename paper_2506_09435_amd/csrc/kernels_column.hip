@@ -358,169 +358,12 @@ __global__ __launch_bounds__(256) void k_apply(const T *__restrict__ x, T *__res
 // det J_h.  G r is evaluated as f B (B^T r), f = w_q det J_h z_zeta.  Same operator as the
 // stored-factor kernel; HBM traffic drops to the vectors x and y.
 // ---------------------------------------------------------------------------------------------
-template <int P, int DIM, typename T, bool MASK, bool DOT>
-__global__ __launch_bounds__(256) void k_apply_fused(const T *__restrict__ x, T *__restrict__ y,
-                                                     const T *__restrict__ cg, const T *__restrict__ hmT,
-                                                     int64_t hstride, const T *__restrict__ sig,
-                                                     const T *__restrict__ half_ds,
-                                                     const int32_t *__restrict__ eh_nodes,
-                                                     const uint8_t *__restrict__ flags,
-                                                     const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
-                                                     double *__restrict__ partial, const int32_t *__restrict__ skip) {
-  using S = Sh<P, DIM>;
-  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
-  __shared__ T su[CPB * NP];
-  __shared__ T sx[CPB * NP];
-  __shared__ T sy[DIM == 3 ? CPB * NP : 1];
-  if (skip != nullptr && *skip) return;
-
-  const int lc = threadIdx.x / NH;
-  const int t = threadIdx.x - lc * NH;
-  const int i = t % N1, j = t / N1;
-  const int ci = blockIdx.x * CPB + lc;
-  const bool active = ci < ncols;
-  const int col = active ? cols[ci] : 0;
-  const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
-  const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
-  const int64_t ho = (int64_t)col * NH + t;
-
-  // column-node geometry
-  T H = T(1), Hx = T(0), hx = T(0), Hy = T(0), hy = T(0);
-  T A00 = T(1), A01 = T(0), A10 = T(0), A11 = T(1), dJ = T(1);
-  if (active) {
-    H = cg[0 * hstride + ho];
-    Hx = cg[1 * hstride + ho];
-    hx = cg[2 * hstride + ho];
-    if constexpr (DIM == 3) {
-      Hy = cg[3 * hstride + ho];
-      hy = cg[4 * hstride + ho];
-      A00 = hmT[0 * hstride + ho];
-      A01 = hmT[1 * hstride + ho];
-      A10 = hmT[2 * hstride + ho];
-      A11 = hmT[3 * hstride + ho];
-      dJ = hmT[4 * hstride + ho];
-    } else {
-      A00 = hmT[0 * hstride + ho];
-      dJ = hmT[1 * hstride + ho];
-    }
-  }
-  const T wh = (T)(DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i));
-  const T wdJ = wh * dJ;
-
-  T Dri[N1], Drj[N1], Dci[N1], Dcj[N1];
-#pragma unroll
-  for (int m = 0; m < N1; ++m) {
-    Dri[m] = dmat<T>(P, i, m);
-    Dci[m] = dmat<T>(P, m, i);
-    if constexpr (DIM == 3) {
-      Drj[m] = dmat<T>(P, j, m);
-      Dcj[m] = dmat<T>(P, m, j);
-    }
-  }
-  T *u_c = su + lc * NP;
-  T *x_c = sx + lc * NP;
-  T *y_c = sy + (DIM == 3 ? lc * NP : 0);
-
-  T ucol[N1];
-  T carry = T(0);
-  double dot = 0.0;
-  ucol[0] = active ? x[hn] : T(0);
-  const int vtop = P * nz;
-
-  for (int l = 0; l < nz; ++l) {
-#pragma unroll
-    for (int k = 1; k < N1; ++k) ucol[k] = active ? x[(int64_t)(l * P + k) * n_s + hn] : T(0);
-#pragma unroll
-    for (int k = 0; k < N1; ++k) u_c[k * NH + t] = ucol[k];
-    __syncthreads();
-
-    const T zz = half_ds[l] * H;
-    const T izz = T(1) / zz;
-    const T fl0 = wdJ * zz;
-    T vz[N1];
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      T ux = T(0), uy = T(0), uz = T(0);
-#pragma unroll
-      for (int m = 0; m < N1; ++m) ux += Dri[m] * u_c[k * NH + j * N1 + m];
-      if constexpr (DIM == 3) {
-#pragma unroll
-        for (int m = 0; m < N1; ++m) uy += Drj[m] * u_c[k * NH + m * N1 + i];
-      }
-#pragma unroll
-      for (int m = 0; m < N1; ++m) uz += dmat<T>(P, k, m) * ucol[m];
-      const T sg = sig[l * P + k];
-      const T f = (T)wgt(P, k) * fl0;
-      const T zx = sg * Hx - hx;
-      const int q = k * NH + t;
-      if constexpr (DIM == 3) {
-        const T zy = sg * Hy - hy;
-        const T b2x = -(zx * A00 + zy * A10) * izz;
-        const T b2y = -(zx * A01 + zy * A11) * izz;
-        const T gx = A00 * ux + A10 * uy + b2x * uz;
-        const T gy = A01 * ux + A11 * uy + b2y * uz;
-        const T gz = izz * uz;
-        x_c[q] = f * (A00 * gx + A01 * gy);
-        y_c[q] = f * (A10 * gx + A11 * gy);
-        vz[k] = f * (b2x * gx + b2y * gy + izz * gz);
-      } else {
-        const T b1x = -zx * A00 * izz;
-        const T g0 = A00 * ux + b1x * uz;
-        const T g1 = izz * uz;
-        x_c[q] = f * (A00 * g0);
-        vz[k] = f * (b1x * g0 + izz * g1);
-      }
-    }
-    __syncthreads();
-
-    T yk[N1];
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      T acc = T(0);
-#pragma unroll
-      for (int m = 0; m < N1; ++m) acc += Dci[m] * x_c[k * NH + j * N1 + m];
-      if constexpr (DIM == 3) {
-#pragma unroll
-        for (int m = 0; m < N1; ++m) acc += Dcj[m] * y_c[k * NH + m * N1 + i];
-      }
-#pragma unroll
-      for (int m = 0; m < N1; ++m) acc += dmat<T>(P, m, k) * vz[m];
-      yk[k] = acc;
-    }
-    yk[0] += carry;
-    if (active) {
-      const int kend = (l == nz - 1) ? N1 : P;
-#pragma unroll
-      for (int k = 0; k < N1; ++k) {
-        if (k < kend) {
-          const int v = l * P + k;
-          const int64_t idx = (int64_t)v * n_s + hn;
-          T val;
-          if (MASK && v == vtop) {
-            y[idx] = T(0);
-            val = T(0);
-          } else {
-            val = scatter(y, idx, yk[k], fl);
-          }
-          if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
-        }
-      }
-    }
-    carry = yk[P];
-    ucol[0] = ucol[P];
-  }
-  if constexpr (DOT) {
-    double s = block_sum<S::NT>(dot);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  }
-}
-
 // Same operator, register-lean schedule: the forward (gradient) loop over the zeta index k
 // runs at run time, reading the uniform row D[k][.] through the scalar cache, and scatters the
 // zeta part of the transposed contraction, y_zeta[k'] += D[k][k'] v_zeta[k], straight into a
 // register line; the backward loop is unrolled.  Live registers: the thread's D rows, its
 // vertical line, the y_zeta line and the column geometry.
-template <int P, int DIM, typename T, bool MASK, bool DOT, int CPBv = Sh<P, DIM>::CPB, bool PF = true, int UF = 1>
+template <int P, int DIM, typename T, bool MASK, bool DOT>
 __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T *__restrict__ y,
                                                       const T *__restrict__ cg, const T *__restrict__ hmT,
                                                       int64_t hstride, const T *__restrict__ sig,
@@ -530,7 +373,7 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
                                                       const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
                                                       double *__restrict__ partial, const int32_t *__restrict__ skip) {
   using S = Sh<P, DIM>;
-  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = CPBv;
+  constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
   __shared__ T su[CPB * NP];
   __shared__ T sx[CPB * NP];
   __shared__ T sy[DIM == 3 ? CPB * NP : 1];
@@ -588,27 +431,18 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
   const int vtop = P * nz;
 
   T nxt[N1];
-  if constexpr (PF) {
 #pragma unroll
-    for (int k = 1; k < N1; ++k) nxt[k] = active ? x[(int64_t)k * n_s + hn] : T(0);
-  }
+  for (int k = 1; k < N1; ++k) nxt[k] = active ? x[(int64_t)k * n_s + hn] : T(0);
   for (int l = 0; l < nz; ++l) {
-    if constexpr (PF) {
 #pragma unroll
-      for (int k = 1; k < N1; ++k) ucol[k] = nxt[k];
-    } else {
-#pragma unroll
-      for (int k = 1; k < N1; ++k) ucol[k] = active ? x[(int64_t)(l * P + k) * n_s + hn] : T(0);
-    }
+    for (int k = 1; k < N1; ++k) ucol[k] = nxt[k];
 #pragma unroll
     for (int k = 0; k < N1; ++k) u_c[k * NH + t] = ucol[k];
     __syncthreads();
-    if constexpr (PF) {
-      // issue the next layer's loads now; they complete behind this layer's arithmetic
-      if (l + 1 < nz) {
+    // issue the next layer's loads now; they complete behind this layer's arithmetic
+    if (l + 1 < nz) {
 #pragma unroll
-        for (int k = 1; k < N1; ++k) nxt[k] = active ? x[(int64_t)((l + 1) * P + k) * n_s + hn] : T(0);
-      }
+      for (int k = 1; k < N1; ++k) nxt[k] = active ? x[(int64_t)((l + 1) * P + k) * n_s + hn] : T(0);
     }
 
     const T zz = half_ds[l] * H;
@@ -617,7 +451,7 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
     T yz[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) yz[k] = T(0);
-#pragma unroll UF
+#pragma unroll 1
     for (int k = 0; k < N1; ++k) {
       T ux = T(0), uy = T(0), uz = T(0);
       const T *row = u_c + k * NH;
@@ -659,7 +493,7 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
     // own u entries are no longer read by other threads: reuse them for the output line
 #pragma unroll
     for (int k = 0; k < N1; ++k) u_c[k * NH + t] = yz[k];
-#pragma unroll UF
+#pragma unroll 1
     for (int k = 0; k < N1; ++k) {
       // independent partial sums keep the FP64 FMA chains short
       T a0 = u_c[k * NH + t], a1 = T(0), a2 = T(0), a3 = T(0);
@@ -1537,32 +1371,6 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
     if (cr.count == 0) continue;
     const int nb = (cr.count + S::CPB - 1) / S::CPB;
     if (fused) {
-      bool done = false;
-      if constexpr (P == 6 && DIM == 3) {
-        // alternative schedules kept for measurement: 1 one column per workgroup, 2 no
-        // next-layer prefetch, 3 k loops unrolled by two
-        const int tune = c.apply_tune;
-        if (tune == 1) {
-          k_apply_fused2<P, DIM, T, MASK, DOT, 1, true><<<cr.count, S::NH, 0, s>>>(
-              x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
-              DOT ? partial + off : nullptr, skip);
-          off += cr.count;
-          done = true;
-        } else if (tune == 2) {
-          k_apply_fused2<P, DIM, T, MASK, DOT, S::CPB, false><<<nb, S::NT, 0, s>>>(
-              x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
-              DOT ? partial + off : nullptr, skip);
-          off += nb;
-          done = true;
-        } else if (tune == 3) {
-          k_apply_fused2<P, DIM, T, MASK, DOT, S::CPB, true, 2><<<nb, S::NT, 0, s>>>(
-              x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
-              DOT ? partial + off : nullptr, skip);
-          off += nb;
-          done = true;
-        }
-      }
-      if (done) continue;
       if constexpr (DIM == 3) {
         if (owner_apply_active(c)) {
           T *F = nullptr;
@@ -1589,10 +1397,6 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
                                                                 c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
                                                                 DOT ? partial + off : nullptr, skip);
     }
-    else if (c.apply_variant == 2)
-      k_apply_fused<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags,
-                                                               c.d_cols + cr.offset, cr.count, c.nz, c.n_s,
-                                                               DOT ? partial + off : nullptr, skip);
     else
       k_apply<P, DIM, T, MASK, DOT><<<nb, S::NT, 0, s>>>(x, y, G, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
                                                          cr.count, c.nz, c.n_s, DOT ? partial + off : nullptr, skip);
@@ -1621,6 +1425,10 @@ static hipError_t apply_dispatch(Ctx &c, fnpf_dtype dt, const void *x, void *y, 
 
 hipError_t launch_apply(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
                         const int32_t *skip, hipStream_t s) {
+  // one partial per block of every launch when the dot product is fused
+  if (partial != nullptr &&
+      !partials_fit(c.n_partial, owner_apply_active(c) ? owner_apply_blocks(c) : c.max_colour_blocks, 1))
+    return hipErrorInvalidValue;
   if (c.dim == 3) {
     FNPF_DISPATCH(3, c.p, return (apply_dispatch<P_, 3>(c, dt, x, y, mask, partial, skip, s)));
   } else {

@@ -41,10 +41,11 @@ constexpr int kMgCoef = 32;                   // coefficient-table entries per l
 // Grid of the streaming vector kernels of the cycle: FP32 passes move half the bytes per element
 // and need twice the blocks in flight to keep HBM busy (FP64 passes are slower with the larger
 // grid).  Their reductions use the same grid, so partial counts follow it; the context's partial
-// buffer holds kMaxVecPartials doubles (up to three sums per block of the larger grid).
+// buffer is sized from the table of partials.h, which lists both grids (up to two sums per block).
 template <typename T>
 constexpr int kVB = sizeof(T) == 4 ? 2 * kVecBlocks : kVecBlocks;
-static_assert(3 * kVB<float> <= kMaxVecPartials, "partial buffer too small for the FP32 grid");
+static_assert(kVB<float> == 2 * kPartialVecBlocks && kVB<double> == kPartialVecBlocks,
+              "vector grids must match the partial-sum table (partials.h)");
 
 // Interpolation tables for a fine degree pf (2..8) and pc = pf / 2:
 //   c_IP[pf][r (pc+1) + a] = l^c_a(x^f_r)   coarse Lagrange basis at the fine GLL nodes
@@ -1104,7 +1105,7 @@ fnpf_status mg_refresh(Ctx &c, hipStream_t s) {
   {
     const int nl = (int)c.mg.size() + 1;
     const int base = (sizeof(T) == 8 ? 0 : 1) * nl;
-    double *pw = c.d_partial + c.n_partial - 4;   // two scalars past the partials the dots use
+    double *pw = c.d_mg_scal;   // two scalars of the power iteration, apart from the partials
     for (int l = 0; l < nl; ++l) {
       hipError_t e;
       if (l == 0) {

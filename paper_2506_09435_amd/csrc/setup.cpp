@@ -257,6 +257,7 @@ std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double>
         for (int a = 0; a < dim - 1; ++a) c.h_node_xy[id * (dim - 1) + a] = xh[(e * nh + t) * (dim - 1) + a];
       }
   }
+  c.h_xh = xh;
   // horizontal metrics and lumped masses
   hm.assign((size_t)ncomp * n_eh * nh, 0.0);
   mlump_w.assign(n_s, 0.0);
@@ -467,6 +468,107 @@ std::string coarse_numbering(const Ctx &f, int pc, std::vector<int32_t> &nodes, 
   n_s = next;
   nodes.resize((size_t)n_eh * nhc);
   for (size_t k = 0; k < nodes.size(); ++k) nodes[k] = (int32_t)info[keys[k]][2];
+  return "";
+}
+
+// Degree-p Lagrange interpolation of a surface field at physical horizontal points (observation
+// operators such as wave gauges).  An element contains a point when the Newton inverse of its
+// isoparametric map, x(xi, eta) = sum_ij l_i(xi) l_j(eta) x_ij over its GLL node coordinates,
+// lands in [-1, 1]^(dim-1) (to 1e-10); the first such element in element order is taken.  On an
+// edge shared by two elements both give the same weights, since only the edge's nodes are nonzero.
+namespace {
+void lagrange_row(int p, const double *x, double t, double *L, double *dL) {
+  for (int j = 0; j <= p; ++j) {
+    double v = 1.0, d = 0.0;
+    for (int m = 0; m <= p; ++m) {
+      if (m == j) continue;
+      const double f = (t - x[m]) / (x[j] - x[m]);
+      d = d * f + v / (x[j] - x[m]);
+      v *= f;
+    }
+    L[j] = v;
+    if (dL) dL[j] = d;
+  }
+}
+}  // namespace
+
+std::string surface_interp_weights(const Ctx &c, int32_t n_pts, const double *pts, int32_t *node, double *wout) {
+  const int p = c.p, n1 = p + 1, nh = c.nh, dm = c.dim - 1;
+  std::vector<double> x(n1), wq(n1), D(n1 * n1), Li(n1), Lj(n1), dLi(n1), dLj(n1);
+  gll_host(p, x.data(), wq.data(), D.data());
+  char buf[160];
+  for (int32_t k = 0; k < n_pts; ++k) {
+    const double px = pts[k * dm], py = dm == 2 ? pts[k * dm + 1] : 0.0;
+    bool found = false;
+    for (int64_t e = 0; e < c.n_eh && !found; ++e) {
+      const double *xe = c.h_xh.data() + e * nh * dm;
+      double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+      for (int t = 0; t < nh; ++t)
+        for (int a = 0; a < dm; ++a) {
+          lo[a] = std::min(lo[a], xe[t * dm + a]);
+          hi[a] = std::max(hi[a], xe[t * dm + a]);
+        }
+      // the element lies inside its node box up to its edge curvature: test a box widened by
+      // a quarter of its size
+      const double q[2] = {px, py};
+      bool out = false;
+      for (int a = 0; a < dm; ++a) {
+        const double pad = 0.25 * (hi[a] - lo[a]) + 1e-12;
+        if (q[a] < lo[a] - pad || q[a] > hi[a] + pad) out = true;
+      }
+      if (out) continue;
+      double r[2] = {0.0, 0.0};
+      bool conv = false;
+      for (int it = 0; it < 60; ++it) {
+        lagrange_row(p, x.data(), r[0], Li.data(), dLi.data());
+        if (dm == 2) lagrange_row(p, x.data(), r[1], Lj.data(), dLj.data());
+        double X[2] = {0, 0}, J[2][2] = {{0, 0}, {0, 0}};
+        for (int t = 0; t < nh; ++t) {
+          const int i = t % n1, j = t / n1;
+          const double li = Li[i], lj = dm == 2 ? Lj[j] : 1.0;
+          const double di = dLi[i], dj = dm == 2 ? dLj[j] : 0.0;
+          for (int a = 0; a < dm; ++a) {
+            const double v = xe[t * dm + a];
+            X[a] += li * lj * v;
+            J[a][0] += di * lj * v;
+            if (dm == 2) J[a][1] += li * dj * v;
+          }
+        }
+        double f0 = X[0] - q[0], f1 = dm == 2 ? X[1] - q[1] : 0.0, d0, d1;
+        if (dm == 1) {
+          d0 = f0 / J[0][0];
+          d1 = 0.0;
+        } else {
+          const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+          d0 = (J[1][1] * f0 - J[0][1] * f1) / det;
+          d1 = (-J[1][0] * f0 + J[0][0] * f1) / det;
+        }
+        r[0] -= d0;
+        r[1] -= d1;
+        if (!(std::fabs(r[0]) < 3.0 && std::fabs(r[1]) < 3.0)) break;   // diverging: not this element
+        // reference coordinates are O(1); rounding of the physical residual (coordinates of
+        // size |x| over a Jacobian of the element's half width) limits the last correction
+        if (std::fabs(d0) + std::fabs(d1) < 1e-11) {
+          conv = true;
+          break;
+        }
+      }
+      if (!conv || std::fabs(r[0]) > 1.0 + 1e-10 || std::fabs(r[1]) > 1.0 + 1e-10) continue;
+      r[0] = std::min(1.0, std::max(-1.0, r[0]));
+      r[1] = std::min(1.0, std::max(-1.0, r[1]));
+      lagrange_row(p, x.data(), r[0], Li.data(), nullptr);
+      if (dm == 2) lagrange_row(p, x.data(), r[1], Lj.data(), nullptr);
+      for (int t = 0; t < nh; ++t) {
+        node[(int64_t)k * nh + t] = c.h_eh_nodes[e * nh + t];
+        wout[(int64_t)k * nh + t] = Li[t % n1] * (dm == 2 ? Lj[t / n1] : 1.0);
+      }
+      found = true;
+    }
+    if (!found) {
+      std::snprintf(buf, sizeof buf, "point %d (%g, %g) lies outside the mesh", k, px, py);
+      return buf;
+    }
+  }
   return "";
 }
 

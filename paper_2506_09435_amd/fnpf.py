@@ -63,6 +63,7 @@ SIGNATURES = {
     "fnpf_destroy": (C.c_int, [C.c_void_p]),
     "fnpf_sizes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_node_coords": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fnpf_surface_interp_weights": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_enable_fp32": (C.c_int, [C.c_void_p]),
     "fnpf_set_apply_variant": (C.c_int, [C.c_void_p, C.c_int32]),
     "fnpf_geom": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -133,16 +134,21 @@ def gll(p: int):
     return x, w, D
 
 
-def _ptr(t, dtype=None):
-    import torch
+def _ptr(t, dtype=None, n=None, device=None):
+    """Device address of tensor t after checking what the C ABI cannot: the element count n
+    (the call reads or writes exactly n elements), the dtype, contiguity and the device."""
     if t is None:
         return None
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
     if not t.is_cuda:
         raise ValueError("expected a device tensor")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
-    if dtype is not None and t.dtype != dtype:
-        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if device is not None and t.device != device:
+        raise ValueError(f"expected a tensor on {device}, got one on {t.device}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -182,6 +188,16 @@ class Context:
         self.npt = (mesh.p + 1) ** mesh.dim
         self.device = torch.device("cuda", torch.cuda.current_device())
 
+    def _v(self, t, dtype=None):
+        """Pointer to a volume vector [n_v] on this context's device."""
+        import torch
+        return _ptr(t, torch.float64 if dtype is None else dtype, self.n_v, self.device)
+
+    def _s(self, t):
+        """Pointer to a surface vector [n_s] (FP64) on this context's device."""
+        import torch
+        return _ptr(t, torch.float64, self.n_s, self.device)
+
     def _check(self, st, where):
         if st:
             raise FnpfError(st, f"{where}: {lib().fnpf_last_error(self._h).decode()}")
@@ -203,6 +219,18 @@ class Context:
         self._check(lib().fnpf_node_coords(self._h, xy.ctypes.data), "fnpf_node_coords")
         return xy
 
+    def surface_interp_weights(self, points):
+        """Lagrange interpolation at horizontal points: (node [n, nh] int32, w [n, nh]) with
+        f(point_k) = sum_t w[k, t] f[node[k, t]] (fnpf_surface_interp_weights)."""
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, self.dim - 1))
+        n = pts.shape[0]
+        nh = (self.p + 1) ** (self.dim - 1)
+        node = np.zeros((n, nh), dtype=np.int32)
+        w = np.zeros((n, nh))
+        self._check(lib().fnpf_surface_interp_weights(self._h, n, pts.ctypes.data, node.ctypes.data, w.ctypes.data),
+                    "fnpf_surface_interp_weights")
+        return node, w
+
     def node_xy(self):
         xy = self.node_coords()
         if self.dim == 2:
@@ -219,7 +247,7 @@ class Context:
 
     def geom(self, eta, h, stream=None):
         import torch
-        self._check(lib().fnpf_geom(self._h, _ptr(eta, torch.float64), _ptr(h, torch.float64), _stream(stream)),
+        self._check(lib().fnpf_geom(self._h, self._s(eta), self._s(h), _stream(stream)),
                     "fnpf_geom")
 
     def export_geometry(self, dtype=F64, stream=None):
@@ -227,25 +255,27 @@ class Context:
         tdt = torch.float64 if dtype == F64 else torch.float32
         G = torch.empty((self.n_e, self.ng, self.npt), dtype=tdt, device=self.device)
         diag = torch.empty(self.n_v, dtype=torch.float64, device=self.device)
-        self._check(lib().fnpf_export_geometry(self._h, dtype, _ptr(G), _ptr(diag), _stream(stream)),
-                    "fnpf_export_geometry")
+        self._check(lib().fnpf_export_geometry(self._h, dtype, _ptr(G, tdt, G.numel(), self.device),
+                                               self._v(diag), _stream(stream)), "fnpf_export_geometry")
         return G, diag
 
     def laplace_apply(self, x, y=None, mask_dirichlet=False, stream=None):
         import torch
+        if x.dtype not in (torch.float64, torch.float32):
+            raise TypeError(f"expected float64 or float32, got {x.dtype}")
         dtype = F64 if x.dtype == torch.float64 else F32
         if y is None:
             y = torch.empty_like(x)
-        self._check(lib().fnpf_laplace_apply(self._h, dtype, _ptr(x), _ptr(y, x.dtype), int(mask_dirichlet),
-                                             _stream(stream)), "fnpf_laplace_apply")
+        self._check(lib().fnpf_laplace_apply(self._h, dtype, self._v(x, x.dtype), self._v(y, x.dtype),
+                                             int(mask_dirichlet), _stream(stream)), "fnpf_laplace_apply")
         return y
 
     def neumann_load(self, q, f=None, stream=None):
         import torch
         if f is None:
             f = torch.empty(self.n_v, dtype=torch.float64, device=self.device)
-        self._check(lib().fnpf_neumann_load(self._h, _ptr(q, torch.float64), _ptr(f, torch.float64),
-                                            _stream(stream)), "fnpf_neumann_load")
+        qp = _ptr(q, torch.float64, self.dim * self.n_v, self.device)
+        self._check(lib().fnpf_neumann_load(self._h, qp, self._v(f), _stream(stream)), "fnpf_neumann_load")
         return f
 
     def solve(self, phi_surface, phi=None, neumann_f=None, opts=None, stream=None, raise_on_error=True):
@@ -254,8 +284,8 @@ class Context:
             phi = torch.zeros(self.n_v, dtype=torch.float64, device=self.device)
         info = SolveInfo()
         o = opts if opts is not None else default_opts()
-        st = lib().fnpf_solve(self._h, _ptr(phi_surface, torch.float64), _ptr(neumann_f, torch.float64),
-                              _ptr(phi, torch.float64), C.byref(o), C.byref(info), _stream(stream))
+        st = lib().fnpf_solve(self._h, self._s(phi_surface), self._v(neumann_f),
+                              self._v(phi), C.byref(o), C.byref(info), _stream(stream))
         if raise_on_error:
             self._check(st, "fnpf_solve")
         return phi, info.as_dict() | dict(status=STATUS[st])
@@ -264,7 +294,7 @@ class Context:
         import torch
         if w is None:
             w = torch.empty(self.n_s, dtype=torch.float64, device=self.device)
-        self._check(lib().fnpf_w_surface(self._h, _ptr(phi, torch.float64), _ptr(w, torch.float64),
+        self._check(lib().fnpf_w_surface(self._h, self._v(phi), self._s(w),
                                          _stream(stream)), "fnpf_w_surface")
         return w
 
@@ -272,8 +302,8 @@ class Context:
         import torch
         de = torch.empty(self.n_s, dtype=torch.float64, device=self.device)
         dp = torch.empty_like(de)
-        self._check(lib().fnpf_rhs(self._h, _ptr(eta, torch.float64), _ptr(phi_s, torch.float64),
-                                   _ptr(w, torch.float64), _ptr(de), _ptr(dp), _stream(stream)), "fnpf_rhs")
+        self._check(lib().fnpf_rhs(self._h, self._s(eta), self._s(phi_s),
+                                   self._s(w), self._s(de), self._s(dp), _stream(stream)), "fnpf_rhs")
         return de, dp
 
     def set_linear(self, linear=True):
@@ -308,13 +338,13 @@ class Context:
     def modal_filter(self, f, stream=None):
         import torch
         out = torch.empty(self.n_s, dtype=torch.float64, device=self.device)
-        self._check(lib().fnpf_modal_filter(self._h, _ptr(f, torch.float64), _ptr(out), _stream(stream)),
+        self._check(lib().fnpf_modal_filter(self._h, self._s(f), self._s(out), _stream(stream)),
                     "fnpf_modal_filter")
         return out
 
     def modal_filter_vjp(self, out_bar, f_bar, stream=None):
         import torch
-        self._check(lib().fnpf_modal_filter_vjp(self._h, _ptr(out_bar, torch.float64), _ptr(f_bar, torch.float64),
+        self._check(lib().fnpf_modal_filter_vjp(self._h, self._s(out_bar), self._s(f_bar),
                                                 _stream(stream)), "fnpf_modal_filter_vjp")
         return f_bar
 
@@ -334,9 +364,9 @@ class Context:
         import torch
         infos = (SolveInfo * 4)()
         o = opts if opts is not None else default_opts()
-        st = lib().fnpf_rk4_step(self._h, _ptr(eta, torch.float64), _ptr(phi_s, torch.float64),
-                                 _ptr(h, torch.float64), float(t), float(dt), C.byref(o),
-                                 _ptr(tape, torch.float64), infos, _stream(stream))
+        st = lib().fnpf_rk4_step(self._h, self._s(eta), self._s(phi_s),
+                                 self._s(h), float(t), float(dt), C.byref(o),
+                                 _ptr(tape, torch.float64, 4 * self.tape_record, self.device), infos, _stream(stream))
         self._check(st, "fnpf_rk4_step")
         return [infos[k].as_dict() for k in range(4)]
 
@@ -353,15 +383,15 @@ class Context:
     def rhs_vjp(self, eta, phi_s, w, deta_bar, dphi_bar, eta_bar, phis_bar, w_bar, stream=None):
         import torch
         f = torch.float64
-        self._check(lib().fnpf_rhs_vjp(self._h, _ptr(eta, f), _ptr(phi_s, f), _ptr(w, f), _ptr(deta_bar, f),
-                                       _ptr(dphi_bar, f), _ptr(eta_bar, f), _ptr(phis_bar, f), _ptr(w_bar, f),
+        self._check(lib().fnpf_rhs_vjp(self._h, self._s(eta), self._s(phi_s), self._s(w), self._s(deta_bar),
+                                       self._s(dphi_bar), self._s(eta_bar), self._s(phis_bar), self._s(w_bar),
                                        _stream(stream)), "fnpf_rhs_vjp")
 
     def w_surface_vjp(self, w, w_bar, phi_bar, eta_bar, h_bar, stream=None):
         import torch
         f = torch.float64
-        self._check(lib().fnpf_w_surface_vjp(self._h, _ptr(w, f), _ptr(w_bar, f), _ptr(phi_bar, f),
-                                             _ptr(eta_bar, f), _ptr(h_bar, f), _stream(stream)),
+        self._check(lib().fnpf_w_surface_vjp(self._h, self._s(w), self._s(w_bar), self._v(phi_bar),
+                                             self._s(eta_bar), self._s(h_bar), _stream(stream)),
                     "fnpf_w_surface_vjp")
 
     def solve_adjoint(self, phi_bar, lam=None, opts=None, stream=None):
@@ -370,14 +400,14 @@ class Context:
             lam = torch.zeros(self.n_v, dtype=torch.float64, device=self.device)
         info = SolveInfo()
         o = opts if opts is not None else default_opts()
-        self._check(lib().fnpf_solve_adjoint(self._h, _ptr(phi_bar, torch.float64), _ptr(lam, torch.float64),
+        self._check(lib().fnpf_solve_adjoint(self._h, self._v(phi_bar), self._v(lam),
                                              C.byref(o), C.byref(info), _stream(stream)), "fnpf_solve_adjoint")
         return lam, info.as_dict()
 
     def geom_vjp(self, lam, phi, eta_bar, h_bar, stream=None):
         import torch
         f = torch.float64
-        self._check(lib().fnpf_geom_vjp(self._h, _ptr(lam, f), _ptr(phi, f), _ptr(eta_bar, f), _ptr(h_bar, f),
+        self._check(lib().fnpf_geom_vjp(self._h, self._v(lam), self._v(phi), self._s(eta_bar), self._s(h_bar),
                                         _stream(stream)), "fnpf_geom_vjp")
 
     def rk4_step_vjp(self, h, t, dt, tape, eta_bar, phis_bar, h_bar, opts=None, stream=None):
@@ -386,20 +416,21 @@ class Context:
         f = torch.float64
         infos = (SolveInfo * 4)()
         o = opts if opts is not None else default_opts()
-        self._check(lib().fnpf_rk4_step_vjp(self._h, _ptr(h, f), float(t), float(dt), _ptr(tape, f),
-                                            _ptr(eta_bar, f), _ptr(phis_bar, f), _ptr(h_bar, f), C.byref(o),
+        self._check(lib().fnpf_rk4_step_vjp(self._h, self._s(h), float(t), float(dt),
+                                            _ptr(tape, f, 4 * self.tape_record, self.device),
+                                            self._s(eta_bar), self._s(phis_bar), self._s(h_bar), C.byref(o),
                                             infos, _stream(stream)), "fnpf_rk4_step_vjp")
         return [infos[k].as_dict() for k in range(4)]
 
     def get_warm_start(self, stream=None):
         import torch
         phi = torch.empty(self.n_v, dtype=torch.float64, device=self.device)
-        self._check(lib().fnpf_get_warm_start(self._h, _ptr(phi), _stream(stream)), "fnpf_get_warm_start")
+        self._check(lib().fnpf_get_warm_start(self._h, self._v(phi), _stream(stream)), "fnpf_get_warm_start")
         return phi
 
     def set_warm_start(self, phi=None, stream=None):
         import torch
-        self._check(lib().fnpf_set_warm_start(self._h, _ptr(phi, torch.float64) if phi is not None else None,
+        self._check(lib().fnpf_set_warm_start(self._h, self._v(phi) if phi is not None else None,
                                               _stream(stream)), "fnpf_set_warm_start")
 
     def sync(self, stream=None):

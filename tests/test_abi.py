@@ -95,3 +95,17 @@ def test_null_context_calls():
     o = fnpf.default_opts()
     assert (o.precision, o.precond, o.rtol, o.check_every, o.cheb_degree, o.extrapolate) == (0, 2, 1e-8, 8, 2, 4)
     assert o.inner_rtol == 1e-6
+
+
+def test_binding_pointer_checks():
+    """The binding is the only guard against undersized or mistyped device arrays (the C ABI takes
+    bare pointers): element count and dtype are checked before anything reaches the library."""
+    torch = pytest.importorskip("torch")
+    t = torch.zeros(5, dtype=torch.float64)
+    with pytest.raises(ValueError, match="expected 6 elements"):
+        fnpf._ptr(t, torch.float64, n=6)
+    with pytest.raises(TypeError):
+        fnpf._ptr(t, torch.float32, n=5)
+    with pytest.raises(ValueError, match="device tensor"):
+        fnpf._ptr(t, torch.float64, n=5)
+    assert fnpf._ptr(None, torch.float64, n=5) is None

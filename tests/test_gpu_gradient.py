@@ -71,7 +71,8 @@ def test_gradient_vs_complex_step_and_fd():
     assert abs(d_adj - d_cs) <= 1e-9 * abs(d_cs)
     # keeping every tape (the default here) or checkpoints every 1 or 3 steps with recomputation
     # gives the same gradient
-    for every in (0, 1, 3):
+    # (every > N: one checkpoint at step 0 and the whole rollout recomputed)
+    for every in (0, 1, 3, N, N + 1, 10 * N):
         c2 = torch.tensor(c0, device="cuda", requires_grad=True)
         e2 = torch.tensor(eta0, device="cuda", requires_grad=True)
         loss(c2, e2, every=every).backward()
@@ -85,3 +86,39 @@ def test_gradient_vs_complex_step_and_fd():
         Jm = float(loss(c.detach() - eps * vct, e0.detach() - eps * vet))
     d_fd = (Jp - Jm) / (2 * eps)
     assert abs(d_adj - d_fd) <= 1e-5 * abs(d_fd)
+
+
+def test_rollout_rejects_negative_checkpoint_interval():
+    wl, m, xc, c0, gauges, obs, rng = _problem()
+    fctx = fnpf.Context(m, g=wl.g)
+    z = torch.zeros(m.n_s, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        rollout(fctx, z, z, z + 1.0, 0.0, wl.dt, 2, checkpoint_every=-1)
+
+
+def test_gauge_weights_match_oracle_and_reproduce_fields():
+    """fnpf_surface_interp_weights against the oracle's gauge matrix on axis-aligned elements
+    (both pinned by polynomial reproduction), and on the curved cylinder mesh: fields linear in
+    x and y lie in the isoparametric space, so interpolation reproduces them at any point."""
+    wl, m, xc, c0, gauges, obs, rng = _problem()
+    fctx = fnpf.Context(m, g=wl.g)
+    pts = np.array(list(gauges) + [[0.0, 0.0], [38.0, 1.0], [19.0, 0.5], [38.0 * 5 / 12, 1.0 / 3]])
+    P = gauge_matrix(fctx, pts).cpu().numpy()
+    Po = ts.gauge_matrix(m, pts)
+    np.testing.assert_allclose(P, Po, rtol=0, atol=1e-14)
+    wl3 = configs.c3(p=3, nz=1)
+    f3 = fnpf.Context(wl3.mesh, g=wl3.g)
+    x, y = f3.node_xy()
+    r = np.random.default_rng(5)
+    ang = r.uniform(0, 2 * np.pi, 40)
+    rad = r.uniform(0.25, 0.9, 40)
+    pts3 = np.concatenate([np.stack([5.0 + rad * np.cos(ang), 2.5 + rad * np.sin(ang)], 1),
+                           np.stack([r.uniform(0, 10, 20), r.uniform(0, 5, 20)], 1),
+                           [[5.25, 2.5], [5.0, 2.75], [0.0, 0.0], [10.0, 5.0]]])     # on the cylinder, corners
+    node, w = f3.surface_interp_weights(pts3)
+    np.testing.assert_allclose(w.sum(1), 1.0, atol=1e-13)
+    for f, want in ((x, pts3[:, 0]), (y, pts3[:, 1]),
+                    (0.3 * x - 1.7 * y + 2.0, 0.3 * pts3[:, 0] - 1.7 * pts3[:, 1] + 2.0)):
+        np.testing.assert_allclose((w * f[node]).sum(1), want, rtol=0, atol=1e-12)
+    with pytest.raises(fnpf.FnpfError):
+        f3.surface_interp_weights([[5.0, 2.5]])          # inside the cylinder: not in the mesh

@@ -414,6 +414,29 @@ def test_error_paths():
         pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precond=3))
     with pytest.raises(fnpf.FnpfError):
         pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precond=2, cheb_degree=0))
+    # the removed measurement schedules (2..5) and unknown variants are rejected
+    for v in (-1, 2, 3, 4, 5, 8):
+        with pytest.raises(fnpf.FnpfError) as ei:
+            pr.ctx.set_apply_variant(v)
+        assert ei.value.name == "ERR_ARG"
+    # the binding checks sizes, dtypes and devices before the library sees a pointer
+    pr.ctx.geom(pr.d_eta, pr.d_h)
+    x = pr.d_h.new_zeros(pr.m.n_v)
+    with pytest.raises(ValueError):
+        pr.ctx.laplace_apply(x[:-1])
+    with pytest.raises(ValueError):
+        pr.ctx.laplace_apply(x, y=x.new_zeros(pr.m.n_v - 1))
+    with pytest.raises(ValueError):
+        pr.ctx.w_surface(x, w=x.new_zeros(pr.m.n_s + 1))
+    with pytest.raises(ValueError):
+        pr.ctx.rk4_step(pr.d_eta.clone(), pr.d_phis.clone(), pr.d_h[:-1], 0.0, 0.01)
+    with pytest.raises(ValueError):
+        pr.ctx.rk4_step(pr.d_eta.clone(), pr.d_phis.clone(), pr.d_h, 0.0, 0.01,
+                        tape=x.new_zeros(4 * pr.ctx.tape_record - 1))
+    with pytest.raises(ValueError):
+        pr.ctx.geom(pr.d_eta.cpu(), pr.d_h)
+    with pytest.raises(TypeError):
+        pr.ctx.laplace_apply(x.half())
 
 
 def test_bitwise_repeatable():

@@ -251,3 +251,39 @@ def test_lpf_linear_and_small_amplitude_limit():
         fn = run(fnpf, amp * e1, amp * p1)
         diffs.append(np.linalg.norm(fn[0] - fl[0]))
     assert 3.6 < diffs[1] / diffs[0] < 4.4
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (2, 5), (3, 2), (3, 4)])
+def test_gauge_matrix_reproduces_polynomials(dim, p):
+    """(P f)_g = f(point_g) for every field of degree <= p per direction (the element space on
+    axis-aligned elements), at interior points, on element edges, at element corners and on the
+    domain boundary; a transposed reference coordinate, a wrong node order or a wrong map to the
+    reference element fails it because the x and y degrees differ."""
+    rng = np.random.default_rng(11)
+    if dim == 2:
+        m = wm.structured_slice(4, 0.5, 3.7, False, p=p, nz=1)
+        xs = np.concatenate([rng.uniform(0.5, 3.7, 6), [0.5, 3.7, 0.5 + 3.2 / 4, 0.5 + 2 * 3.2 / 4]])
+        pts = xs[:, None]
+        coef = rng.standard_normal(p + 1)
+
+        def f(x, y):
+            return sum(coef[a] * x ** a for a in range(p + 1))
+    else:
+        m = wm.structured_box(3, 2, -1.0, 2.0, 0.5, 1.7, False, False, p=p, nz=1)
+        ex, ey = np.linspace(-1.0, 2.0, 4), np.linspace(0.5, 1.7, 3)
+        pts = np.array([[rng.uniform(-1, 2), rng.uniform(0.5, 1.7)] for _ in range(6)]
+                       + [[ex[1], rng.uniform(0.5, 1.7)], [rng.uniform(-1, 2), ey[1]],   # element edges
+                          [ex[1], ey[1]], [ex[2], ey[1]],                                  # interior vertices
+                          [-1.0, 0.5], [2.0, 1.7], [-1.0, rng.uniform(0.5, 1.7)]])         # boundary
+        coef = rng.standard_normal((p + 1, p))
+
+        def f(x, y):
+            return sum(coef[a, b] * x ** a * y ** b for a in range(p + 1) for b in range(p))
+    x, y = geo.node_xy(m)
+    P = ts.gauge_matrix(m, pts)
+    want = np.array([f(pt[0], pt[1] if dim == 3 else 0.0) for pt in pts])
+    np.testing.assert_allclose(P @ f(x, y), want, rtol=0, atol=1e-11 * np.abs(want).max())
+    # each row is a partition of unity over the nodes of one element
+    np.testing.assert_allclose(P.sum(axis=1), 1.0, atol=1e-13)
+    with pytest.raises(ValueError):
+        ts.gauge_matrix(m, [[10.0] + ([0.0] if dim == 3 else [])])

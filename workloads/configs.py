@@ -55,6 +55,17 @@ class Workload:
         return cr, gen * ec, gen * es, gen * pc, gen * ps
 
 
+def parity_start(wl: Workload):
+    """(t0, eta0, phi0) of the full-size two-step parity runs.  C2 starts from its own wave at
+    t = 0; the tanks with relaxation zones (C3, C4) start from their incident linear wave over the
+    whole domain at t = t_ramp, when generation is fully ramped in, so that every stage solves a
+    nonzero problem and both zones act on the state."""
+    if wl.relax_wave is None:
+        return 0.0, wl.eta0, wl.phi0
+    t0, wave = wl.t_ramp, wl.relax_wave
+    return t0, (lambda x, y: wave.eta(x, y, t0)), (lambda x, y: wave.phi(x, y, t0))
+
+
 def c1() -> Workload:
     g = G_STD
     k, h = math.pi, 1.0

@@ -86,6 +86,11 @@ void free_all(Ctx &c) {
   dfree(c.d_ps_slot);
   dfree(c.d_F64);
   dfree(c.d_F32);
+  dfree(c.d_tslot);
+  dfree(c.d_xch);
+  dfree(c.d_tps_node);
+  dfree(c.d_tps_ptr);
+  dfree(c.d_tps_slot);
   dfree(c.d_flags);
   dfree(c.d_face_tag);
   dfree(c.d_hm);
@@ -184,7 +189,7 @@ fnpf_status ensure32(Ctx &c) {
   HIPCHK(dalloc(&c.d_p32, c.n_v));
   HIPCHK(dalloc(&c.d_q32, c.n_v));
   HIPCHK(dalloc(&c.d_d32, c.n_v));
-  HIPCHK(dalloc(&c.d_F32, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(c.n_slots, 1)));
+  HIPCHK(dalloc(&c.d_F32, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(std::max(c.n_slots, c.n_tslots), 1)));
   c.want32 = true;
   c.have_geom32 = false;
   return FNPF_OK;
@@ -694,10 +699,22 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   UP(c.d_cols, cols.data(), cols.size());
   {
     UP(c.d_slot, c.h_slot.data(), c.h_slot.size());
-    UP(c.d_ps_node, c.h_ps_node.data(), std::max<size_t>(c.h_ps_node.size(), 1));
+    if (c.h_ps_node.empty()) c.h_ps_node.push_back(0);   // a mesh without shared nodes: one unused entry
+    if (c.h_ps_slot.empty()) c.h_ps_slot.push_back(0);
+    UP(c.d_ps_node, c.h_ps_node.data(), c.h_ps_node.size());
     UP(c.d_ps_ptr, c.h_ps_ptr.data(), c.h_ps_ptr.size());
-    UP(c.d_ps_slot, c.h_ps_slot.data(), std::max<size_t>(c.h_ps_slot.size(), 1));
-    AL(c.d_F64, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(c.n_slots, 1));
+    UP(c.d_ps_slot, c.h_ps_slot.data(), c.h_ps_slot.size());
+    AL(c.d_F64, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(std::max(c.n_slots, c.n_tslots), 1));
+    if (c.dim == 3) {
+      // the lists may be empty (a mesh within one tile): upload one unused entry then
+      if (c.h_tps_node.empty()) c.h_tps_node.push_back(0);
+      if (c.h_tps_slot.empty()) c.h_tps_slot.push_back(0);
+      UP(c.d_tslot, c.h_tslot.data(), c.h_tslot.size());
+      UP(c.d_xch, c.h_xch.data(), c.h_xch.size());
+      UP(c.d_tps_node, c.h_tps_node.data(), c.h_tps_node.size());
+      UP(c.d_tps_ptr, c.h_tps_ptr.data(), c.h_tps_ptr.size());
+      UP(c.d_tps_slot, c.h_tps_slot.data(), c.h_tps_slot.size());
+    }
   }
   UP(c.d_flags, flags.data(), flags.size());
   UP(c.d_face_tag, tags.data(), tags.size());

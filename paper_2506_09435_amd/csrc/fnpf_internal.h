@@ -19,6 +19,10 @@ constexpr uint8_t kFirst = 1;              // column is the first writer of this
 constexpr uint8_t kLast = 2;               // column is the last writer (sees the final sum)
 constexpr uint8_t kOwned = 4;              // column owns this horizontal node (owner-computes apply)
 constexpr uint8_t kShared = 8;             // the node belongs to more than one column
+// tile assembly of the owner-computes apply (a tile = the columns of one workgroup)
+constexpr uint8_t kTRep = 16;              // the column sums this node's contributions in its tile
+constexpr uint8_t kTOwn = 32;              // ... and its tile owns the node (stores y there)
+constexpr uint8_t kTShared = 64;           // the node also receives face slots of other tiles
 
 // Horizontal metric components stored per (column, local horizontal node).
 // 3D: A = J_h^{-1} (A00, A01, A10, A11), det J_h, J_h (x_xi, x_eta, y_xi, y_eta).
@@ -189,6 +193,20 @@ struct Ctx {
   int64_t n_slots = 0;
   int n_ps = 0;
   int32_t *d_slot = nullptr, *d_ps_node = nullptr, *d_ps_ptr = nullptr, *d_ps_slot = nullptr;
+  // tile assembly of the owner-computes apply: a tile is tile_cols consecutive columns (one
+  // workgroup); contributions of a tile's columns at a node are summed in LDS by the tile's
+  // representative column of the node (exchange entries h_xch: [n_eh][nh][4] int16, the entry this
+  // column writes and up to three its representative reads, -1 none), and only the tile sums of
+  // non-owning tiles (and exchange overflow) go through face slots h_tslot
+  int tile_cols = 0;
+  int tile_xmax = 0;                      // exchange entries per tile (LDS)
+  std::vector<int32_t> h_tslot;           // [n_eh][nh] face slot, -1 none
+  std::vector<int16_t> h_xch;             // [n_eh][nh][4]
+  std::vector<int32_t> h_tps_node, h_tps_ptr, h_tps_slot;  // nodes with face slots, CSR of the slots
+  int64_t n_tslots = 0;
+  int n_tps = 0;
+  int32_t *d_tslot = nullptr, *d_tps_node = nullptr, *d_tps_ptr = nullptr, *d_tps_slot = nullptr;
+  int16_t *d_xch = nullptr;
   double *d_F64 = nullptr;                // [p nz + 1][n_slots]
   float *d_F32 = nullptr;
   double *d_cg64 = nullptr;               // [5|3][n_eh*nh] H, H_xi, h_xi, (H_eta, h_eta) per column node

@@ -562,11 +562,14 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
 //   4  line (i,j): y = sA + sB + zeta part, assembled into global y under the colour schedule
 //
 // OWN = false: colour schedule (cols = the colour's columns, read-add-write of shared nodes).
-// OWN = true: one launch over all columns (cols unused, column = index); a column stores its
-// contributions at the nodes it owns into y and the others into its face slots F[v][slot];
-// k_apply_faces then adds the slots to the owners.  Blocks are mapped so that each XCD (blocks
-// dispatched round-robin over 8) walks a contiguous range of columns, keeping neighbouring
-// columns' shared cache lines in the same L2.
+// OWN = true: one launch over all columns (cols unused, column = index); the CPB columns of a
+// workgroup form a tile.  At a node shared by several columns of the tile, the others pass their
+// values through LDS exchange entries (xch: the entry a column writes, and the up to three its
+// representative reads) to the node's representative column, which stores the tile's sum into y
+// where the tile owns the node and into its face slot F[v][slot] elsewhere (as does a column
+// whose exchange entry did not fit); k_apply_faces then adds the slots to the owners.  Blocks are
+// mapped so that each XCD (blocks dispatched round-robin over 8) walks a contiguous range of
+// tiles, keeping neighbouring tiles' shared cache lines in the same L2.
 template <int P, typename T, bool MASK, bool DOT, bool OWN = false>
 __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T *__restrict__ y,
                                                      const T *__restrict__ cg, const T *__restrict__ hmT,
@@ -578,9 +581,11 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
                                                      double *__restrict__ partial, const int32_t *__restrict__ skip,
                                                      T *__restrict__ F = nullptr,
                                                      const int32_t *__restrict__ slot = nullptr,
-                                                     int64_t n_slots = 0) {
+                                                     int64_t n_slots = 0,
+                                                     const int16_t *__restrict__ xch = nullptr) {
   using S = Sh<P, 3>;
   constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, CPB = S::CPB;
+  constexpr int XM = CPB * NH / 2;   // exchange entries per tile (the host's tile_xmax)
   // sA holds the xi-lines (planes of NH, line stride N1: lane t reads from 7t, conflict-free);
   // sB the eta-lines with the plane stride padded to SB = N1 (mod 64), so that lane t = b N1 + a
   // of the eta-line (i = a, k = b) starts at b SB + a = t (mod 64) and a wave's loads fall in
@@ -590,6 +595,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
   constexpr int NPB = N1 * SB;
   __shared__ T sA[CPB * NP];
   __shared__ T sB[CPB * NPB];
+  __shared__ T sX[OWN ? N1 * XM : 1];
   if (skip != nullptr && *skip) return;
 
   const int lc = threadIdx.x / NH;
@@ -637,11 +643,20 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
   // face slots (OWN): [p nz + 1][n_slots]
   __amdgpu_buffer_rsrc_t rf = ry;
   uint32_t fb = 0, rowf = 0;
+  bool has_slot = false;
+  int xw = -1, xr0 = -1, xr1 = -1, xr2 = -1;
   if constexpr (OWN) {
     rf = vec_rsrc(F, (uint32_t)((int64_t)(P * nz + 1) * n_slots * (int64_t)sizeof(T)));
     const int32_t sl = active ? slot[ho] : -1;
+    has_slot = sl >= 0;
     fb = (uint32_t)(sl < 0 ? 0 : sl) * (uint32_t)sizeof(T);
     rowf = (uint32_t)n_slots * (uint32_t)sizeof(T);
+    if (active) {
+      xw = xch[ho * 4];
+      xr0 = xch[ho * 4 + 1];
+      xr1 = xch[ho * 4 + 2];
+      xr2 = xch[ho * 4 + 3];
+    }
   }
 
   T ucol[N1];
@@ -747,28 +762,54 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
 #pragma unroll
     for (int k = 0; k < N1; ++k) yv[k] = yz[k] + (Ab[k * NH + t] + Bb[k * SB + t]);
     yv[0] += carry;
-    if (active) {
+    carry = yv[P];
+    if constexpr (OWN) {
+      // tile assembly: the tile's other columns at a shared node hand their values (this
+      // layer's stored levels) to the node's representative
+      if (xw >= 0) {
+#pragma unroll
+        for (int k = 0; k < N1; ++k)
+          if (k < kend) sX[k * XM + xw] = yv[k];
+      }
+      __syncthreads();
+      if (active && (fl & kTRep)) {
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+          if (k < kend) {
+            T a = yv[k];
+            if (xr0 >= 0) a += sX[k * XM + xr0];
+            if (xr1 >= 0) a += sX[k * XM + xr1];
+            if (xr2 >= 0) a += sX[k * XM + xr2];
+            yv[k] = a;
+          }
+        }
+      }
+      if (active && ((fl & kTRep) || has_slot)) {
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+          if (k < kend) {
+            const int v = l * P + k;
+            if (fl & kTOwn) {
+              const T val = (MASK && v == vtop) ? T(0) : yv[k];
+              buf_st(val, ry, hb, (uint32_t)v * rowb);
+              if (DOT && !(fl & kTShared)) dot += (double)ucol[k] * (double)val;
+            } else if (!(MASK && v == vtop)) {
+              buf_st(yv[k], rf, fb, (uint32_t)v * rowf);
+            }
+          }
+        }
+      }
+    } else if (active) {
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
         if (k < kend) {
           const int v = l * P + k;
-          if constexpr (OWN) {
-            if (fl & kOwned) {
-              const T val = (MASK && v == vtop) ? T(0) : yv[k];
-              buf_st(val, ry, hb, (uint32_t)v * rowb);
-              if (DOT && !(fl & kShared)) dot += (double)ucol[k] * (double)val;
-            } else if (!(MASK && v == vtop)) {
-              buf_st(yv[k], rf, fb, (uint32_t)v * rowf);
-            }
-          } else {
-            const T val = (MASK && v == vtop) ? T(0) : yv[k] + old[k];
-            buf_st(val, ry, hb, (uint32_t)v * rowb);
-            if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
-          }
+          const T val = (MASK && v == vtop) ? T(0) : yv[k] + old[k];
+          buf_st(val, ry, hb, (uint32_t)v * rowb);
+          if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
         }
       }
     }
-    carry = yv[P];
     ucol[0] = ucol[P];
   }
   if constexpr (DOT) {
@@ -841,12 +882,14 @@ __global__ __launch_bounds__(256) void k_apply_faces(const T *__restrict__ x, T 
 bool owner_apply_active(const Ctx &c) {
   if (c.dim != 3 || c.apply_variant != 0 || !c.apply_owner) return false;
   const int64_t lim = int64_t(1) << 32;
-  return c.n_v * 8 < lim && (int64_t)(c.p * c.nz + 1) * c.n_slots * 8 < lim;
+  return c.n_v * 8 < lim && (int64_t)(c.p * c.nz + 1) * std::max(c.n_slots, c.n_tslots) * 8 < lim;
 }
 
-static int face_blocks(const Ctx &c) {
-  return ((c.n_ps + 255) / 256) * ((c.p * c.nz + 1 + kFaceLevels - 1) / kFaceLevels);
+// blocks of a face pass over n nodes with face slots
+static int face_blocks_n(const Ctx &c, int n) {
+  return ((n + 255) / 256) * ((c.p * c.nz + 1 + kFaceLevels - 1) / kFaceLevels);
 }
+static int face_blocks(const Ctx &c) { return face_blocks_n(c, c.n_ps); }
 
 // the face pass alone (k_apply_faces without the dot product): y at the shared nodes += the face
 // slots of the context's F buffer of y's precision
@@ -879,7 +922,7 @@ hipError_t launch_faces(Ctx &c, fnpf_dtype dt, void *y, bool mask, hipStream_t s
 int owner_apply_blocks(const Ctx &c) {
   if (c.dim != 3) return 0;
   const int cpb = 256 / c.nh;
-  return (c.n_eh + cpb - 1) / cpb + face_blocks(c);
+  return (c.n_eh + cpb - 1) / cpb + face_blocks_n(c, c.n_tps);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1373,15 +1416,16 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
     if (fused) {
       if constexpr (DIM == 3) {
         if (owner_apply_active(c)) {
+          if (c.tile_cols != S::CPB) return hipErrorInvalidValue;   // host tiles = workgroups
           T *F = nullptr;
           if constexpr (sizeof(T) == 8) F = (T *)c.d_F64; else F = (T *)c.d_F32;
           const int nb1 = (c.n_eh + S::CPB - 1) / S::CPB;
           k_apply_lines<P, T, MASK, DOT, true><<<nb1, S::NT, 0, s>>>(
               x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s,
-              DOT ? partial : nullptr, skip, F, c.d_slot, c.n_slots);
-          if (c.n_ps > 0)
-            k_apply_faces<T, MASK, DOT><<<face_blocks(c), 256, 0, s>>>(
-                x, y, F, c.d_ps_node, c.d_ps_ptr, c.d_ps_slot, c.n_ps, c.p * c.nz + 1, c.n_s, c.n_slots,
+              DOT ? partial : nullptr, skip, F, c.d_tslot, c.n_tslots, c.d_xch);
+          if (c.n_tps > 0)
+            k_apply_faces<T, MASK, DOT><<<face_blocks_n(c, c.n_tps), 256, 0, s>>>(
+                x, y, F, c.d_tps_node, c.d_tps_ptr, c.d_tps_slot, c.n_tps, c.p * c.nz + 1, c.n_s, c.n_tslots,
                 DOT ? partial + nb1 : nullptr, skip);
           return hipGetLastError();
         }

@@ -402,6 +402,77 @@ std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double>
       c.h_ps_ptr.push_back((int32_t)c.h_ps_slot.size());
     }
     c.n_ps = (int)c.h_ps_node.size();
+
+    // Tile assembly of the 3D owner-computes apply.  A tile is the tile_cols consecutive columns
+    // of one workgroup; a node belongs to the tile of its owner column.  In each tile, the first
+    // of the tile's columns that has a node is its representative: up to three other columns of
+    // the tile pass their contributions through LDS exchange entries (at most tile_xmax per
+    // tile), further ones get face slots of their own.  A representative stores y where its tile
+    // owns the node and writes the tile's sum to a face slot elsewhere; the face pass adds the
+    // slots of a node (in increasing slot order) to the owner's value.
+    if (dim == 3) {
+      const int tc = 256 / nh;
+      c.tile_cols = tc;
+      c.tile_xmax = tc * nh / 2;
+      c.h_tslot.assign(n_eh * nh, -1);
+      c.h_xch.assign(n_eh * nh * 4, (int16_t)-1);
+      std::vector<std::vector<int32_t>> node_slots;        // per node with slots: its slots
+      std::vector<int32_t> slot_of_node(n_s, -1);          // index into node_slots
+      int64_t nts = 0;
+      auto add_slot = [&](int32_t id) {
+        if (slot_of_node[id] < 0) {
+          slot_of_node[id] = (int32_t)node_slots.size();
+          node_slots.emplace_back();
+        }
+        node_slots[slot_of_node[id]].push_back((int32_t)nts);
+        return (int32_t)nts++;
+      };
+      std::vector<int64_t> rep(n_s, -1);                  // (column, local node) of the representative
+      std::vector<int> nxr(n_s, 0);                        // exchange entries read by the representative
+      for (int64_t t0 = 0; t0 < n_eh; t0 += tc) {
+        const int64_t t1 = std::min<int64_t>(t0 + tc, n_eh);
+        int xcount = 0;
+        for (int64_t e = t0; e < t1; ++e)
+          for (int t = 0; t < nh; ++t) {
+            const int64_t o = e * nh + t;
+            const int32_t id = m.eh_nodes[o];
+            if (rep[id] < 0 || rep[id] / nh < t0) {        // first column of this tile with the node
+              rep[id] = o;
+              nxr[id] = 0;
+              flags[o] |= kTRep;
+              if (owner[id] / tc == t0 / tc)
+                flags[o] |= kTOwn;
+              else
+                c.h_tslot[o] = add_slot(id);
+              continue;
+            }
+            const int64_t r = rep[id];
+            if (nxr[id] < 3 && xcount < c.tile_xmax) {
+              c.h_xch[o * 4] = (int16_t)xcount;
+              c.h_xch[r * 4 + 1 + nxr[id]] = (int16_t)xcount;
+              ++nxr[id];
+              ++xcount;
+            } else {
+              c.h_tslot[o] = add_slot(id);                // exchange full: a face slot of its own
+            }
+          }
+      }
+      if (nts >= INT32_MAX) return "too many face slots for the tile assembly";
+      c.n_tslots = nts;
+      c.h_tps_node.clear();
+      c.h_tps_slot.clear();
+      c.h_tps_ptr.assign(1, 0);
+      for (int64_t n = 0; n < n_s; ++n) {
+        if (slot_of_node[n] < 0) continue;
+        c.h_tps_node.push_back((int32_t)n);
+        for (int32_t sl : node_slots[slot_of_node[n]]) c.h_tps_slot.push_back(sl);
+        c.h_tps_ptr.push_back((int32_t)c.h_tps_slot.size());
+      }
+      c.n_tps = (int)c.h_tps_node.size();
+      // the owner tile's representative takes the dot product of nodes without face slots
+      for (int64_t o = 0; o < n_eh * nh; ++o)
+        if ((flags[o] & kTOwn) && slot_of_node[m.eh_nodes[o]] >= 0) flags[o] |= kTShared;
+    }
   }
   return "";
 }

@@ -38,12 +38,15 @@ def _case(name):
         wl = configs.small_slice(nx=4, nz=2, p=p, periodic=True)
     elif kind == "box":
         wl = configs.small_box(nx=3, ny=3, nz=2 if p < 7 else 1, p=p, periodic=(True, False))
+    elif kind == "column":
+        # a single walled column: no node is shared, so no face slots and no exchange at all
+        wl = configs.small_box(nx=1, ny=1, nz=3, p=p, periodic=(False, False))
     else:
         raise KeyError(name)
     return wl
 
 
-CASES = ["slice_p1", "slice_p8", "box_p1", "box_p2", "box_p7", "box_p8"]
+CASES = ["slice_p1", "slice_p8", "box_p1", "box_p2", "box_p7", "box_p8", "column_p4"]
 
 
 def _setup(name):

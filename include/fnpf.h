@@ -251,6 +251,20 @@ fnpf_status fnpf_export_geometry(fnpf_ctx ctx, fnpf_dtype dtype, void *G, double
 fnpf_status fnpf_laplace_apply(fnpf_ctx ctx, fnpf_dtype dtype, const void *x, void *y, int32_t mask_dirichlet,
                                void *stream);
 
+/* Allocation-free variant of fnpf_laplace_apply, for callers that cannot allocate device memory
+ * during the call: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, operator and result as fnpf_laplace_apply (bitwise identical).
+ * The owner-computes schedule's face slots, which fnpf_laplace_apply keeps in the context,
+ * live here in one library-wide device array of 128 MiB per GPU (allocated when the library's
+ * device code is loaded, held until the process ends); the call allocates nothing.  Every call
+ * on a GPU uses that GPU's one array: calls that overlap on a GPU (other streams, other
+ * contexts, other host threads) race and must be serialised by the caller.  The slots are
+ * written before they are read within each call, so nothing carries over between calls.
+ * Errors: ARG when the face slots, (p nz + 1) * n_tile_slots elements of the dtype, exceed the
+ * array (then use fnpf_laplace_apply); as fnpf_laplace_apply otherwise. */
+fnpf_status fnpf_laplace_apply_noalloc(fnpf_ctx ctx, fnpf_dtype dtype, const void *x, void *y,
+                                       int32_t mask_dirichlet, void *stream);
+
 /* Eq. 1 boundary data: f_i = sum over the bottom and the wall/body faces of
  * int (q . n) l_i dS for a nodal flux field q[dim][n_v] (device, FP64,
  * physical components x, (y,) z), with the current geometry.  f[n_v] device. */

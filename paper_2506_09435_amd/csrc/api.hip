@@ -679,6 +679,8 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
   if (c.device >= 0 && c.device < 64 && !uploaded[c.device]) {
     he = upload_constants(c.device);
     if (he != hipSuccess) return bad(he);
+    he = init_noalloc_scratch(c.device);
+    if (he != hipSuccess) return bad(he);
     uploaded[c.device] = true;
   }
   const int nsides = 2 * (c.dim - 1);
@@ -869,6 +871,32 @@ fnpf_status fnpf_laplace_apply(fnpf_ctx ctx, fnpf_dtype dtype, const void *x, vo
   if (dtype == FNPF_F32 && !c.have_geom32)
     return fail(&c, FNPF_ERR_STATE, "no FP32 factors: call fnpf_enable_fp32, then fnpf_geom");
   HIPCHK(launch_apply(c, dtype, x, y, mask != 0, nullptr, nullptr, (hipStream_t)stream));
+  return FNPF_OK;
+}
+
+fnpf_status fnpf_laplace_apply_noalloc(fnpf_ctx ctx, fnpf_dtype dtype, const void *x, void *y, int32_t mask,
+                                       void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!x || !y) return fail(&c, FNPF_ERR_ARG, "fnpf_laplace_apply_noalloc: x and y must be device pointers");
+  if (x == y) return fail(&c, FNPF_ERR_ARG, "fnpf_laplace_apply_noalloc: x and y must not alias");
+  if (dtype != FNPF_F64 && dtype != FNPF_F32) return fail(&c, FNPF_ERR_ARG, "bad dtype");
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_laplace_apply_noalloc before fnpf_geom");
+  if (dtype == FNPF_F32 && !c.have_geom32)
+    return fail(&c, FNPF_ERR_STATE, "no FP32 factors: call fnpf_enable_fp32, then fnpf_geom");
+  // only the owner-computes schedule uses face slots; the others need no scratch
+  const size_t word = dtype == FNPF_F64 ? sizeof(double) : sizeof(float);
+  const size_t need = owner_apply_active(c) ? (size_t)(c.p * c.nz + 1) * (size_t)c.n_tslots * word : 0;
+  if (need > noalloc_scratch_bytes()) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "fnpf_laplace_apply_noalloc: the face slots need %zu bytes, the scratch holds %zu; use "
+                  "fnpf_laplace_apply", need, noalloc_scratch_bytes());
+    return fail(&c, FNPF_ERR_ARG, buf);
+  }
+  void *scr = noalloc_scratch(c.device);
+  if (scr == nullptr) return fail(&c, FNPF_ERR_STATE, "scratch address unknown on this device");
+  HIPCHK(launch_apply(c, dtype, x, y, mask != 0, nullptr, nullptr, (hipStream_t)stream, scr));
   return FNPF_OK;
 }
 

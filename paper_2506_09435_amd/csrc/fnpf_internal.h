@@ -62,10 +62,16 @@ struct Ctx;
 
 // Kernel launchers (kernels_*.hip). All return hipSuccess or the launch error.
 hipError_t upload_constants(int device);
+// The allocation-free apply's face-slot scratch: a file-scope device array of
+// noalloc_scratch_bytes(); init_noalloc_scratch looks up its address on the current device (once
+// per device, at context creation) and noalloc_scratch returns it (nullptr before).
+hipError_t init_noalloc_scratch(int device);
+void *noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
 hipError_t launch_geom(Ctx &c, const double *eta, const double *h, bool store_G, bool h_is_total,
                        hipStream_t s);
 hipError_t launch_apply(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
-                        const int32_t *skip, hipStream_t s);
+                        const int32_t *skip, hipStream_t s, void *face_scratch = nullptr);
 hipError_t launch_neumann(Ctx &c, const double *q, double *f, hipStream_t s);
 hipError_t launch_wsurf(Ctx &c, const double *phi, double *w, hipStream_t s);
 struct RkStageArgs {

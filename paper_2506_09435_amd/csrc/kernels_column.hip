@@ -41,6 +41,32 @@ constexpr int kEOStride = 2 * kMaxH * kMaxH + 2 * kMaxH;
 __constant__ double c_EO64[(kMaxP + 1) * 2 * kEOStride];
 __constant__ float c_EO32[(kMaxP + 1) * 2 * kEOStride];
 
+// Face-slot scratch of the allocation-free apply (fnpf_laplace_apply_noalloc): a file-scope array
+// in the library's device code, one copy per GPU, allocated when the code object is loaded and
+// held until the process ends.  Host code never passes its name to a kernel (on the host it is a
+// stand-in, not a device address): init_noalloc_scratch stores each device's address of it, taken
+// with hipGetSymbolAddress while that device is current, and the apply takes that address.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+static void *g_scratch_dev[kMaxDevices] = {nullptr};
+
+hipError_t init_noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch_dev[device] != nullptr) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[device] = ptr;
+  return hipSuccess;
+}
+
+void *noalloc_scratch(int device) {
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_dev[device] : nullptr;
+}
+
+size_t noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
+
 hipError_t upload_constants(int /*device*/) {
   static double D64[kMaxN1 * kDStride];
   static float D32[kMaxN1 * kDStride];
@@ -1393,7 +1419,7 @@ hipError_t launch_geom(Ctx &c, const double *eta, const double *h, bool store_G,
 
 template <int P, int DIM, typename T, bool MASK, bool DOT>
 static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *partial, const int32_t *skip,
-                             hipStream_t s) {
+                             hipStream_t s, T *face_scratch) {
   using S = Sh<P, DIM>;
   const int64_t hs = (int64_t)c.n_eh * c.nh;
   const bool fused = c.apply_variant == 0;
@@ -1417,8 +1443,10 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
       if constexpr (DIM == 3) {
         if (owner_apply_active(c)) {
           if (c.tile_cols != S::CPB) return hipErrorInvalidValue;   // host tiles = workgroups
-          T *F = nullptr;
-          if constexpr (sizeof(T) == 8) F = (T *)c.d_F64; else F = (T *)c.d_F32;
+          T *F = face_scratch;
+          if (F == nullptr) {
+            if constexpr (sizeof(T) == 8) F = (T *)c.d_F64; else F = (T *)c.d_F32;
+          }
           const int nb1 = (c.n_eh + S::CPB - 1) / S::CPB;
           k_apply_lines<P, T, MASK, DOT, true><<<nb1, S::NT, 0, s>>>(
               x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s,
@@ -1451,32 +1479,36 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
 
 template <int P, int DIM>
 static hipError_t apply_dispatch(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
-                                 const int32_t *skip, hipStream_t s) {
+                                 const int32_t *skip, hipStream_t s, void *fs) {
   const bool dot = partial != nullptr;
   if (dt == FNPF_F64) {
     const double *xx = (const double *)x;
     double *yy = (double *)y;
-    if (!mask) return apply_impl<P, DIM, double, false, false>(c, xx, yy, c.d_G64, nullptr, skip, s);
-    if (!dot) return apply_impl<P, DIM, double, true, false>(c, xx, yy, c.d_G64, nullptr, skip, s);
-    return apply_impl<P, DIM, double, true, true>(c, xx, yy, c.d_G64, partial, skip, s);
+    double *F = (double *)fs;
+    if (!mask) return apply_impl<P, DIM, double, false, false>(c, xx, yy, c.d_G64, nullptr, skip, s, F);
+    if (!dot) return apply_impl<P, DIM, double, true, false>(c, xx, yy, c.d_G64, nullptr, skip, s, F);
+    return apply_impl<P, DIM, double, true, true>(c, xx, yy, c.d_G64, partial, skip, s, F);
   }
   const float *xx = (const float *)x;
   float *yy = (float *)y;
-  if (!mask) return apply_impl<P, DIM, float, false, false>(c, xx, yy, c.d_G32, nullptr, skip, s);
-  if (!dot) return apply_impl<P, DIM, float, true, false>(c, xx, yy, c.d_G32, nullptr, skip, s);
-  return apply_impl<P, DIM, float, true, true>(c, xx, yy, c.d_G32, partial, skip, s);
+  float *F = (float *)fs;
+  if (!mask) return apply_impl<P, DIM, float, false, false>(c, xx, yy, c.d_G32, nullptr, skip, s, F);
+  if (!dot) return apply_impl<P, DIM, float, true, false>(c, xx, yy, c.d_G32, nullptr, skip, s, F);
+  return apply_impl<P, DIM, float, true, true>(c, xx, yy, c.d_G32, partial, skip, s, F);
 }
 
+// face_scratch: device memory for the face slots in place of the context's own (nullptr: the
+// context's); it must hold (p nz + 1) * n_tslots elements of the apply's precision
 hipError_t launch_apply(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
-                        const int32_t *skip, hipStream_t s) {
+                        const int32_t *skip, hipStream_t s, void *face_scratch) {
   // one partial per block of every launch when the dot product is fused
   if (partial != nullptr &&
       !partials_fit(c.n_partial, owner_apply_active(c) ? owner_apply_blocks(c) : c.max_colour_blocks, 1))
     return hipErrorInvalidValue;
   if (c.dim == 3) {
-    FNPF_DISPATCH(3, c.p, return (apply_dispatch<P_, 3>(c, dt, x, y, mask, partial, skip, s)));
+    FNPF_DISPATCH(3, c.p, return (apply_dispatch<P_, 3>(c, dt, x, y, mask, partial, skip, s, face_scratch)));
   } else {
-    FNPF_DISPATCH(2, c.p, return (apply_dispatch<P_, 2>(c, dt, x, y, mask, partial, skip, s)));
+    FNPF_DISPATCH(2, c.p, return (apply_dispatch<P_, 2>(c, dt, x, y, mask, partial, skip, s, face_scratch)));
   }
   return hipSuccess;
 }

@@ -151,8 +151,9 @@ def accuracy_leg(rtols=(1e-8, 1e-9, 1e-10), names=("C2", "C3", "C4"), bar=1e-8):
     return dict(errors=errs, bar=bar, rtol=max(ok) if ok else None, steps=2, workloads=list(names))
 
 
-def cpu_baseline(wl, target_s=10.0):
-    """Oracle apply (numpy, FP64) on a bounded sample of columns of the same mesh."""
+def cpu_baseline(wl, target_s=10.0, c2_step=False):
+    """Oracle apply (numpy, FP64) on a bounded sample of columns of the same mesh (all host threads
+    and one thread), and the oracle's ERK4 step time on C1 (and C2 when asked)."""
     import numpy as np
     from oracle import geometry as geo
     from oracle import operator as op
@@ -182,26 +183,50 @@ def cpu_baseline(wl, target_s=10.0):
     dofs = geo.dof_map(m, cols=cols)
     rng = np.random.default_rng(0)
     xv = rng.standard_normal(m.n_v)
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        op.apply(m, G, xv, dofs)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or reps >= 200:
-            break
     dof_per_col = m.n_v / m.n_eh
-    gdofs = ncol * dof_per_col * reps / el / 1e9
-    threads = None
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
-    except Exception:
-        pass
+
+    def timed(limit_s):
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            op.apply(m, G, xv, dofs)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= limit_s or reps >= 200:
+                return ncol * dof_per_col * reps / el / 1e9, reps, el
+
+    from threadpoolctl import threadpool_info, threadpool_limits
+    gdofs, reps, el = timed(target_s)
+    threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
     cores = threads or len(os.sched_getaffinity(0))
-    return dict(value=gdofs, unit="GDOF/s", cores=int(cores), kind="oracle",
-                sample=f"numpy R2 apply over {ncol} of {m.n_eh} columns ({ncol * m.nz} elements), "
-                       f"{reps} reps in {el:.1f} s; DoF counted as columns x n_v/n_eh")
+    with threadpool_limits(limits=1):
+        gdofs1, reps1, el1 = timed(target_s / 2)
+    out = dict(value=gdofs, unit="GDOF/s", cores=int(cores), kind="oracle",
+               sample=f"numpy R2 apply over {ncol} of {m.n_eh} columns ({ncol * m.nz} elements), "
+                      f"{reps} reps in {el:.1f} s; DoF counted as columns x n_v/n_eh",
+               one_thread=dict(value=gdofs1, unit="GDOF/s", cores=1, sample=f"same apply, {reps1} reps in {el1:.1f} s"))
+    out["rk4_step"] = oracle_steps(["C1"] + (["C2"] if c2_step else []), cores)
+    return out
+
+
+def oracle_steps(names, cores):
+    """Wall time of the oracle's ERK4 step (Sec. 3.2; Steps 4.1-4.7 per stage) on the host:
+    C1 over its 32 steps (dense direct solves), C2 over one step (Jacobi-PCG, rtol 1e-8)."""
+    from oracle import timestep as ts
+    from workloads import configs
+    res = {}
+    for nm in names:
+        wl = configs.ALL[nm]()
+        nsteps = 32 if nm == "C1" else 1
+        md = ts.Model(wl, solver="dense" if nm == "C1" else "cg", rtol=1e-8)
+        eta, phi = md.initial_state()
+        t0 = time.perf_counter()
+        md.run(nsteps=nsteps, eta=eta, phi_s=phi)
+        el = time.perf_counter() - t0
+        res[nm] = dict(s_per_step=el / nsteps, steps=nsteps, cores=int(cores),
+                       solver="dense direct solve" if nm == "C1" else "Jacobi-PCG rtol 1e-8",
+                       iters_per_stage=None if nm == "C1" else md.last_iters)
+    return res
 
 
 def adjoint_leg(nsteps, rtol, fd_dirs, precond=1, adj_precond=None):
@@ -411,6 +436,8 @@ def main():
                     help="solver rtol of the timed steps; 'auto': the loosest of 1e-8, 1e-9, 1e-10 at which "
                          "two full-size C2/C3/C4 steps of both paths are within 1e-8 of the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-c2", action="store_true",
+                    help="also time one oracle ERK4 step of C2 (minutes on the host)")
     ap.add_argument("--no-fp64-steps", action="store_true")
     ap.add_argument("--no-jacobi-steps", action="store_true",
                     help="skip the reference mixed steps with the Jacobi preconditioner")
@@ -536,7 +563,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl)
+        cpu = cpu_baseline(wl, c2_step=args.cpu_baseline_c2)
         print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
 
     bytes64 = apply_bytes_fused(m.n_v, m.n_eh, m.nh, 8, m.dim)

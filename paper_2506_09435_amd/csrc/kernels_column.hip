@@ -955,7 +955,14 @@ int owner_apply_blocks(const Ctx &c) {
 // Geometry (paper Sec. 3.1.2, Step 4.1): z = -h + sigma_v (eta + h) per node level; per point
 // G = w det(J) J^-1 J^-T with J = [[J_h, 0], [z_xi, z_eta, z_zeta]]; assembled Jacobi diagonal.
 // ---------------------------------------------------------------------------------------------
-template <int P, int DIM>
+//
+// OWN = false: colour schedule over the columns of one colour (cols), the diagonal assembled by
+// read-add-write.  OWN = true (3D): one launch over all columns, the CPB columns of a workgroup a
+// tile as in the owner-computes apply: the tile's columns pass their diagonal contributions at
+// shared nodes to the node's representative through LDS exchange entries (xch), which stores the
+// diagonal (and its inverses where no other tile contributes) or writes its tile's sum to a face
+// slot; k_diag_faces completes the nodes with face slots.
+template <int P, int DIM, bool OWN = false>
 __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, const double *__restrict__ hb,
                                               const double *__restrict__ hm, int64_t hstride,
                                               const int32_t *__restrict__ eh_nodes, const uint8_t *__restrict__ flags,
@@ -965,28 +972,50 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
                                               double *__restrict__ diag, double *__restrict__ dinv,
                                               float *__restrict__ dinv32, double *__restrict__ Hout,
                                               double *__restrict__ hout, double *__restrict__ cg64,
-                                              float *__restrict__ cg32, int h_is_total, int32_t *__restrict__ err) {
+                                              float *__restrict__ cg32, int h_is_total, int32_t *__restrict__ err,
+                                              double *__restrict__ F = nullptr,
+                                              const int32_t *__restrict__ slot = nullptr, int64_t n_slots = 0,
+                                              const int16_t *__restrict__ xch = nullptr) {
   using S = Sh<P, DIM>;
   constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, NG = S::NG, CPB = S::CPB;
+  constexpr int XM = CPB * NH / 2;   // exchange entries per tile (the host's tile_xmax)
+  constexpr int NT = 256;
   __shared__ double sH[CPB * NH];
   __shared__ double sh[CPB * NH];
   __shared__ double s0[CPB * NP];
   __shared__ double s1[DIM == 3 ? CPB * NP : 1];
+  __shared__ double sX[OWN ? N1 * XM : 1];     // partners' values at shared nodes
+  __shared__ double sS[OWN ? N1 * NT : 1];     // a storing column's own values
 
   const int lc = threadIdx.x / NH;
   const int t = threadIdx.x - lc * NH;
   const int i = t % N1, j = t / N1;
-  const int ci = blockIdx.x * CPB + lc;
+  int blk = blockIdx.x;
+  if constexpr (OWN) {
+    const int nb = gridDim.x, q = nb >> 3, r = nb & 7, xc = blk & 7;
+    blk = (xc < r ? xc * (q + 1) : r * (q + 1) + (xc - r) * q) + (blk >> 3);
+  }
+  const int ci = blk * CPB + lc;
   const bool active = ci < ncols;
-  const int col = active ? cols[ci] : 0;
+  const int col = active ? (OWN ? ci : cols[ci]) : 0;
   const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
   const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
   const int64_t ho = (int64_t)col * NH + t;
+  int xw = -1, xr0 = -1, xr1 = -1, xr2 = -1;
+  int32_t sl = -1;
+  if (OWN && active) {
+    xw = xch[ho * 4];
+    xr0 = xch[ho * 4 + 1];
+    xr1 = xch[ho * 4 + 2];
+    xr2 = xch[ho * 4 + 3];
+    sl = slot[ho];
+  }
+  const bool stores = OWN && active && ((fl & kTRep) || sl >= 0);
 
   const double Hn = active ? (h_is_total ? eta[hn] : eta[hn] + hb[hn]) : 1.0;
   const double hnv = active ? hb[hn] : 0.0;
   if (active && !(Hn > 0.0)) *err = 1;
-  if (active && (fl & kFirst)) {
+  if (active && (fl & (OWN ? kOwned : kFirst))) {
     Hout[hn] = Hn;
     hout[hn] = hnv;
   }
@@ -1037,12 +1066,11 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
     detJh = active ? hm[1 * hstride + ho] : 1.0;
   }
   const double wh = DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i);
-  double Dci2[N1], Dcj2[N1];
-#pragma unroll
-  for (int m = 0; m < N1; ++m) {
-    double a = dmat<double>(P, m, i), b = dmat<double>(P, m, j);
-    Dci2[m] = a * a;
-    Dcj2[m] = b * b;
+  // squared derivative entries D[m][c]^2 in LDS (read in the diagonal sums), not in registers
+  __shared__ double sD2[N1 * N1];
+  if (threadIdx.x < N1 * N1) {
+    const double a = dmat<double>(P, threadIdx.x / N1, threadIdx.x % N1);
+    sD2[threadIdx.x] = a * a;
   }
   const double Dii = dmat<double>(P, i, i), Djj = dmat<double>(P, j, j);
 
@@ -1050,6 +1078,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   const int64_t e0 = (int64_t)col * nz;
   for (int l = 0; l < nz; ++l) {
     const double zz = 0.5 * (layer_s[l + 1] - layer_s[l]) * Hn;   // z_zeta (sigma-linear per layer)
+    const double izz = 1.0 / zz;
     double gz[N1];
     double *Ge64 = G64 ? G64 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
     float *Ge32 = G32 ? G32 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
@@ -1061,9 +1090,9 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
       const int q = k * NH + t;
       if constexpr (DIM == 3) {
         const double zy = -hy + sg * Hy;
-        const double b2x = -(zx * A00 + zy * A10) / zz;
-        const double b2y = -(zx * A01 + zy * A11) / zz;
-        const double b2z = 1.0 / zz;
+        const double b2x = -(zx * A00 + zy * A10) * izz;
+        const double b2y = -(zx * A01 + zy * A11) * izz;
+        const double b2z = izz;
         const double g00 = f * (A00 * A00 + A01 * A01);
         const double g01 = f * (A00 * A10 + A01 * A11);
         const double g02 = f * (A00 * b2x + A01 * b2y);
@@ -1090,8 +1119,8 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
         s1[lc * NP + q] = g11;
         gz[k] = g22;
       } else {
-        const double b1x = -zx * A00 / zz;
-        const double b1z = 1.0 / zz;
+        const double b1x = -zx * A00 * izz;
+        const double b1z = izz;
         const double g00 = f * A00 * A00;
         const double g01 = f * A00 * b1x;
         const double g11 = f * (b1x * b1x + b1z * b1z);
@@ -1118,7 +1147,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
     for (int k = 0; k < N1; ++k) {
       double d = 0.0;
 #pragma unroll
-      for (int m = 0; m < N1; ++m) d += Dci2[m] * s0[lc * NP + k * NH + j * N1 + m];
+      for (int m = 0; m < N1; ++m) d += sD2[m * N1 + i] * s0[lc * NP + k * NH + j * N1 + m];
 #pragma unroll
       for (int m = 0; m < N1; ++m) {
         const double a = dmat<double>(P, m, k);
@@ -1130,22 +1159,27 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
       const double f = wh * wgt(P, k) * detJh * zz;
       if constexpr (DIM == 3) {
 #pragma unroll
-        for (int m = 0; m < N1; ++m) d += Dcj2[m] * s1[lc * NP + k * NH + m * N1 + i];
+        for (int m = 0; m < N1; ++m) d += sD2[m * N1 + j] * s1[lc * NP + k * NH + m * N1 + i];
         const double zy = -hy + sg * Hy;
-        const double b2x = -(zx * A00 + zy * A10) / zz;
-        const double b2y = -(zx * A01 + zy * A11) / zz;
+        const double b2x = -(zx * A00 + zy * A10) * izz;
+        const double b2y = -(zx * A01 + zy * A11) * izz;
         const double c01 = f * (A00 * A10 + A01 * A11);
         const double c02 = f * (A00 * b2x + A01 * b2y);
         const double c12 = f * (A10 * b2x + A11 * b2y);
         d += 2.0 * (Dii * Djj * c01 + Dii * Dkk * c02 + Djj * Dkk * c12);
       } else {
-        const double b1x = -zx * A00 / zz;
+        const double b1x = -zx * A00 * izz;
         const double c01 = f * A00 * b1x;
         d += 2.0 * Dii * Dkk * c01;
       }
       if (k == 0) d += carry;
       if (k == P && l < nz - 1) {
         top = d;   // the level shared with the next layer, completed there
+      } else if (OWN) {
+        if (xw >= 0)
+          sX[k * XM + xw] = d;
+        else
+          sS[k * NT + threadIdx.x] = d;
       } else if (active) {
         const int v = l * P + k;
         const int64_t idx = (int64_t)v * n_s + hn;
@@ -1159,6 +1193,147 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
     }
     __syncthreads();
     carry = top;
+    if constexpr (OWN) {
+      // representatives add their partners' values and store (the next writes to sX and sS
+      // follow the next layer's first barrier)
+      if (stores) {
+        const int kh = (l == nz - 1) ? N1 : P;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+          if (k < kh) {
+            double a = sS[k * NT + threadIdx.x];
+            if (xr0 >= 0) a += sX[k * XM + xr0];
+            if (xr1 >= 0) a += sX[k * XM + xr1];
+            if (xr2 >= 0) a += sX[k * XM + xr2];
+            const int v = l * P + k;
+            const int64_t idx = (int64_t)v * n_s + hn;
+            if (fl & kTOwn) {
+              diag[idx] = a;
+              if (!(fl & kTShared)) {
+                const double di = (v == P * nz) ? 0.0 : 1.0 / a;
+                dinv[idx] = di;
+                if (dinv32) dinv32[idx] = (float)di;
+              }
+            } else {
+              F[(int64_t)v * n_slots + sl] = a;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Face pass of the owner-computes geometry: diag += the face slots of the other tiles at each node
+// with slots (in increasing slot order), and the inverses there (0 on the top level).
+__global__ __launch_bounds__(256) void k_diag_faces(double *__restrict__ diag, double *__restrict__ dinv,
+                                                    float *__restrict__ dinv32, const double *__restrict__ F,
+                                                    const int32_t *__restrict__ ps_node,
+                                                    const int32_t *__restrict__ ps_ptr,
+                                                    const int32_t *__restrict__ ps_slot, int n_ps, int nlev,
+                                                    int64_t n_s, int64_t n_slots) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n_ps * nlev) return;
+  const int v = (int)(g / n_ps);
+  const int k = (int)(g - (int64_t)v * n_ps);
+  const int64_t n = ps_node[k];
+  const int64_t idx = (int64_t)v * n_s + n;
+  double a = diag[idx];
+  for (int q = ps_ptr[k]; q < ps_ptr[k + 1]; ++q) a += F[(int64_t)v * n_slots + ps_slot[q]];
+  diag[idx] = a;
+  const double di = (v == nlev - 1) ? 0.0 : 1.0 / a;
+  dinv[idx] = di;
+  if (dinv32) dinv32[idx] = (float)di;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Vertical line blocks of A_II (the line smoother of the p-multigrid preconditioner): the entries
+// A[(v, n), (v - d, n)], d = 1..p, coupling the nodes of one vertical node line.  For the node
+// (i, j) of a column and levels k != k' of one element layer (collocated quadrature), only the
+// zeta-zeta term and, at element edges (D_ii or D_jj nonzero), the mixed terms survive:
+//   sum_c D[c][k] D[c][k'] G_zz(c) + D_ii (D[k][k'] G_xz(k) + D[k'][k] G_xz(k'))
+//                                  + D_jj (D[k][k'] G_yz(k) + D[k'][k] G_yz(k')),
+// all at points of the thread's own vertical line.  Row v = l p + k (k = 1..p) takes its
+// sub-diagonals from layer l; row 0 has none.  Colour schedule (read-add-write over the columns
+// of a horizontal node).  Band layout: band[d][v][n] (d = 1..p; d = 0 is left to the factor).
+// ---------------------------------------------------------------------------------------------
+template <int P, int DIM>
+__global__ __launch_bounds__(256) void k_line_band(const double *__restrict__ cg, const double *__restrict__ hm,
+                                                   int64_t hstride, const int32_t *__restrict__ eh_nodes,
+                                                   const uint8_t *__restrict__ flags,
+                                                   const int32_t *__restrict__ cols, int ncols, int nz, int64_t n_s,
+                                                   const double *__restrict__ sigma,
+                                                   const double *__restrict__ layer_s, double *__restrict__ band) {
+  using S = Sh<P, DIM>;
+  constexpr int N1 = S::N1, NH = S::NH, CPB = S::CPB;
+  const int lc = threadIdx.x / NH;
+  const int t = threadIdx.x - lc * NH;
+  const int i = t % N1, j = t / N1;
+  const int ci = blockIdx.x * CPB + lc;
+  if (ci >= ncols) return;
+  const int col = cols[ci];
+  const int hn = eh_nodes[(int64_t)col * NH + t];
+  const uint8_t fl = flags[(int64_t)col * NH + t];
+  const int64_t ho = (int64_t)col * NH + t;
+  const int64_t nlev = (int64_t)P * nz + 1;
+  const double H = cg[0 * hstride + ho], Hx = cg[1 * hstride + ho], hx = cg[2 * hstride + ho];
+  double Hy = 0.0, hy = 0.0, A00, A01 = 0.0, A10 = 0.0, A11 = 0.0, detJh;
+  if constexpr (DIM == 3) {
+    Hy = cg[3 * hstride + ho];
+    hy = cg[4 * hstride + ho];
+    A00 = hm[0 * hstride + ho];
+    A01 = hm[1 * hstride + ho];
+    A10 = hm[2 * hstride + ho];
+    A11 = hm[3 * hstride + ho];
+    detJh = hm[4 * hstride + ho];
+  } else {
+    A00 = hm[0 * hstride + ho];
+    detJh = hm[1 * hstride + ho];
+  }
+  const double wh = DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i);
+  const double Dii = dmat<double>(P, i, i), Djj = DIM == 3 ? dmat<double>(P, j, j) : 0.0;
+  // row 0 (bottom level) has no sub-diagonal entries
+#pragma unroll
+  for (int d = 1; d <= P; ++d) scatter(band, ((int64_t)d * nlev + 0) * n_s + hn, 0.0, fl);
+  for (int l = 0; l < nz; ++l) {
+    const double zz = 0.5 * (layer_s[l + 1] - layer_s[l]) * H;
+    const double izz = 1.0 / zz;
+    double gzz[N1], gxz[N1], gyz[N1];
+#pragma unroll
+    for (int c = 0; c < N1; ++c) {
+      const double sg = sigma[l * P + c];
+      const double zx = -hx + sg * Hx;
+      const double f = wh * wgt(P, c) * detJh * zz;
+      if constexpr (DIM == 3) {
+        const double zy = -hy + sg * Hy;
+        const double b2x = -(zx * A00 + zy * A10) * izz;
+        const double b2y = -(zx * A01 + zy * A11) * izz;
+        gxz[c] = f * (A00 * b2x + A01 * b2y);
+        gyz[c] = f * (A10 * b2x + A11 * b2y);
+        gzz[c] = f * (b2x * b2x + b2y * b2y + izz * izz);
+      } else {
+        const double b1x = -zx * A00 * izz;
+        gxz[c] = f * A00 * b1x;
+        gyz[c] = 0.0;
+        gzz[c] = f * (b1x * b1x + izz * izz);
+      }
+    }
+#pragma unroll
+    for (int k = 1; k <= P; ++k) {
+      const int64_t v = (int64_t)l * P + k;
+#pragma unroll
+      for (int d = 1; d <= P; ++d) {
+        double val = 0.0;
+        if (d <= k) {
+          const int kp = k - d;
+#pragma unroll
+          for (int c = 0; c < N1; ++c) val += dmat<double>(P, c, k) * dmat<double>(P, c, kp) * gzz[c];
+          const double dk = dmat<double>(P, k, kp), dkp = dmat<double>(P, kp, k);
+          val += Dii * (dk * gxz[k] + dkp * gxz[kp]) + Djj * (dk * gyz[k] + dkp * gyz[kp]);
+        }
+        scatter(band, ((int64_t)d * nlev + v) * n_s + hn, val, fl);
+      }
+    }
   }
 }
 
@@ -1396,6 +1571,26 @@ static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, bool sto
                             hipStream_t s) {
   using S = Sh<P, DIM>;
   const int64_t hs = (int64_t)c.n_eh * c.nh;
+  if constexpr (DIM == 3) {
+    // owner-computes with the apply's tiles and face slots (same 32-bit range conditions)
+    const int64_t lim = int64_t(1) << 32;
+    if (c.tile_cols == S::CPB && c.n_v * 8 < lim) {
+      const int nb = (c.n_eh + S::CPB - 1) / S::CPB;
+      k_geom<P, DIM, true><<<nb, S::NT, 0, s>>>(
+          eta, h, c.d_hm, hs, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s, c.d_sigma, c.d_layer_s,
+          store_G ? c.d_G64 : nullptr, (store_G && c.want32) ? c.d_G32 : nullptr, c.d_diag, c.d_dinv,
+          c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh, c.d_cg64, c.want32 ? c.d_cg32 : nullptr,
+          h_is_total ? 1 : 0, c.d_err, c.d_F64, c.d_tslot, c.n_tslots, c.d_xch);
+      if (c.n_tps > 0) {
+        const int nlev = c.p * c.nz + 1;
+        const int64_t work = (int64_t)c.n_tps * nlev;
+        k_diag_faces<<<(int)((work + 255) / 256), 256, 0, s>>>(c.d_diag, c.d_dinv, c.want32 ? c.d_dinv32 : nullptr,
+                                                                c.d_F64, c.d_tps_node, c.d_tps_ptr, c.d_tps_slot,
+                                                                c.n_tps, nlev, c.n_s, c.n_tslots);
+      }
+      return hipGetLastError();
+    }
+  }
   for (const auto &cr : c.colours) {
     if (cr.count == 0) continue;
     const int nb = (cr.count + S::CPB - 1) / S::CPB;
@@ -1509,6 +1704,29 @@ hipError_t launch_apply(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask
     FNPF_DISPATCH(3, c.p, return (apply_dispatch<P_, 3>(c, dt, x, y, mask, partial, skip, s, face_scratch)));
   } else {
     FNPF_DISPATCH(2, c.p, return (apply_dispatch<P_, 2>(c, dt, x, y, mask, partial, skip, s, face_scratch)));
+  }
+  return hipSuccess;
+}
+
+template <int P, int DIM>
+static hipError_t line_band_impl(Ctx &c, double *band, hipStream_t s) {
+  using S = Sh<P, DIM>;
+  const int64_t hs = (int64_t)c.n_eh * c.nh;
+  for (const auto &cr : c.colours) {
+    if (cr.count == 0) continue;
+    const int nb = (cr.count + S::CPB - 1) / S::CPB;
+    k_line_band<P, DIM><<<nb, S::NT, 0, s>>>(c.d_cg64, c.d_hm, hs, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset,
+                                             cr.count, c.nz, c.n_s, c.d_sigma, c.d_layer_s, band);
+  }
+  return hipGetLastError();
+}
+
+// band[d][v][n] (d = 1..p) of the current geometry's vertical line blocks (colour schedule)
+hipError_t launch_line_band(Ctx &c, double *band, hipStream_t s) {
+  if (c.dim == 3) {
+    FNPF_DISPATCH(3, c.p, return (line_band_impl<P_, 3>(c, band, s)));
+  } else {
+    FNPF_DISPATCH(2, c.p, return (line_band_impl<P_, 2>(c, band, s)));
   }
   return hipSuccess;
 }

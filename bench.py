@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -229,7 +230,7 @@ def oracle_steps(names, cores):
     return res
 
 
-def adjoint_leg(nsteps, rtol, fd_dirs, precond=1, adj_precond=None):
+def adjoint_leg(nsteps, rtol, fd_dirs, precond=1, adj_precond=None, line=0):
     """C4 bar: gauge misfit over nsteps ERK4 steps, gradient w.r.t. 64 bathymetry controls and eta0.
 
     Returns the forward and backward (checkpoint recomputation + adjoint) times, their ratio
@@ -261,15 +262,16 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1, adj_precond=None):
     # Jacobi by default: on this 0.55 M-DoF mesh with 9.5:1 elements in plan the multigrid cycle
     # costs more than its iteration savings in the rollout (200 steps: forward 9.2 s with the
     # multigrid preconditioner against 5.7 s, backward 15.3 s against 7.3 s)
-    o = fnpf.default_opts(rtol=rtol, precond=precond, check_every=25 if precond == 1 else 5)
+    o = fnpf.default_opts(rtol=rtol, precond=precond, check_every=25 if precond == 1 else 5, line_smoother=line)
     with torch.no_grad():
         obs = rollout(fctx, eta_in, phi_in, B @ c_true, 0.0, wl.dt, nsteps, opts=o) @ P.T
 
-    oa = o if adj_precond is None else fnpf.default_opts(rtol=rtol, precond=adj_precond,
+    oa = o if adj_precond is None else fnpf.default_opts(rtol=rtol, precond=adj_precond, line_smoother=line,
                                                           check_every=25 if adj_precond == 1 else 5)
 
-    def loss(c, e0, opts):
-        traj = rollout(fctx, e0, phi_in, B @ c, 0.0, wl.dt, nsteps, opts=opts, adj_opts=oa if opts is o else None)
+    def loss(c, e0, opts, every=None):
+        traj = rollout(fctx, e0, phi_in, B @ c, 0.0, wl.dt, nsteps, opts=opts, adj_opts=oa if opts is o else None,
+                       checkpoint_every=every)
         return 0.5 * ((traj @ P.T - obs) ** 2).sum()
 
     c = torch.tensor(c0, device="cuda", requires_grad=True)
@@ -290,12 +292,29 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1, adj_precond=None):
     J.backward()
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
+    # the same gradient with sqrt(N) step checkpoints: the backward recomputes every segment
+    every = max(1, int(math.ceil(math.sqrt(nsteps))))
+    c2 = torch.tensor(c0, device="cuda", requires_grad=True)
+    e2 = eta_in.clone().requires_grad_(True)
+    fctx.set_warm_start(None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J2 = loss(c2, e2, o, every=every)
+    torch.cuda.synchronize()
+    t_fwd_ckpt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J2.backward()
+    torch.cuda.synchronize()
+    t_bwd_ckpt = time.perf_counter() - t0
+    ckpt_agree = float(torch.linalg.norm(c2.grad - c.grad) / torch.linalg.norm(c.grad))
     out = dict(workload=f"C4 bar 64x16x4 p=5 (n_v={m.n_v}), {nsteps} steps, 8 gauges, 64 controls + eta0, "
                         f"FP64 forward and adjoint",
                rtol=rtol, preconditioner={1: "Jacobi", 2: "p-multigrid"}.get(precond, "none"),
                adjoint_preconditioner={1: "Jacobi", 2: "p-multigrid"}.get(
                    precond if adj_precond is None else adj_precond, "none"),
                t_forward_s=t_fwd, t_forward_taped_s=t_fwd_taped, t_backward_s=t_bwd, ratio=t_bwd / t_fwd,
+               checkpoint_every=every, t_forward_checkpointed_s=t_fwd_ckpt, t_backward_checkpointed_s=t_bwd_ckpt,
+               ratio_checkpointed=t_bwd_ckpt / t_fwd, gradient_rel_diff_checkpointed_vs_taped=ckpt_agree,
                grad_norm_c=float(c.grad.norm()), loss=float(J.detach()))
     if fd_dirs > 0:
         o12 = fnpf.default_opts(rtol=1e-12, check_every=25)
@@ -446,6 +465,9 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="apply variant (fnpf_set_apply_variant)")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="C4 steps of the adjoint leg (0: skip)")
     ap.add_argument("--adjoint-fd", type=int, default=0, help="finite-difference directions checked in the adjoint leg")
+    ap.add_argument("--adjoint-precond", type=int, default=1, help="preconditioner of the adjoint leg (1 Jacobi, 2 p-multigrid)")
+    ap.add_argument("--adjoint-line", type=int, default=0, help="vertical line smoothing in the adjoint leg's multigrid")
+    ap.add_argument("--line-smoother", type=int, default=0, help="vertical line smoothing in the C5 steps' multigrid")
     ap.add_argument("--apply-sweep", action="store_true",
                     help="only the apply throughput for p = 1..6 at 40-50 M DoF (one JSON line)")
     ap.add_argument("--no-extensions", action="store_true",
@@ -516,8 +538,9 @@ def main():
         args.rtol = float(args.rtol)
 
     # -- ERK4 steps --------------------------------------------------------------------
-    o_mixed = fnpf.default_opts(precision=1, rtol=args.rtol, inner_rtol=1e-6, check_every=5, max_outer=30)
-    o_f64 = fnpf.default_opts(precision=0, rtol=args.rtol, check_every=5)
+    o_mixed = fnpf.default_opts(precision=1, rtol=args.rtol, inner_rtol=1e-6, check_every=5, max_outer=30,
+                                line_smoother=args.line_smoother)
+    o_f64 = fnpf.default_opts(precision=0, rtol=args.rtol, check_every=5, line_smoother=args.line_smoother)
     o_jacobi = fnpf.default_opts(precision=1, precond=1, rtol=args.rtol, inner_rtol=1e-4, check_every=25,
                                  max_outer=30)
     ctx.set_warm_start(None)
@@ -558,7 +581,8 @@ def main():
 
     adj = None
     if args.adjoint_steps > 0:
-        adj = adjoint_leg(args.adjoint_steps, args.rtol, args.adjoint_fd)
+        adj = adjoint_leg(args.adjoint_steps, args.rtol, args.adjoint_fd, precond=args.adjoint_precond,
+                          line=args.adjoint_line)
         print(f"[bench] adjoint leg {adj}", file=sys.stderr, flush=True)
 
     cpu = None
@@ -591,7 +615,8 @@ def main():
         pcg_iters_per_stage=dict(f64=it_f64, mixed=it_mixed, mixed_jacobi=it_jac),
         preconditioner="p-multigrid V-cycle (degrees 6, 3, 1; Chebyshev-Jacobi smoothing, degree 2)",
         extensions=ext,
-        adjoint_forward_ratio=None if adj is None else adj["ratio"],
+        adjoint_forward_ratio=None if adj is None else dict(every_tape=adj["ratio"],
+                                                            sqrt_n_checkpoints=adj["ratio_checkpointed"]),
         adjoint=adj,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                       traffic=traffic,

@@ -147,6 +147,13 @@ typedef struct {
   int32_t use_graph;     /* 1: the check_every iterations between host checks are captured
                             once as a HIP graph and replayed (default); 0: launched one by one.
                             Results are identical. */
+  int32_t line_smoother; /* precond 2: 0 (default) Chebyshev smoothing of D^-1 A (point
+                            Jacobi); 1 of B^-1 A, B the vertical line blocks of A_II (the
+                            unknowns of one vertical node line coupled, banded with half
+                            bandwidth p), factored by Cholesky after every geometry update, for
+                            meshes whose thin layers couple the vertical strongly; every level
+                            uses it and the smoothing intervals come from Lanczos / power
+                            iterations in the B inner product. */
 } fnpf_solve_opts;
 
 typedef struct {
@@ -157,7 +164,8 @@ typedef struct {
 } fnpf_solve_info;
 
 /* Defaults: FP64, p-multigrid (precond 2), rtol 1e-8, atol 0, max_iter 20000,
- * check_every 8, inner_rtol 1e-6, max_outer 30, extrapolate 4, cheb_degree 2, use_graph 1. */
+ * check_every 8, inner_rtol 1e-6, max_outer 30, extrapolate 4, cheb_degree 2, use_graph 1,
+ * line_smoother 0. */
 void fnpf_default_opts(fnpf_solve_opts *opts);
 
 /* Create a context on the current HIP device: validates and copies the mesh,
@@ -264,6 +272,16 @@ fnpf_status fnpf_laplace_apply(fnpf_ctx ctx, fnpf_dtype dtype, const void *x, vo
  * array (then use fnpf_laplace_apply); as fnpf_laplace_apply otherwise. */
 fnpf_status fnpf_laplace_apply_noalloc(fnpf_ctx ctx, fnpf_dtype dtype, const void *x, void *y,
                                        int32_t mask_dirichlet, void *stream);
+
+/* The vertical line smoother's block solve (opts.line_smoother): z = B^-1 r on the unknowns and
+ * z = 0 on the free-surface level, B the vertical line blocks of A_II for the current geometry
+ * (for horizontal node n, the principal submatrix of the Laplace operator on levels
+ * 0 .. p nz - 1 of its node line), through their Cholesky factors, which this call (re)builds.
+ * The smoother stands in for the multigrid the paper's Laplace solves use (Sec. 4, solver
+ * settings).  r, z [n_v] device arrays of dtype (F32: factors rounded from FP64); no aliasing.
+ * Errors: STATE before fnpf_geom (F32: without FP32 data); GEOM if a block is not positive
+ * definite. */
+fnpf_status fnpf_line_smoother_apply(fnpf_ctx ctx, fnpf_dtype dtype, const void *r, void *z, void *stream);
 
 /* Eq. 1 boundary data: f_i = sum over the bottom and the wall/body faces of
  * int (q . n) l_i dS for a nodal flux field q[dim][n_v] (device, FP64,

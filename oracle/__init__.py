@@ -14,7 +14,8 @@ simulations"), citing the section/equation it implements:
 * ``gll``       GLL nodes, weights, derivative matrix (nodal Lagrange P^p, Sec. 3.1)
 * ``geometry``  extruded, surface-following mesh and per-point factors (Sec. 3.1.2)
 * ``operator``  Laplace bilinear form a[phi; nu] (Eq. 4): assembled and matrix-free
-* ``solve``     Dirichlet lift at the free surface, Neumann data, CG solve (Eq. 1, Sec. 4)
+* ``solve``     Dirichlet lift at the free surface, Neumann data, CG solve (Eq. 1, Sec. 4),
+                and the vertical line blocks of A_II with their block solve
 * ``surface``   vertical-velocity recovery (Sec. 3.4 Steps 4.4-4.5) and the
                 Zakharov free-surface right-hand side (Eqs. 2-3, 5)
 * ``timestep``  ERK4 (Sec. 3.2), relaxation zones (Sec. 3.3), mass and energy

@@ -96,3 +96,29 @@ def solve_cg(mesh, G, phi_s, f=None, x0=None, rtol=1e-13, max_iter=100000, dofs=
     if return_info:
         return phi, dict(iters=it, rel_res=float(rn / bnorm) if bnorm else 0.0)
     return phi
+
+
+def line_unknowns(mesh):
+    """Volume indices of every vertical node line's unknowns: [n_s][p nz] (level-major
+    numbering v n_s + n, levels 0 .. p nz - 1; the free-surface level is Dirichlet)."""
+    nl = mesh.p * mesh.nz
+    return np.arange(nl)[None, :] * mesh.n_s + np.arange(mesh.n_s)[:, None]
+
+
+def line_blocks(mesh, A):
+    """The vertical line blocks of A_II: for every horizontal node n, the principal submatrix of
+    the assembled operator on the unknowns of its node line.  They form the block-diagonal part
+    of A_II that a vertical line smoother inverts in place of the Jacobi diagonal (a multilevel
+    preconditioner in the role of the paper's algebraic multigrid, Sec. 4 solver settings)."""
+    idx = line_unknowns(mesh)
+    return np.stack([A[np.ix_(ix, ix)] for ix in idx])
+
+
+def line_solve(mesh, blocks, r):
+    """z = B^-1 r with B the block-diagonal line part of A_II (dense solve per line); z is zero
+    on the free-surface level."""
+    idx = line_unknowns(mesh)
+    z = np.zeros(mesh.n_v, dtype=np.result_type(blocks, r))
+    for n, ix in enumerate(idx):
+        z[ix] = np.linalg.solve(blocks[n], np.asarray(r)[ix])
+    return z

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfnpf.so")
 
-SOURCES = ["setup.cpp", "kernels_column.hip", "kernels_vec.hip", "multigrid.hip", "surface_quad.hip", "api.hip"]
+SOURCES = ["setup.cpp", "kernels_column.hip", "kernels_vec.hip", "multigrid.hip", "line_smoother.hip",
+           "surface_quad.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -132,6 +132,8 @@ void free_all(Ctx &c) {
   dfree(c.d_nd);
   dfree(c.d_partial);
   dfree(c.d_mg_scal);
+  dfree(c.d_lb64);
+  dfree(c.d_lb32);
   dfree(c.d_sc);
   if (c.h_sc) (void)hipHostFree(c.h_sc);
   c.h_sc = nullptr;
@@ -364,6 +366,7 @@ Ctx::GraphKey graph_key(const Ctx &c, const void *x, const fnpf_solve_opts &o, i
   k.variant = c.apply_variant;
   k.lines = c.apply_lines;
   k.owner = c.apply_owner;
+  k.line = c.mg_line;
   k.nb = nb;
   return k;
 }
@@ -377,6 +380,7 @@ fnpf_status pcg64(Ctx &c, const double *f, double *x, const fnpf_solve_opts &o, 
     if (st != FNPF_OK) return st;
   }
   if (mg) {
+    mg_set_line(c, o.line_smoother != 0);
     fnpf_status st = mg_refresh<double>(c, s);
     if (st != FNPF_OK) return fail(&c, st, c.err.empty() ? "p-multigrid setup failed" : c.err);
   }
@@ -433,6 +437,7 @@ fnpf_status pcg_mixed(Ctx &c, const double *f, double *x, const fnpf_solve_opts 
     if (st != FNPF_OK) return st;
   }
   if (mg) {
+    mg_set_line(c, o.line_smoother != 0);
     fnpf_status st = mg_refresh<float>(c, s);
     if (st != FNPF_OK) return fail(&c, st, c.err.empty() ? "p-multigrid setup failed" : c.err);
   }
@@ -503,6 +508,8 @@ fnpf_status validate_opts(Ctx &c, const fnpf_solve_opts &o) {
   if (o.extrapolate < 0 || o.extrapolate >= Ctx::kHistMax)
     return fail(&c, FNPF_ERR_ARG, "opts.extrapolate must be in 0..4");
   if (o.use_graph != 0 && o.use_graph != 1) return fail(&c, FNPF_ERR_ARG, "opts.use_graph must be 0 or 1");
+  if (o.line_smoother != 0 && o.line_smoother != 1)
+    return fail(&c, FNPF_ERR_ARG, "opts.line_smoother must be 0 (point) or 1 (vertical lines)");
   if (o.precision == 1 && (!(o.inner_rtol > 0.0) || !(o.inner_rtol < 1.0) || o.max_outer < 1))
     return fail(&c, FNPF_ERR_ARG, "opts.inner_rtol must be in (0,1) and max_outer >= 1 for the mixed path");
   return FNPF_OK;
@@ -597,6 +604,7 @@ void fnpf_default_opts(fnpf_solve_opts *o) {
   o->extrapolate = 4;
   o->cheb_degree = 2;
   o->use_graph = 1;
+  o->line_smoother = 0;
 }
 
 const char *fnpf_status_string(fnpf_status s) {
@@ -898,6 +906,24 @@ fnpf_status fnpf_laplace_apply_noalloc(fnpf_ctx ctx, fnpf_dtype dtype, const voi
   if (scr == nullptr) return fail(&c, FNPF_ERR_STATE, "scratch address unknown on this device");
   HIPCHK(launch_apply(c, dtype, x, y, mask != 0, nullptr, nullptr, (hipStream_t)stream, scr));
   return FNPF_OK;
+}
+
+fnpf_status fnpf_line_smoother_apply(fnpf_ctx ctx, fnpf_dtype dtype, const void *r, void *z, void *stream) {
+  if (!ctx) return FNPF_ERR_ARG;
+  Ctx &c = ctx->c;
+  if (!r || !z) return fail(&c, FNPF_ERR_ARG, "fnpf_line_smoother_apply: r and z must be device pointers");
+  if (r == z) return fail(&c, FNPF_ERR_ARG, "fnpf_line_smoother_apply: r and z must not alias");
+  if (dtype != FNPF_F64 && dtype != FNPF_F32) return fail(&c, FNPF_ERR_ARG, "bad dtype");
+  if (!c.have_geom) return fail(&c, FNPF_ERR_STATE, "fnpf_line_smoother_apply before fnpf_geom");
+  if (dtype == FNPF_F32 && !c.have_geom32)
+    return fail(&c, FNPF_ERR_STATE, "no FP32 data: call fnpf_enable_fp32, then fnpf_geom");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(line_setup(c, s));
+  if (dtype == FNPF_F64)
+    HIPCHK(line_apply<double>(c, (const double *)r, (double *)z, s));
+  else
+    HIPCHK(line_apply<float>(c, (const float *)r, (float *)z, s));
+  return check_err_flag(c, s);
 }
 
 fnpf_status fnpf_neumann_load(fnpf_ctx ctx, const double *q, double *f, void *stream) {

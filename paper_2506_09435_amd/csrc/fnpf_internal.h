@@ -268,6 +268,10 @@ struct Ctx {
   std::vector<MgLevel> mg;
   bool mg_built = false;
   bool mg_stale64 = true, mg_stale32 = true;   // geometry changed since the last refresh
+  bool mg_line = false;                   // smoothing with the vertical line blocks instead of D
+  // Cholesky factors of this level's vertical line blocks, [p+1][p nz+1][n_s] (line_smoother.hip)
+  double *d_lb64 = nullptr;
+  float *d_lb32 = nullptr;
   double *mg_f64[4] = {nullptr, nullptr, nullptr, nullptr};  // fine-level z, r, d, q
   float *mg_f32[4] = {nullptr, nullptr, nullptr, nullptr};
   double *d_mgc = nullptr;                // Chebyshev coefficient table [precision][level][32]
@@ -280,10 +284,10 @@ struct Ctx {
   struct GraphKey {
     const void *x = nullptr;
     int precond = -1, check_every = 0, cheb = 0, variant = -1, nb = 0;
-    bool lines = false, owner = false;
+    bool lines = false, owner = false, line = false;
     bool operator==(const GraphKey &o) const {
       return x == o.x && precond == o.precond && check_every == o.check_every && cheb == o.cheb &&
-             variant == o.variant && nb == o.nb && lines == o.lines && owner == o.owner;
+             variant == o.variant && nb == o.nb && lines == o.lines && owner == o.owner && line == o.line;
     }
   };
   hipGraph_t g_graph[2] = {nullptr, nullptr};
@@ -344,6 +348,27 @@ Ctx &ctx_of(fnpf_ctx h);
 fnpf_status ctx_ensure32(Ctx &c);
 fnpf_status geom_impl_total(Ctx &c, const double *H, const double *h, hipStream_t s);
 hipError_t launch_faces(Ctx &c, fnpf_dtype dt, void *y, bool mask, hipStream_t s, const int32_t *skip);
+// vertical line smoother (line_smoother.hip): band[d][v][n] of B assembled from the geometry,
+// the level's Cholesky factors (FP64, and FP32 when the level keeps FP32 data), and the smoothing
+// steps with them
+hipError_t launch_line_band(Ctx &c, double *band, hipStream_t s);
+void mg_set_line(Ctx &c, bool line);
+hipError_t line_setup(Ctx &c, hipStream_t s);
+template <typename T>
+hipError_t line_apply(const Ctx &c, const T *w, T *z, hipStream_t s);
+template <typename T>
+hipError_t line_cheb0(const Ctx &c, const T *b, T *r, T *d, T *x, const double *cf, const int32_t *skip,
+                      hipStream_t s);
+template <typename T>
+hipError_t line_cheb1(const Ctx &c, const T *b, T *q, T *r, T *d, T *x, const double *cf, const int32_t *skip,
+                      hipStream_t s);
+template <typename T>
+hipError_t line_chebk(const Ctx &c, T *q, T *r, T *d, T *x, const double *cf, int k, const int32_t *skip,
+                      hipStream_t s);
+template <typename T>
+hipError_t line_lanczos_w(const Ctx &c, T *q, const T *v, T *vp, const double *al, const double *be, hipStream_t s);
+template <typename T>
+hipError_t line_bnorm_partials(const Ctx &c, const T *w, double *partial, int nblocks, hipStream_t s);
 
 // host setup (setup.cpp)
 void gll_host(int p, double *x, double *w, double *D);

@@ -789,9 +789,24 @@ __global__ void k_set_scalar(double *p, double v) {
 // Chebyshev smoothing of A x = b on level L (D^-1 A spectrum estimate lam), m steps.  From zero:
 // x = p(D^-1 A) D^-1 b; otherwise x += p(D^-1 A) D^-1 (b - A x).  On return r = b - A x_{m-1}
 // and d = x_m - x_{m-1}.
+// line: B^-1 (the level's vertical line blocks, line_smoother.hip) in place of D^-1.
 template <typename T>
 hipError_t smooth(Ctx &L, const T *b, T *x, T *r, T *d, T *q, const double *cf, int m, bool from_zero,
-                  const int32_t *skip, hipStream_t s) {
+                  const int32_t *skip, hipStream_t s, bool line = false) {
+  if (line) {
+    hipError_t e = hipSuccess;
+    if (from_zero) {
+      e = line_cheb0<T>(L, b, r, d, x, cf, skip, s);
+    } else {
+      if ((e = launch_apply(L, Prec<T>::dt, x, q, true, nullptr, skip, s)) != hipSuccess) return e;
+      e = line_cheb1<T>(L, b, q, r, d, x, cf, skip, s);
+    }
+    for (int k = 2; k <= m && e == hipSuccess; ++k) {
+      if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
+      e = line_chebk<T>(L, q, r, d, x, cf, k, skip, s);
+    }
+    return e;
+  }
   const T *dinv = Prec<T>::dinv(L);
   const int64_t n = L.n_v;
   if (from_zero) {
@@ -827,13 +842,14 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
   }
   const double *cf = coef_table<T>(c, l);
   const int last = (int)c.mg.size();
-  if (l == last) return smooth<T>(L, b, x, r, d, q, cf, kMgCoarseSteps, true, skip, s);
+  const bool line = c.mg_line;
+  if (l == last) return smooth<T>(L, b, x, r, d, q, cf, kMgCoarseSteps, true, skip, s, line);
   MgLevel &C = c.mg[l];
   T *bc = Prec<T>::lv(C)[0], *xc = Prec<T>::lv(C)[1];
   const int64_t n = L.n_v;
   const T *dinv = Prec<T>::dinv(L);
   hipError_t e = hipSuccess;
-  if (m == 2) {
+  if (m == 2 && !line) {
     if (!(l == 0 && pre_scaled)) k_scale<T><<<kVB<T>, kVecThreads, 0, s>>>(d, b, dinv, cf, n, skip);
     if ((e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s)) != hipSuccess) return e;
     k_pre2<T><<<kVB<T>, kVecThreads, 0, s>>>(x, b, q, dinv, cf, n, skip);
@@ -852,7 +868,7 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
     }
     return hipGetLastError();
   }
-  e = smooth<T>(L, b, x, r, d, q, cf, m, true, skip, s);
+  e = smooth<T>(L, b, x, r, d, q, cf, m, true, skip, s, line);
   if (e != hipSuccess) return e;
   // residual of the smoothed x, r - A d, restricted directly
   e = launch_apply(L, Prec<T>::dt, d, q, true, nullptr, skip, s);
@@ -863,7 +879,7 @@ hipError_t vcycle(Ctx &c, int l, const T *b, T *x, const int32_t *skip, int m, h
   if (e != hipSuccess) return e;
   e = prolong_to<T>(L, *C.c, xc, x, skip, s);
   if (e != hipSuccess) return e;
-  return smooth<T>(L, b, x, r, d, q, cf, m, false, skip, s);
+  return smooth<T>(L, b, x, r, d, q, cf, m, false, skip, s, line);
 }
 
 // Eigenvalues and eigenvectors of a small symmetric matrix a[n][n] (row-major, destroyed) by
@@ -960,20 +976,99 @@ hipError_t lanczos_lambda(Ctx &c, Ctx &L, T *u, T *v, T *vp, T *q, double &lam, 
   return hipGetLastError();
 }
 
+// The same Lanczos recurrence for B^-1 A (B: the level's vertical line blocks), self-adjoint in
+// <u, v>_B = u^T B v = (L^T u).(L^T v): w = B^-1 q - alpha v - beta vp (one line solve), its B-norm
+// from the factor, alpha = v.A v as before.
+template <typename T>
+hipError_t lanczos_lambda_line(Ctx &c, Ctx &L, T *u, T *v, T *vp, T *q, double &lam, hipStream_t s) {
+  const T *dinv = Prec<T>::dinv(L);   // only places the start vector on the unknowns
+  const int64_t n = L.n_v;
+  constexpr int K = kLanczosSteps;
+  double *al = c.d_mg_lz, *be = c.d_mg_lz + K, *nrm = c.d_mg_lz + 2 * K;
+  const double rel = 1e-12;
+  std::vector<double> y(K, 0.0);
+  hipError_t e = hipSuccess;
+  for (int pass = 0; pass < 2; ++pass) {
+    T *a = v, *b = vp;
+    k_lz_start<T><<<kVB<T>, kVecThreads, 0, s>>>(a, b, dinv, n, c.d_partial);
+    if ((e = line_bnorm_partials<T>(L, a, c.d_partial, kVB<T>, s)) != hipSuccess) return e;
+    k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, nrm, 1, nullptr, 0.0);
+    k_lz_scale<T><<<kVB<T>, kVecThreads, 0, s>>>(a, n, nrm);
+    for (int j = 0; j < K; ++j) {
+      if (pass == 1) k_lz_acc<T><<<kVB<T>, kVecThreads, 0, s>>>(u, a, n, y[j], j == 0);
+      if (pass == 1 && j == K - 1) break;
+      if ((e = launch_apply(L, Prec<T>::dt, a, q, true, nullptr, nullptr, s)) != hipSuccess) return e;
+      if (pass == 0) {
+        k_lz_dot<T><<<kVB<T>, kVecThreads, 0, s>>>(a, q, n, c.d_partial);
+        k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, al + j, 0, nullptr, 0.0);
+      }
+      if ((e = line_lanczos_w<T>(L, q, a, b, al + j, j > 0 ? be + j - 1 : nullptr, s)) != hipSuccess) return e;
+      if (pass == 0) {
+        if ((e = line_bnorm_partials<T>(L, b, c.d_partial, kVB<T>, s)) != hipSuccess) return e;
+        k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, be + j, 1, al + j, rel);
+      }
+      k_lz_scale<T><<<kVB<T>, kVecThreads, 0, s>>>(b, n, be + j);
+      std::swap(a, b);
+    }
+    if (pass == 0) {
+      std::vector<double> h(2 * K);
+      if ((e = hipMemcpyAsync(h.data(), c.d_mg_lz, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return e;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      std::vector<double> t((size_t)K * K, 0.0), w, z;
+      for (int j = 0; j < K; ++j) {
+        t[(size_t)j * K + j] = h[j];
+        if (j + 1 < K) t[(size_t)j * K + j + 1] = t[(size_t)(j + 1) * K + j] = h[K + j];
+      }
+      symmetric_eigen(K, t, w, z);
+      int top = 0;
+      for (int k = 1; k < K; ++k)
+        if (w[k] > w[top]) top = k;
+      lam = w[top];
+      for (int j = 0; j < K; ++j) y[j] = z[(size_t)j * K + top];
+    }
+  }
+  return hipGetLastError();
+}
+
+// power-iteration scalars of B^-1 A: pw[0] = (v.Av)/(v.Bv), pw[1] = sqrt(v.Bv) (pw[2], pw[3]: the sums)
+__global__ void k_line_pow_fin(double *pw) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double vbv = pw[3];
+  pw[0] = vbv > 0.0 ? pw[2] / vbv : 0.0;
+  pw[1] = vbv > 0.0 ? sqrt(vbv) : 1.0;
+}
+
 // Largest eigenvalue of D^-1 A on level L, left in *pw on the device: Lanczos the first time
 // (Ritz vector into v), then Rayleigh-quotient power iterations from the previous eigenvector
 // estimate v after each geometry update (no host synchronisation).  w1, w2, q are work vectors.
+// With the line smoother (c.mg_line) the same for B^-1 A.
 template <typename T>
 hipError_t estimate_lambda(Ctx &c, Ctx &L, T *v, T *q, T *w1, T *w2, bool warm, double *pw, hipStream_t s) {
   if (!warm) {
     double lam = 0.0;
-    hipError_t e = lanczos_lambda<T>(c, L, v, w1, w2, q, lam, s);
+    hipError_t e = c.mg_line ? lanczos_lambda_line<T>(c, L, v, w1, w2, q, lam, s)
+                             : lanczos_lambda<T>(c, L, v, w1, w2, q, lam, s);
     if (e != hipSuccess) return e;
     k_set_scalar<<<1, 1, 0, s>>>(pw, lam);
     return hipGetLastError();
   }
   const T *dinv = Prec<T>::dinv(L);
   const int64_t n = L.n_v;
+  if (c.mg_line) {
+    for (int it = 0; it < kPowNext; ++it) {
+      hipError_t e = launch_apply(L, Prec<T>::dt, v, q, true, nullptr, nullptr, s);
+      if (e != hipSuccess) return e;
+      k_lz_dot<T><<<kVB<T>, kVecThreads, 0, s>>>(v, q, n, c.d_partial);
+      k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, pw + 2, 0, nullptr, 0.0);
+      if ((e = line_bnorm_partials<T>(L, v, c.d_partial, kVB<T>, s)) != hipSuccess) return e;
+      k_lz_fin<<<1, kVecThreads, 0, s>>>(c.d_partial, kVB<T>, pw + 3, 0, nullptr, 0.0);
+      k_line_pow_fin<<<1, 1, 0, s>>>(pw);
+      if ((e = line_apply<T>(L, q, v, s)) != hipSuccess) return e;
+      k_lz_scale<T><<<kVB<T>, kVecThreads, 0, s>>>(v, n, pw + 1);
+    }
+    return hipGetLastError();
+  }
   for (int it = 0; it < kPowNext; ++it) {
     hipError_t e = launch_apply(L, Prec<T>::dt, v, q, true, nullptr, nullptr, s);
     if (e != hipSuccess) return e;
@@ -1100,6 +1195,12 @@ fnpf_status mg_refresh(Ctx &c, hipStream_t s) {
     if (st != FNPF_OK) return st;
     F = L.c;
   }
+  if (c.mg_line) {
+    // the vertical line blocks of every level from its current geometry, factored
+    if (line_setup(c, s) != hipSuccess) return FNPF_ERR_HIP;
+    for (auto &L : c.mg)
+      if (line_setup(*L.c, s) != hipSuccess) return FNPF_ERR_HIP;
+  }
   // eigenvalue estimates, warm-started from the previous geometry's eigenvector estimates, and the
   // coefficient table of this precision, all stream-ordered before any later use
   {
@@ -1134,15 +1235,25 @@ template <typename T>
 hipError_t mg_vcycle(Ctx &c, const T *r, T *z, const int32_t *skip, int smooth_deg, hipStream_t s,
                      double *dot_partial, bool *dot_done, bool pre_scaled) {
   if (dot_done) *dot_done = false;
-  return vcycle<T>(c, 0, r, z, skip, smooth_deg, s, dot_partial, dot_done, pre_scaled && smooth_deg == 2 &&
-                                                                               !c.mg.empty());
+  return vcycle<T>(c, 0, r, z, skip, smooth_deg, s, dot_partial, dot_done,
+                   pre_scaled && smooth_deg == 2 && !c.mg.empty() && !c.mg_line);
 }
 template hipError_t mg_vcycle<double>(Ctx &, const double *, double *, const int32_t *, int, hipStream_t, double *,
                                       bool *, bool);
 template hipError_t mg_vcycle<float>(Ctx &, const float *, float *, const int32_t *, int, hipStream_t, double *,
                                      bool *, bool);
 
-static bool mg_prescale(const Ctx &c, int smooth_deg) { return smooth_deg == 2 && !c.mg.empty(); }
+static bool mg_prescale(const Ctx &c, int smooth_deg) { return smooth_deg == 2 && !c.mg.empty() && !c.mg_line; }
+
+// Selects point (Jacobi) or vertical line smoothing; a change re-estimates every level's
+// smoothing interval and rebuilds the line factors at the next refresh.
+void mg_set_line(Ctx &c, bool line) {
+  if (c.mg_line == line) return;
+  c.mg_line = line;
+  c.mg_stale64 = c.mg_stale32 = true;
+  c.mg_ev_ok64 = c.mg_ev_ok32 = false;
+  for (auto &L : c.mg) L.ev_ok64 = L.ev_ok32 = false;
+}
 
 hipError_t launch_mg_update(Ctx &c, fnpf_dtype dt, void *x, void *r, const void *p, const void *q, double *partial,
                             PcgScalars *sc, hipStream_t s, int smooth_deg) {

@@ -41,7 +41,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double),
                 ("max_iter", C.c_int32), ("check_every", C.c_int32), ("inner_rtol", C.c_double),
                 ("max_outer", C.c_int32), ("extrapolate", C.c_int32), ("cheb_degree", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("line_smoother", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -70,6 +70,7 @@ SIGNATURES = {
     "fnpf_export_geometry": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_laplace_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "fnpf_laplace_apply_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "fnpf_line_smoother_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_neumann_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fnpf_w_surface": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -270,6 +271,18 @@ class Context:
         self._check(lib().fnpf_laplace_apply(self._h, dtype, self._v(x, x.dtype), self._v(y, x.dtype),
                                              int(mask_dirichlet), _stream(stream)), "fnpf_laplace_apply")
         return y
+
+    def line_smoother_apply(self, r, z=None, stream=None):
+        """z = B^-1 r with the vertical line blocks of the current geometry (fnpf_line_smoother_apply)."""
+        import torch
+        if r.dtype not in (torch.float64, torch.float32):
+            raise TypeError(f"expected float64 or float32, got {r.dtype}")
+        if z is None:
+            z = torch.empty_like(r)
+        self._check(lib().fnpf_line_smoother_apply(self._h, F64 if r.dtype == torch.float64 else F32,
+                                                   self._v(r, r.dtype), self._v(z, r.dtype), _stream(stream)),
+                    "fnpf_line_smoother_apply")
+        return z
 
     def neumann_load(self, q, f=None, stream=None):
         import torch

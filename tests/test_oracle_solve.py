@@ -115,3 +115,70 @@ def test_w_exact_for_linear_fields_on_curved_mesh():
     Xn = _nodal(m2, eta, h)
     w = sf.w_surface(m2, 2.0 * Xn[:, 1] - 0.5 * Xn[:, 0], eta, h)
     np.testing.assert_allclose(w, 2.0, atol=1e-12)
+
+
+def _line_case(dim, p, nz, seed=3):
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        m = wm.structured_slice(4, 0.0, 2.0, True, p=p, nz=nz)
+    else:
+        m = wm.structured_box(3, 2, 0.0, 1.5, 0.0, 1.0, True, False, p=p, nz=nz)
+    x, y = geo.node_xy(m)
+    eta = 0.05 * np.cos(2.0 * x) + 0.02 * rng.standard_normal(m.n_s)
+    h = 1.0 + 0.1 * np.sin(x + 0.3 * y)
+    G, _, _ = geo.factors(m, eta, h)
+    return m, op.assemble_dense(m, G)
+
+
+@pytest.mark.parametrize("dim,p,nz", [(2, 3, 2), (2, 5, 3), (3, 2, 3), (3, 4, 2)])
+def test_line_blocks_structure(dim, p, nz):
+    """Each vertical line block is SPD and coupled only within element layers (half bandwidth p,
+    nothing between levels of different layers); the blocks' traces add up to tr(A_II)."""
+    m, A = _line_case(dim, p, nz)
+    B = sv.line_blocks(m, A)
+    nl = p * nz
+    assert B.shape == (m.n_s, nl, nl)
+    lev = np.arange(nl)
+    same_layer = np.zeros((nl, nl), dtype=bool)       # both levels in one element layer
+    for l in range(nz):
+        inl = (lev >= l * p) & (lev <= l * p + p)
+        same_layer |= inl[:, None] & inl[None, :]
+    for b in B:
+        np.testing.assert_allclose(b, b.T, atol=1e-14 * np.abs(b).max())
+        assert np.linalg.eigvalsh(b).min() > 0.0
+        assert np.all(b[~same_layer] == 0.0)
+    I = sv.interior_mask(m)
+    assert abs(np.trace(B, axis1=1, axis2=2).sum() - np.trace(A[np.ix_(I, I)])) < 1e-12 * np.trace(A)
+
+
+@pytest.mark.parametrize("dim,p,nz", [(2, 4, 2), (3, 3, 2)])
+def test_line_solve_recovers_a_single_line(dim, p, nz):
+    """For x supported on the unknowns of one vertical line, (A x) on that line is B_n x_n, so the
+    line solve returns x there exactly (up to rounding), whatever the couplings to other lines."""
+    m, A = _line_case(dim, p, nz, seed=5)
+    B = sv.line_blocks(m, A)
+    idx = sv.line_unknowns(m)
+    rng = np.random.default_rng(9)
+    for n in (0, m.n_s // 2, m.n_s - 1):
+        x = np.zeros(m.n_v)
+        x[idx[n]] = rng.standard_normal(idx.shape[1])
+        z = sv.line_solve(m, B, A @ x)
+        np.testing.assert_allclose(z[idx[n]], x[idx[n]], rtol=0, atol=1e-11 * np.abs(x).max())
+        assert np.all(z[sv.surface_slice(m)] == 0.0)
+
+
+def test_line_block_closed_form_p1_flat_column():
+    """p = 1, one flat walled column of half widths a, d and layer half thickness c: the line
+    block is tridiagonal with off-diagonal -a d / (2 c) per layer (the zeta-zeta term
+    sum_c D[c][0] D[c][1] w det J / c^2 with D = [[-1/2, 1/2], [-1/2, 1/2]], unit weights; the
+    cross terms vanish on flat geometry)."""
+    lx, ly, nz = 0.8, 0.5, 4
+    m = wm.structured_box(1, 1, 0.0, lx, 0.0, ly, False, False, p=1, nz=nz)
+    eta = np.zeros(m.n_s)
+    h = np.full(m.n_s, 2.0)
+    G, _, _ = geo.factors(m, eta, h)
+    B = sv.line_blocks(m, op.assemble_dense(m, G))
+    a, d, c = lx / 2, ly / 2, 2.0 / nz / 2
+    for b in B:
+        np.testing.assert_allclose(np.diag(b, 1), -a * d / (2 * c), rtol=1e-13)
+        assert np.all(np.triu(b, 2) == 0.0)

@@ -208,10 +208,12 @@ fnpf_status fnpf_surface_interp_weights(fnpf_ctx ctx, int32_t n_pts, const doubl
  *     registers from five numbers per column node (eta+h, h and their
  *     horizontal derivatives) and the static horizontal metrics, so an apply
  *     reads x and writes y only.  3D: line schedule (below) with
- *     owner-computes assembly -- one launch over all columns stores each
- *     column's values at the horizontal nodes it owns (each node belongs to
- *     the lowest-numbered column that has it) and its other values into face
- *     slots, and a second launch adds the slots to the owners.  It is fastest
+ *     owner-computes assembly -- one launch over all columns, in which the
+ *     columns of a workgroup (256 / (p+1)^2 consecutive ones) form a tile
+ *     that sums its shared nodes in LDS and stores the nodes it owns (a node
+ *     belongs to the tile of the lowest-numbered column that has it) and its
+ *     other sums into face slots; a second launch adds the slots to the
+ *     owners.  It is fastest
  *     when each column's own nodes are numbered consecutively (shared ones
  *     first); any consistent numbering gives the same result.  The
  *     kernels index with 32-bit byte offsets: when n_v * 8 bytes or the
@@ -222,6 +224,9 @@ fnpf_status fnpf_surface_interp_weights(fnpf_ctx ctx, int32_t n_pts, const doubl
  *     of shared nodes;
  *   1 stored factors: fnpf_geom stores G (6 or 3 per point, FP64 and FP32)
  *     and the apply streams it from HBM;
+ *   2 as 0, but the FP32 apply at degree 6 (3D) runs the horizontal (xi, eta)
+ *     contractions on the matrix cores (v_mfma_f32_16x16x4f32, D padded to
+ *     16 x 8); FP64 and other degrees as 0;
  *   6 fused geometry, line schedule with colour assembly (3D): in the
  *     horizontal contraction phases each thread owns one xi-line and one
  *     eta-line of the element, so derivative coefficients are uniform

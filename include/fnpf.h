@@ -224,9 +224,6 @@ fnpf_status fnpf_surface_interp_weights(fnpf_ctx ctx, int32_t n_pts, const doubl
  *     of shared nodes;
  *   1 stored factors: fnpf_geom stores G (6 or 3 per point, FP64 and FP32)
  *     and the apply streams it from HBM;
- *   2 as 0, but the FP32 apply at degree 6 (3D) runs the horizontal (xi, eta)
- *     contractions on the matrix cores (v_mfma_f32_16x16x4f32, D padded to
- *     16 x 8); FP64 and other degrees as 0;
  *   6 fused geometry, line schedule with colour assembly (3D): in the
  *     horizontal contraction phases each thread owns one xi-line and one
  *     eta-line of the element, so derivative coefficients are uniform

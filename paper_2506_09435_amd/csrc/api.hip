@@ -366,7 +366,6 @@ Ctx::GraphKey graph_key(const Ctx &c, const void *x, const fnpf_solve_opts &o, i
   k.variant = c.apply_variant;
   k.lines = c.apply_lines;
   k.owner = c.apply_owner;
-  k.mfma = c.apply_mfma;
   k.line = c.mg_line;
   k.nb = nb;
   return k;
@@ -818,12 +817,11 @@ fnpf_status fnpf_node_coords(fnpf_ctx ctx, double *xy) {
 fnpf_status fnpf_set_apply_variant(fnpf_ctx ctx, int32_t variant) {
   if (!ctx) return FNPF_ERR_ARG;
   Ctx &c = ctx->c;
-  if (variant != 0 && variant != 1 && variant != 2 && variant != 6 && variant != 7)
-    return fail(&c, FNPF_ERR_ARG, "apply variant must be 0, 1, 2, 6 or 7");
-  c.apply_lines = c.dim == 3 && (variant == 0 || variant == 2 || variant == 6);
-  c.apply_owner = c.dim == 3 && (variant == 0 || variant == 2);
-  c.apply_mfma = c.dim == 3 && variant == 2;
-  if (variant == 2 || variant >= 6) variant = 0;   // schedules of the fused apply (apply_lines, _owner, _mfma)
+  if (variant != 0 && variant != 1 && variant != 6 && variant != 7)
+    return fail(&c, FNPF_ERR_ARG, "apply variant must be 0, 1, 6 or 7");
+  c.apply_lines = c.dim == 3 && (variant == 0 || variant == 6);
+  c.apply_owner = c.dim == 3 && variant == 0;
+  if (variant >= 6) variant = 0;   // 6 and 7 are schedules of the fused apply (apply_lines, apply_owner)
   if (variant == c.apply_variant) return FNPF_OK;
   c.apply_variant = variant;
   if (variant == 1) {

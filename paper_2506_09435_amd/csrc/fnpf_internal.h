@@ -192,7 +192,6 @@ struct Ctx {
   int apply_variant = 0;
   bool apply_lines = false;               // 3D fused apply with the xi/eta line schedule
   bool apply_owner = false;               // 3D line schedule with owner-computes assembly (two passes)
-  bool apply_mfma = false;                // owner apply in FP32 at degree 6: horizontal phases on MFMA
   // owner-computes assembly: contributions of a column at nodes it does not own go to face
   // slots (column-major numbering); the second pass adds them at the owner
   std::vector<int32_t> h_slot;            // [n_eh][nh] slot id, -1 where owned
@@ -285,11 +284,10 @@ struct Ctx {
   struct GraphKey {
     const void *x = nullptr;
     int precond = -1, check_every = 0, cheb = 0, variant = -1, nb = 0;
-    bool lines = false, owner = false, line = false, mfma = false;
+    bool lines = false, owner = false, line = false;
     bool operator==(const GraphKey &o) const {
       return x == o.x && precond == o.precond && check_every == o.check_every && cheb == o.cheb &&
-             variant == o.variant && nb == o.nb && lines == o.lines && owner == o.owner && line == o.line &&
-             mfma == o.mfma;
+             variant == o.variant && nb == o.nb && lines == o.lines && owner == o.owner && line == o.line;
     }
   };
   hipGraph_t g_graph[2] = {nullptr, nullptr};

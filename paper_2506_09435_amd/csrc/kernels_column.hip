@@ -596,71 +596,7 @@ __global__ __launch_bounds__(256) void k_apply_fused2(const T *__restrict__ x, T
 // whose exchange entry did not fit); k_apply_faces then adds the slots to the owners.  Blocks are
 // mapped so that each XCD (blocks dispatched round-robin over 8) walks a contiguous range of
 // tiles, keeping neighbouring tiles' shared cache lines in the same L2.
-// MF (FP32, degree 6, OWN): phases 1 and 3 on the matrix cores (mfma_lines); the launch then has
-// 256 threads, of which the last 11 take part in those phases only.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kMfmaGroup = 1;   // blocks of 16 lines per round of loads, products and stores
-
-// The horizontal contractions of one phase of a degree-6 workgroup as v_mfma_f32_16x16x4f32
-// products, in place.  Both line sets are stored line-contiguous here (sA: xi-lines, sB: eta-lines,
-// line L = 49 column + 7 plane + row at 7 L, the arrays padded to 256 lines); line n of a block
-// of 16 gets C[.][n] = M B[.][n] with M = D (TR = 0) or D^T (TR = 1), rows padded to 16, and
-// B[m][n] = element m of the line, in two K-steps: m = 0..3, then m = 3..6 with the column of
-// m = 3 zeroed in the second A operand (so no step reads past its line).  Operand layout of the
-// instruction: A[i][k] and B[k][j] at lane i + 16 k (j + 16 k), C[i][j] at lane j + 16 (i / 4),
-// register i % 4; lane l reads elements l / 16 and l / 16 + 3 of line l % 16 and, for l < 32,
-// writes elements 4 (l / 16) .. 4 (l / 16) + 3 (those below 7) of it.  Wave w takes blocks
-// w, w + 4, w + 8, w + 12, G at a time (all loads, then the products, then the stores); C
-// columns depend only on their own line, so the padding lines of block 15 (uninitialised) are
-// read but never stored.
-template <int G = kMfmaGroup>
-__device__ __forceinline__ void mfma_lines(float *__restrict__ sA, float *__restrict__ sB, float a0, float a1) {
-  constexpr int N1 = 7, NL = 245, BS = 4 * 16 * N1;   // a wave's next block: 4 blocks of 16 lines on
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int n = lane & 15, kq = lane >> 4;
-  float *xa = sA + (w * 16 + n) * N1, *xb = sB + (w * 16 + n) * N1;
-#pragma unroll
-  for (int u0 = 0; u0 < 4; u0 += G) {
-    float bx0[G], bx1[G], be0[G], be1[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int o = (u0 + g) * BS;
-      bx0[g] = xa[o + kq];
-      bx1[g] = xa[o + kq + 3];
-      be0[g] = xb[o + kq];
-      be1[g] = xb[o + kq + 3];
-    }
-    f32x4 cx[G], ce[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-      cx[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bx0[g], z, 0, 0, 0);
-      ce[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, be0[g], z, 0, 0, 0);
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      cx[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bx1[g], cx[g], 0, 0, 0);
-      ce[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, be1[g], ce[g], 0, 0, 0);
-    }
-    if (kq < 2) {
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int o = (u0 + g) * BS;
-        if ((w + 4 * (u0 + g)) * 16 + n < NL) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (4 * kq + q < N1) {
-              xa[o + 4 * kq + q] = cx[g][q];
-              xb[o + 4 * kq + q] = ce[g][q];
-            }
-          }
-        }
-      }
-    }
-  }
-}
-
-template <int P, typename T, bool MASK, bool DOT, bool OWN = false, bool MF = false>
+template <int P, typename T, bool MASK, bool DOT, bool OWN = false>
 __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T *__restrict__ y,
                                                      const T *__restrict__ cg, const T *__restrict__ hmT,
                                                      int64_t hstride, const T *__restrict__ sig,
@@ -680,46 +616,24 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
   // sB the eta-lines with the plane stride padded to SB = N1 (mod 64), so that lane t = b N1 + a
   // of the eta-line (i = a, k = b) starts at b SB + a = t (mod 64) and a wave's loads fall in
   // distinct banks (degrees < 4: N1 mod 16, to bound the LDS of their many columns per block)
-  // MF: sB holds the eta-lines contiguously as well ((i, j) stored at i N1 + j), and both arrays
-  // have a sixth column's worth of padding: the place of the threads without a column (their
-  // LDS traffic lands there) and of the padding lines of the matrix-core phases
   constexpr int SBM = P >= 4 ? 64 : 16;
-  constexpr int SB = MF ? NH : NH + (((N1 - NH) % SBM) + SBM) % SBM;
+  constexpr int SB = NH + (((N1 - NH) % SBM) + SBM) % SBM;
   constexpr int NPB = N1 * SB;
-  static_assert(!MF || (CPB + 1) * NP >= 256 * N1, "padding covers 16 blocks of 16 lines");
-  __shared__ T sA[(CPB + MF) * NP];
-  __shared__ T sB[(CPB + MF) * NPB];
+  __shared__ T sA[CPB * NP];
+  __shared__ T sB[CPB * NPB];
   __shared__ T sX[OWN ? N1 * XM : 1];
-  static_assert(!MF || (P == 6 && sizeof(T) == 4 && OWN), "matrix-core phases: FP32, degree 6, tiles");
   if (skip != nullptr && *skip) return;
 
-  // MF: threads NT..255 (no column: lc = CPB) work in the LDS padding and store nothing
-  const bool valid = !MF || threadIdx.x < CPB * NH;
   const int lc = threadIdx.x / NH;
   const int t = threadIdx.x - lc * NH;
   const int i = t % N1, j = t / N1;
-  const int tb = MF ? i * N1 + j : t;   // the point's place in its sB plane
   int blk = blockIdx.x;
   if constexpr (OWN) {
     const int nb = gridDim.x, q = nb >> 3, r = nb & 7, xc = blk & 7;
     blk = (xc < r ? xc * (q + 1) : r * (q + 1) + (xc - r) * q) + (blk >> 3);
   }
   const int ci = blk * CPB + lc;
-  const bool active = valid && ci < ncols;
-  // MF: this lane's A operands, D and D^T at row lane % 16, columns lane / 16 and lane / 16 + 3
-  // (the latter zero for lane / 16 = 0)
-  float mA0 = 0.f, mA1 = 0.f, mT0 = 0.f, mT1 = 0.f;
-  if constexpr (MF) {
-    const int r = threadIdx.x & 15, m = (threadIdx.x & 63) >> 4;
-    if (r < N1) {
-      mA0 = dmat<float>(P, r, m);
-      mT0 = dmat<float>(P, m, r);
-      if (m > 0) {
-        mA1 = dmat<float>(P, r, m + 3);
-        mT1 = dmat<float>(P, m + 3, r);
-      }
-    }
-  }
+  const bool active = ci < ncols;
   const int col = active ? (OWN ? ci : cols[ci]) : 0;
   const int hn = active ? eh_nodes[(int64_t)col * NH + t] : 0;
   const uint8_t fl = active ? flags[(int64_t)col * NH + t] : 0;
@@ -787,7 +701,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       Ab[k * NH + t] = ucol[k];
-      Bb[k * SB + tb] = ucol[k];
+      Bb[k * SB + t] = ucol[k];
     }
     T uz[N1];
     const T *E0 = eo_ptr<P, T, 0>(ucol[0]);
@@ -800,9 +714,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     }
 
     // phase 1 (in place: each line is read and written by its one thread)
-    if constexpr (MF) {
-      mfma_lines((float *)sA, (float *)sB, mA0, mA1);
-    } else {
+    {
       T in[N1], out[N1];
 #pragma unroll
       for (int m = 0; m < N1; ++m) in[m] = Ab[xi_base + m];
@@ -829,7 +741,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     T vz[N1], yz[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const int q = k * NH + t, qb = k * SB + tb;
+      const int q = k * NH + t, qb = k * SB + t;
       const T ux = Ab[q], uy = Bb[qb];
       const T sg = sig[l * P + k];
       const T f = (T)wgt(P, k) * fl0;
@@ -846,9 +758,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     __syncthreads();
 
     // phase 3 (in place: only this thread touches these lines now)
-    if constexpr (MF) {
-      mfma_lines((float *)sA, (float *)sB, mT0, mT1);
-    } else {
+    {
       T in[N1], out[N1];
 #pragma unroll
       for (int m = 0; m < N1; ++m) in[m] = Ab[xi_base + m];
@@ -876,7 +786,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     // phase 4
     T yv[N1];
 #pragma unroll
-    for (int k = 0; k < N1; ++k) yv[k] = yz[k] + (Ab[k * NH + t] + Bb[k * SB + tb]);
+    for (int k = 0; k < N1; ++k) yv[k] = yz[k] + (Ab[k * NH + t] + Bb[k * SB + t]);
     yv[0] += carry;
     carry = yv[P];
     if constexpr (OWN) {
@@ -1733,19 +1643,9 @@ static hipError_t apply_impl(Ctx &c, const T *x, T *y, const T *G, double *parti
             if constexpr (sizeof(T) == 8) F = (T *)c.d_F64; else F = (T *)c.d_F32;
           }
           const int nb1 = (c.n_eh + S::CPB - 1) / S::CPB;
-          bool mf = false;
-          if constexpr (P == 6 && sizeof(T) == 4) {
-            if (c.apply_mfma) {
-              k_apply_lines<P, T, MASK, DOT, true, true><<<nb1, 256, 0, s>>>(
-                  x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s,
-                  DOT ? partial : nullptr, skip, F, c.d_tslot, c.n_tslots, c.d_xch);
-              mf = true;
-            }
-          }
-          if (!mf)
-            k_apply_lines<P, T, MASK, DOT, true><<<nb1, S::NT, 0, s>>>(
-                x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s,
-                DOT ? partial : nullptr, skip, F, c.d_tslot, c.n_tslots, c.d_xch);
+          k_apply_lines<P, T, MASK, DOT, true><<<nb1, S::NT, 0, s>>>(
+              x, y, cg, hmT, hs, sig, hds, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s,
+              DOT ? partial : nullptr, skip, F, c.d_tslot, c.n_tslots, c.d_xch);
           if (c.n_tps > 0)
             k_apply_faces<T, MASK, DOT><<<face_blocks_n(c, c.n_tps), 256, 0, s>>>(
                 x, y, F, c.d_tps_node, c.d_tps_ptr, c.d_tps_slot, c.n_tps, c.p * c.nz + 1, c.n_s, c.n_tslots,

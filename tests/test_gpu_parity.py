@@ -54,12 +54,6 @@ def _case(name):
         wl.eta0 = lambda x, y: 0.05 * np.cos(np.asarray(x)) * np.sin(np.asarray(y))
         wl.phi0 = lambda x, y: 0.1 * np.sin(np.asarray(x) + 0.3 * np.asarray(y))
         return wl
-    if name == "box_p6_periodic":
-        return configs.small_box(nx=6, ny=3, nz=1, p=6, periodic=(True, True))
-    if name == "cylinder_p6":
-        wl = _case("cylinder")
-        wl.mesh = wm.cylinder_tank_mesh(p=6, nz=1, n_theta=8, n_rad=1, tank=(6.0, 4.0), spacing=1.0, hole_half=1.0)
-        return wl
     if name.endswith("_blocked"):
         wl = _case(name[: -len("_blocked")])
         wl.mesh = wm.renumber_blocked(wl.mesh)
@@ -155,35 +149,6 @@ def test_apply_random_fp64_fp32(name, variant):
     assert rel(ym[: top.start], yo[: top.start]) < 1e-13
     y32 = host(pr.ctx.laplace_apply(dev(xv).float()))
     assert rel(y32, yo) < 2e-6
-
-
-@pytest.mark.parametrize("name", ["box_walls_p6", "box_walls_p6_sharedfirst", "box_p6_periodic", "cylinder_p6"])
-def test_apply_mfma_fp32(name):
-    """Variant 2: the FP32 degree-6 apply with its horizontal contractions on the matrix cores,
-    against the oracle (plain, masked, inside the mixed PCG) and against variant 0's FP32 apply."""
-    pr = Pair(_case(name), fp32=True, variant=2)
-    pr.ctx.geom(pr.d_eta, pr.d_h)
-    Go, _, _ = pr.oracle_factors()
-    rng = np.random.default_rng(12)
-    xv = rng.standard_normal(pr.m.n_v)
-    yo = op.apply(pr.m, Go, xv)
-    y2 = host(pr.ctx.laplace_apply(dev(xv).float()))
-    assert rel(y2, yo) < 2e-6
-    top = sv.surface_slice(pr.m)
-    ym = host(pr.ctx.laplace_apply(dev(xv).float(), mask_dirichlet=True))
-    assert np.all(ym[top] == 0.0) and rel(ym[: top.start], yo[: top.start]) < 2e-6
-    assert rel(host(pr.ctx.laplace_apply(dev(xv))), yo) < 1e-13          # FP64: variant 0's kernels
-    pr.ctx.set_apply_variant(0)
-    y0 = host(pr.ctx.laplace_apply(dev(xv).float()))
-    assert rel(y2, y0) < 2e-6
-    pr.ctx.set_apply_variant(2)
-    if pr.m.n_v > 5000:
-        return                                   # dense oracle solve: small meshes only
-    A = op.assemble_dense(pr.m, Go)
-    phio = sv.solve_dense(pr.m, A, pr.phis)
-    phim, infom = pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precision=1, rtol=1e-11, inner_rtol=1e-3))
-    assert infom["status"] == "OK"
-    assert rel(host(phim), phio) < 1e-8
 
 
 @pytest.mark.parametrize("name", ["slice_walls", "box_walls_p6", "box_mixed", "cylinder"])
@@ -449,8 +414,8 @@ def test_error_paths():
         pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precond=3))
     with pytest.raises(fnpf.FnpfError):
         pr.ctx.solve(pr.d_phis, opts=fnpf.default_opts(precond=2, cheb_degree=0))
-    # the removed measurement schedules (3..5) and unknown variants are rejected
-    for v in (-1, 3, 4, 5, 8):
+    # the removed measurement schedules (2..5) and unknown variants are rejected
+    for v in (-1, 2, 3, 4, 5, 8):
         with pytest.raises(fnpf.FnpfError) as ei:
             pr.ctx.set_apply_variant(v)
         assert ei.value.name == "ERR_ARG"

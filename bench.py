@@ -35,12 +35,12 @@ FP64_VALU_PEAK_TFS = 78.6
 FP32_VALU_PEAK_TFS = 157.3
 METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/forward ratio"
 
-# HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by the
-# plain-copy calibration), valid only for the kernel source they were taken from.
+# HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by what the
+# counters read for kernels of known size), valid only for the kernel source they were taken from.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "025f7e463dba33f651ebb0be29d05712aaab68dca9cb077da39eabf3a6546268",
-    "fetch_bytes_per_apply": 860810466,
-    "write_bytes_per_apply": 587889039,
+    "kernel_source_sha256": "ca51ef36ea2e8b14e19484a5f80b7aefc7cf5805f924d8b0296f6f894e9ffe19",
+    "fetch_bytes_per_apply": 800725845,
+    "write_bytes_per_apply": 516173691,
 }
 
 
@@ -260,8 +260,8 @@ def adjoint_leg(nsteps, rtol, fd_dirs, precond=1, adj_precond=None, line=0):
     eta_in = torch.tensor(wl.relax_wave.eta(x, y, 0.0), device="cuda")
     phi_in = torch.tensor(wl.relax_wave.phi(x, y, 0.0), device="cuda")
     # Jacobi by default: on this 0.55 M-DoF mesh with 9.5:1 elements in plan the multigrid cycle
-    # costs more than its iteration savings in the rollout (200 steps: forward 9.2 s with the
-    # multigrid preconditioner against 5.7 s, backward 15.3 s against 7.3 s)
+    # costs more than its iteration savings in the rollout (200 steps at rtol 1e-9: forward 11.9 s
+    # with the multigrid preconditioner against 8.0 s, backward 18.3 s against 9.0 s)
     o = fnpf.default_opts(rtol=rtol, precond=precond, check_every=25 if precond == 1 else 5, line_smoother=line)
     with torch.no_grad():
         obs = rollout(fctx, eta_in, phi_in, B @ c_true, 0.0, wl.dt, nsteps, opts=o) @ P.T

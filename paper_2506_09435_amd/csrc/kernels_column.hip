@@ -29,6 +29,7 @@ namespace fnpf {
 __constant__ double c_D64[kMaxN1 * kDStride];
 __constant__ float c_D32[kMaxN1 * kDStride];
 __constant__ double c_W[kMaxN1 * kMaxN1];
+__constant__ double c_DSQ64[kMaxN1 * kDStride];   // D[r][c]^2 (the assembled diagonal's line sums)
 
 // Even-odd coefficient tables of the line contractions with D (tr = 0) and D^T (tr = 1), per
 // degree p, with H = (p+1)/2 pairs (r, p-r) and, for even p, the middle index c = p/2.  Both
@@ -69,6 +70,7 @@ size_t noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
 
 hipError_t upload_constants(int /*device*/) {
   static double D64[kMaxN1 * kDStride];
+  static double DSQ64[kMaxN1 * kDStride];
   static float D32[kMaxN1 * kDStride];
   static double W[kMaxN1 * kMaxN1];
   static double EO64[(kMaxP + 1) * 2 * kEOStride];
@@ -79,6 +81,7 @@ hipError_t upload_constants(int /*device*/) {
     const int n1 = p + 1;
     for (int i = 0; i < n1 * n1; ++i) {
       D64[p * kDStride + i] = D[i];
+      DSQ64[p * kDStride + i] = D[i] * D[i];
       D32[p * kDStride + i] = (float)D[i];
     }
     for (int i = 0; i < n1; ++i) W[p * kMaxN1 + i] = w[i];
@@ -104,6 +107,8 @@ hipError_t upload_constants(int /*device*/) {
     }
   }
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_D64), D64, sizeof(D64));
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_DSQ64), DSQ64, sizeof(DSQ64));
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_D32), D32, sizeof(D32));
   if (e != hipSuccess) return e;
@@ -135,6 +140,7 @@ __device__ __forceinline__ float dmat<float>(int P, int r, int c) {
   return c_D32[P * kDStride + r * (P + 1) + c];
 }
 __device__ __forceinline__ double wgt(int P, int i) { return c_W[P * kMaxN1 + i]; }
+__device__ __forceinline__ double dsq(int P, int r, int c) { return c_DSQ64[P * kDStride + r * (P + 1) + c]; }
 
 // Raw buffer access: a per-thread 32-bit byte offset plus a wave-uniform row offset, so the
 // vertical walk needs one address register per thread.  The descriptor's record count is the
@@ -961,8 +967,10 @@ int owner_apply_blocks(const Ctx &c) {
 // tile as in the owner-computes apply: the tile's columns pass their diagonal contributions at
 // shared nodes to the node's representative through LDS exchange entries (xch), which stores the
 // diagonal (and its inverses where no other tile contributes) or writes its tile's sum to a face
-// slot; k_diag_faces completes the nodes with face slots.
-template <int P, int DIM, bool OWN = false>
+// slot; k_diag_faces completes the nodes with face slots.  SG: also store the per-point factors
+// (G64, G32) for the stored-factor apply; without them the off-diagonal factors are dead code and
+// the kernel needs about two thirds of the registers.
+template <int P, int DIM, bool OWN = false, bool SG = true>
 __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, const double *__restrict__ hb,
                                               const double *__restrict__ hm, int64_t hstride,
                                               const int32_t *__restrict__ eh_nodes, const uint8_t *__restrict__ flags,
@@ -979,13 +987,18 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   using S = Sh<P, DIM>;
   constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, NG = S::NG, CPB = S::CPB;
   constexpr int XM = CPB * NH / 2;   // exchange entries per tile (the host's tile_xmax)
-  constexpr int NT = 256;
-  __shared__ double sH[CPB * NH];
-  __shared__ double sh[CPB * NH];
-  __shared__ double s0[CPB * NP];
-  __shared__ double s1[DIM == 3 ? CPB * NP : 1];
-  __shared__ double sX[OWN ? N1 * XM : 1];     // partners' values at shared nodes
-  __shared__ double sS[OWN ? N1 * NT : 1];     // a storing column's own values
+  // The diagonal at node (i, j, k) of an element, collocated quadrature:
+  //   sum_m D[m][i]^2 G_xx(m, j, k) + sum_m D[m][j]^2 G_yy(i, m, k) + sum_m D[m][k]^2 G_zz(i, j, m)
+  //   + 2 (D_ii D_jj G_xy + D_ii D_kk G_xz + D_jj D_kk G_yz)(i, j, k).
+  // sA holds G_xx at the element's points (plane k, row j, entry i at k NH + j N1 + i) and then, in
+  // place, its xi-line sums; sB the same for G_yy along eta-lines; the zeta sums use the thread's
+  // own vertical line in registers.  sX: the partners' values at shared nodes (OWN) and, before
+  // the layer loop, the surface H and h of the block's columns.
+  constexpr int NX0 = 2 * CPB * NH, NX1 = OWN ? N1 * XM : 0;
+  __shared__ double sA[CPB * NP];
+  __shared__ double sB[DIM == 3 ? CPB * NP : 1];
+  __shared__ double sX[NX0 > NX1 ? NX0 : NX1];
+  double *sH = sX, *sh = sX + CPB * NH;
 
   const int lc = threadIdx.x / NH;
   const int t = threadIdx.x - lc * NH;
@@ -1066,13 +1079,9 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
     detJh = active ? hm[1 * hstride + ho] : 1.0;
   }
   const double wh = DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i);
-  // squared derivative entries D[m][c]^2 in LDS (read in the diagonal sums), not in registers
-  __shared__ double sD2[N1 * N1];
-  if (threadIdx.x < N1 * N1) {
-    const double a = dmat<double>(P, threadIdx.x / N1, threadIdx.x % N1);
-    sD2[threadIdx.x] = a * a;
-  }
-  const double Dii = dmat<double>(P, i, i), Djj = dmat<double>(P, j, j);
+  const double Dii = dmat<double>(P, i, i), Djj = DIM == 3 ? dmat<double>(P, j, j) : 0.0;
+  double *Ab = sA + lc * NP;
+  double *Bb = sB + (DIM == 3 ? lc * NP : 0);
 
   double carry = 0.0;
   const int64_t e0 = (int64_t)col * nz;
@@ -1094,12 +1103,12 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
         const double b2y = -(zx * A01 + zy * A11) * izz;
         const double b2z = izz;
         const double g00 = f * (A00 * A00 + A01 * A01);
-        const double g01 = f * (A00 * A10 + A01 * A11);
-        const double g02 = f * (A00 * b2x + A01 * b2y);
         const double g11 = f * (A10 * A10 + A11 * A11);
-        const double g12 = f * (A10 * b2x + A11 * b2y);
         const double g22 = f * (b2x * b2x + b2y * b2y + b2z * b2z);
-        if (active && Ge64) {
+        if (SG && active && Ge64) {
+          const double g01 = f * (A00 * A10 + A01 * A11);
+          const double g02 = f * (A00 * b2x + A01 * b2y);
+          const double g12 = f * (A10 * b2x + A11 * b2y);
           Ge64[0 * NP + q] = g00;
           Ge64[1 * NP + q] = g01;
           Ge64[2 * NP + q] = g02;
@@ -1115,16 +1124,16 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
             Ge32[5 * NP + q] = (float)g22;
           }
         }
-        s0[lc * NP + q] = g00;
-        s1[lc * NP + q] = g11;
+        Ab[q] = g00;
+        Bb[q] = g11;
         gz[k] = g22;
       } else {
         const double b1x = -zx * A00 * izz;
         const double b1z = izz;
         const double g00 = f * A00 * A00;
-        const double g01 = f * A00 * b1x;
         const double g11 = f * (b1x * b1x + b1z * b1z);
-        if (active && Ge64) {
+        if (SG && active && Ge64) {
+          const double g01 = f * A00 * b1x;
           Ge64[0 * NP + q] = g00;
           Ge64[1 * NP + q] = g01;
           Ge64[2 * NP + q] = g11;
@@ -1134,74 +1143,99 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
             Ge32[2 * NP + q] = (float)g11;
           }
         }
-        s0[lc * NP + q] = g00;
+        Ab[q] = g00;
         gz[k] = g11;
       }
     }
     __syncthreads();
-    // diagonal, one level at a time (not unrolled: the unrolled form held every level's terms and
-    // the derivative tables in registers, which cut the occupancy to one wave per SIMD); the
-    // mixed terms are recomputed from the same expressions as above
+    // line sums in place: the thread's xi-line (j = a, k = b) and, in 3D, eta-line (i = a,
+    // k = b), t = b N1 + a; out_r = sum_m D[m][r]^2 in_m
+    {
+      double in[N1];
+#pragma unroll
+      for (int m = 0; m < N1; ++m) in[m] = Ab[t * N1 + m];
+#pragma unroll
+      for (int r = 0; r < N1; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) a += dsq(P, m, r) * in[m];
+        Ab[t * N1 + r] = a;
+      }
+      if constexpr (DIM == 3) {
+        const int eb = (t / N1) * NH + t % N1;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) in[m] = Bb[eb + m * N1];
+#pragma unroll
+        for (int r = 0; r < N1; ++r) {
+          double a = 0.0;
+#pragma unroll
+          for (int m = 0; m < N1; ++m) a += dsq(P, m, r) * in[m];
+          Bb[eb + r * N1] = a;
+        }
+      }
+    }
+    __syncthreads();
+    // the node's diagonal at each level of the layer element, one level at a time; the node's own
+    // entry of sA (read here by this thread only) then holds its value for the tile assembly
+    const int kh = (l == nz - 1) ? N1 : P;   // levels stored by this layer (the top one by the next)
     double top = 0.0;
 #pragma unroll 1
     for (int k = 0; k < N1; ++k) {
-      double d = 0.0;
+      double d = Ab[k * NH + t];
+      if constexpr (DIM == 3) d += Bb[k * NH + t];
 #pragma unroll
-      for (int m = 0; m < N1; ++m) d += sD2[m * N1 + i] * s0[lc * NP + k * NH + j * N1 + m];
-#pragma unroll
-      for (int m = 0; m < N1; ++m) {
-        const double a = dmat<double>(P, m, k);
-        d += a * a * gz[m];
-      }
+      for (int m = 0; m < N1; ++m) d += dsq(P, m, k) * gz[m];
       const double Dkk = dmat<double>(P, k, k);
       const double sg = sigma[l * P + k];
       const double zx = -hx + sg * Hx;
       const double f = wh * wgt(P, k) * detJh * zz;
       if constexpr (DIM == 3) {
-#pragma unroll
-        for (int m = 0; m < N1; ++m) d += sD2[m * N1 + j] * s1[lc * NP + k * NH + m * N1 + i];
-        const double zy = -hy + sg * Hy;
-        const double b2x = -(zx * A00 + zy * A10) * izz;
-        const double b2y = -(zx * A01 + zy * A11) * izz;
         const double c01 = f * (A00 * A10 + A01 * A11);
-        const double c02 = f * (A00 * b2x + A01 * b2y);
-        const double c12 = f * (A10 * b2x + A11 * b2y);
-        d += 2.0 * (Dii * Djj * c01 + Dii * Dkk * c02 + Djj * Dkk * c12);
+        if (Dkk != 0.0) {   // uniform: D_kk vanishes except at the element's bottom and top levels
+          const double zy = -hy + sg * Hy;
+          const double b2x = -(zx * A00 + zy * A10) * izz;
+          const double b2y = -(zx * A01 + zy * A11) * izz;
+          const double c02 = f * (A00 * b2x + A01 * b2y);
+          const double c12 = f * (A10 * b2x + A11 * b2y);
+          d += 2.0 * (Dii * Djj * c01 + Dii * Dkk * c02 + Djj * Dkk * c12);
+        } else {
+          d += 2.0 * (Dii * Djj * c01);
+        }
       } else {
         const double b1x = -zx * A00 * izz;
         const double c01 = f * A00 * b1x;
         d += 2.0 * Dii * Dkk * c01;
       }
       if (k == 0) d += carry;
-      if (k == P && l < nz - 1) {
-        top = d;   // the level shared with the next layer, completed there
-      } else if (OWN) {
-        if (xw >= 0)
-          sX[k * XM + xw] = d;
-        else
-          sS[k * NT + threadIdx.x] = d;
-      } else if (active) {
-        const int v = l * P + k;
-        const int64_t idx = (int64_t)v * n_s + hn;
-        const double val = scatter(diag, idx, d, fl);
-        if (fl & kLast) {
-          const double di = (v == P * nz) ? 0.0 : 1.0 / val;
-          dinv[idx] = di;
-          if (dinv32) dinv32[idx] = (float)di;
+      if (k == P) top = d;
+      if (k < kh) {
+        if constexpr (OWN) {
+          if (xw >= 0)
+            sX[k * XM + xw] = d;
+          else
+            Ab[k * NH + t] = d;
+        } else if (active) {
+          const int v = l * P + k;
+          const int64_t idx = (int64_t)v * n_s + hn;
+          const double val = scatter(diag, idx, d, fl);
+          if (fl & kLast) {
+            const double di = (v == P * nz) ? 0.0 : 1.0 / val;
+            dinv[idx] = di;
+            if (dinv32) dinv32[idx] = (float)di;
+          }
         }
       }
     }
-    __syncthreads();
     carry = top;
     if constexpr (OWN) {
-      // representatives add their partners' values and store (the next writes to sX and sS
-      // follow the next layer's first barrier)
+      __syncthreads();
+      // representatives add their partners' values and store (the next writes to sX follow the
+      // next layer's first barrier; sA's own entries are rewritten by this thread only)
       if (stores) {
-        const int kh = (l == nz - 1) ? N1 : P;
 #pragma unroll
         for (int k = 0; k < N1; ++k) {
           if (k < kh) {
-            double a = sS[k * NT + threadIdx.x];
+            double a = Ab[k * NH + t];
             if (xr0 >= 0) a += sX[k * XM + xr0];
             if (xr1 >= 0) a += sX[k * XM + xr1];
             if (xr2 >= 0) a += sX[k * XM + xr2];
@@ -1576,7 +1610,8 @@ static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, bool sto
     const int64_t lim = int64_t(1) << 32;
     if (c.tile_cols == S::CPB && c.n_v * 8 < lim) {
       const int nb = (c.n_eh + S::CPB - 1) / S::CPB;
-      k_geom<P, DIM, true><<<nb, S::NT, 0, s>>>(
+      auto kern = store_G ? k_geom<P, DIM, true, true> : k_geom<P, DIM, true, false>;
+      kern<<<nb, S::NT, 0, s>>>(
           eta, h, c.d_hm, hs, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s, c.d_sigma, c.d_layer_s,
           store_G ? c.d_G64 : nullptr, (store_G && c.want32) ? c.d_G32 : nullptr, c.d_diag, c.d_dinv,
           c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh, c.d_cg64, c.want32 ? c.d_cg32 : nullptr,
@@ -1594,11 +1629,13 @@ static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, bool sto
   for (const auto &cr : c.colours) {
     if (cr.count == 0) continue;
     const int nb = (cr.count + S::CPB - 1) / S::CPB;
-    k_geom<P, DIM><<<nb, S::NT, 0, s>>>(eta, h, c.d_hm, hs, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count,
-                                        c.nz, c.n_s, c.d_sigma, c.d_layer_s, store_G ? c.d_G64 : nullptr,
-                                        (store_G && c.want32) ? c.d_G32 : nullptr, c.d_diag, c.d_dinv,
-                                        c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh, c.d_cg64,
-                                        c.want32 ? c.d_cg32 : nullptr, h_is_total ? 1 : 0, c.d_err);
+    auto kern = store_G ? k_geom<P, DIM, false, true> : k_geom<P, DIM, false, false>;
+    kern<<<nb, S::NT, 0, s>>>(eta, h, c.d_hm, hs, c.d_eh_nodes, c.d_flags, c.d_cols + cr.offset, cr.count, c.nz,
+                              c.n_s, c.d_sigma, c.d_layer_s, store_G ? c.d_G64 : nullptr,
+                              (store_G && c.want32) ? c.d_G32 : nullptr, c.d_diag, c.d_dinv,
+                              c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh, c.d_cg64,
+                              c.want32 ? c.d_cg32 : nullptr, h_is_total ? 1 : 0, c.d_err, nullptr, nullptr, 0,
+                              nullptr);
   }
   return hipGetLastError();
 }

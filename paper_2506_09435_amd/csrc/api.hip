@@ -865,7 +865,10 @@ fnpf_status fnpf_export_geometry(fnpf_ctx ctx, fnpf_dtype dtype, void *G, double
     else
       HIPCHK(hipMemcpyAsync(G, c.d_G32, ng * sizeof(float), hipMemcpyDeviceToDevice, s));
   }
-  if (diag) HIPCHK(hipMemcpyAsync(diag, c.d_diag, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (diag) {
+    HIPCHK(ensure_diag(c, s));
+    HIPCHK(hipMemcpyAsync(diag, c.d_diag, c.n_v * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
   return FNPF_OK;
 }
 

@@ -68,8 +68,13 @@ hipError_t upload_constants(int device);
 hipError_t init_noalloc_scratch(int device);
 void *noalloc_scratch(int device);
 size_t noalloc_scratch_bytes();
+// full_diag: store the assembled diagonal at every node (it is also stored when store_G or
+// c.keep_diag); otherwise the owner-computes path keeps only what its inverses need
 hipError_t launch_geom(Ctx &c, const double *eta, const double *h, bool store_G, bool h_is_total,
-                       hipStream_t s);
+                       hipStream_t s, bool full_diag = false);
+// the assembled diagonal d_diag at every node, recomputed from the saved column data if the last
+// geometry update did not store it
+hipError_t ensure_diag(Ctx &c, hipStream_t s);
 hipError_t launch_apply(Ctx &c, fnpf_dtype dt, const void *x, void *y, bool mask, double *partial,
                         const int32_t *skip, hipStream_t s, void *face_scratch = nullptr);
 hipError_t launch_neumann(Ctx &c, const double *q, double *f, hipStream_t s);
@@ -226,6 +231,8 @@ struct Ctx {
   double *d_G64 = nullptr;
   float *d_G32 = nullptr;
   double *d_diag = nullptr;
+  bool have_diag = false;                 // d_diag holds the assembled diagonal at every node
+  bool keep_diag = false;                 // store it at every geometry update (line smoothing reads it)
   double *d_dinv = nullptr;
   float *d_dinv32 = nullptr;
   const double *geom_eta = nullptr;       // eta/h of the last fnpf_geom (caller-owned, used by w recovery)

@@ -140,7 +140,24 @@ __device__ __forceinline__ float dmat<float>(int P, int r, int c) {
   return c_D32[P * kDStride + r * (P + 1) + c];
 }
 __device__ __forceinline__ double wgt(int P, int i) { return c_W[P * kMaxN1 + i]; }
+// 1/a for the Jacobi inverses: the hardware reciprocal estimate refined by two Newton steps
+// (r <- r + r (1 - a r)), within an ulp or two of the correctly rounded quotient at a fraction of
+// the IEEE division's instruction count; a is a positive diagonal entry
+__device__ __forceinline__ double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(r, fma(-a, r, 1.0), r);
+  return fma(r, fma(-a, r, 1.0), r);
+}
 __device__ __forceinline__ double dsq(int P, int r, int c) { return c_DSQ64[P * kDStride + r * (P + 1) + c]; }
+// The squared-derivative table of degree P behind an opaque zero offset that depends on `dep`:
+// its scalar loads cannot be hoisted above `dep` (so the 49 FP64 entries at P = 6 are not held in
+// scalar registers across the whole kernel, which spills them to vector lanes).
+template <typename U>
+__device__ __forceinline__ const double *dsq_ptr(int P, const U &dep) {
+  int z = 0;
+  asm volatile("" : "+s"(z) : "v"(dep));
+  return c_DSQ64 + P * kDStride + z;
+}
 
 // Raw buffer access: a per-thread 32-bit byte offset plus a wave-uniform row offset, so the
 // vertical walk needs one address register per thread.  The descriptor's record count is the
@@ -983,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
                                               float *__restrict__ cg32, int h_is_total, int32_t *__restrict__ err,
                                               double *__restrict__ F = nullptr,
                                               const int32_t *__restrict__ slot = nullptr, int64_t n_slots = 0,
-                                              const int16_t *__restrict__ xch = nullptr) {
+                                              const int16_t *__restrict__ xch = nullptr, int full_diag = 1) {
   using S = Sh<P, DIM>;
   constexpr int N1 = S::N1, NH = S::NH, NP = S::NP, NG = S::NG, CPB = S::CPB;
   constexpr int XM = CPB * NH / 2;   // exchange entries per tile (the host's tile_xmax)
@@ -995,8 +1012,12 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   // own vertical line in registers.  sX: the partners' values at shared nodes (OWN) and, before
   // the layer loop, the surface H and h of the block's columns.
   constexpr int NX0 = 2 * CPB * NH, NX1 = OWN ? N1 * XM : 0;
+  // sB's plane stride padded as the apply's eta-line array: SB = N1 (mod 64), so the 64 lanes of
+  // a wave reading their eta-lines start in distinct banks (degrees < 4: N1 mod 16)
+  constexpr int SBM = P >= 4 ? 64 : 16;
+  constexpr int SB = DIM == 3 ? NH + (((N1 - NH) % SBM) + SBM) % SBM : NH;
   __shared__ double sA[CPB * NP];
-  __shared__ double sB[DIM == 3 ? CPB * NP : 1];
+  __shared__ double sB[DIM == 3 ? CPB * N1 * SB : 1];
   __shared__ double sX[NX0 > NX1 ? NX0 : NX1];
   double *sH = sX, *sh = sX + CPB * NH;
 
@@ -1024,6 +1045,23 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
     sl = slot[ho];
   }
   const bool stores = OWN && active && ((fl & kTRep) || sl >= 0);
+  // OWN stores through raw buffer descriptors with 32-bit byte offsets (the launcher checks that
+  // the level rows of diag and of the face slots fit): a storing thread writes the diagonal where
+  // its tile owns the node and k_diag_faces completes it (or the whole diagonal is kept), the
+  // inverses where no other tile contributes, and its face slot elsewhere
+  constexpr int kSmStore = 1, kSmDiag = 2, kSmInv = 4, kSmSlot = 8, kSmX0 = 16, kSmX1 = 32, kSmX2 = 64;
+  const int smode = !stores ? 0
+                            : kSmStore | ((fl & kTOwn) && (full_diag || (fl & kTShared)) ? kSmDiag : 0) |
+                                  ((fl & kTOwn) && !(fl & kTShared) ? kSmInv : 0) | (!(fl & kTOwn) ? kSmSlot : 0) |
+                                  (xr0 >= 0 ? kSmX0 : 0) | (xr1 >= 0 ? kSmX1 : 0) | (xr2 >= 0 ? kSmX2 : 0);
+  const int xc0 = xr0 < 0 ? 0 : xr0, xc1 = xr1 < 0 ? 0 : xr1, xc2 = xr2 < 0 ? 0 : xr2;
+  const uint32_t row8 = (uint32_t)n_s * 8u, rowF8 = (uint32_t)n_slots * 8u;
+  const uint32_t hb8 = (uint32_t)hn * 8u, fb8 = (uint32_t)(sl < 0 ? 0 : sl) * 8u;
+  const uint32_t nlv = (uint32_t)(P * nz + 1);
+  const __amdgpu_buffer_rsrc_t r_diag = vec_rsrc(diag, OWN ? nlv * row8 : 0u);
+  const __amdgpu_buffer_rsrc_t r_dinv = vec_rsrc(dinv, OWN ? nlv * row8 : 0u);
+  const __amdgpu_buffer_rsrc_t r_dinv32 = vec_rsrc(dinv32, OWN ? nlv * (row8 >> 1) : 0u);
+  const __amdgpu_buffer_rsrc_t r_F = vec_rsrc(F, OWN ? nlv * rowF8 : 0u);
 
   const double Hn = active ? (h_is_total ? eta[hn] : eta[hn] + hb[hn]) : 1.0;
   const double hnv = active ? hb[hn] : 0.0;
@@ -1081,7 +1119,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   const double wh = DIM == 3 ? wgt(P, i) * wgt(P, j) : wgt(P, i);
   const double Dii = dmat<double>(P, i, i), Djj = DIM == 3 ? dmat<double>(P, j, j) : 0.0;
   double *Ab = sA + lc * NP;
-  double *Bb = sB + (DIM == 3 ? lc * NP : 0);
+  double *Bb = sB + (DIM == 3 ? lc * N1 * SB : 0);
 
   double carry = 0.0;
   const int64_t e0 = (int64_t)col * nz;
@@ -1125,7 +1163,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
           }
         }
         Ab[q] = g00;
-        Bb[q] = g11;
+        Bb[k * SB + t] = g11;
         gz[k] = g22;
       } else {
         const double b1x = -zx * A00 * izz;
@@ -1154,22 +1192,24 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
       double in[N1];
 #pragma unroll
       for (int m = 0; m < N1; ++m) in[m] = Ab[t * N1 + m];
+      const double *Q = dsq_ptr(P, in[0]);
 #pragma unroll
       for (int r = 0; r < N1; ++r) {
         double a = 0.0;
 #pragma unroll
-        for (int m = 0; m < N1; ++m) a += dsq(P, m, r) * in[m];
+        for (int m = 0; m < N1; ++m) a += Q[m * N1 + r] * in[m];
         Ab[t * N1 + r] = a;
       }
       if constexpr (DIM == 3) {
-        const int eb = (t / N1) * NH + t % N1;
+        const int eb = (t / N1) * SB + t % N1;
 #pragma unroll
         for (int m = 0; m < N1; ++m) in[m] = Bb[eb + m * N1];
+        const double *Q2 = dsq_ptr(P, in[0]);
 #pragma unroll
         for (int r = 0; r < N1; ++r) {
           double a = 0.0;
 #pragma unroll
-          for (int m = 0; m < N1; ++m) a += dsq(P, m, r) * in[m];
+          for (int m = 0; m < N1; ++m) a += Q2[m * N1 + r] * in[m];
           Bb[eb + r * N1] = a;
         }
       }
@@ -1182,9 +1222,10 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
 #pragma unroll 1
     for (int k = 0; k < N1; ++k) {
       double d = Ab[k * NH + t];
-      if constexpr (DIM == 3) d += Bb[k * NH + t];
+      if constexpr (DIM == 3) d += Bb[k * SB + t];
+      const double *Qk = dsq_ptr(P, d) + k;
 #pragma unroll
-      for (int m = 0; m < N1; ++m) d += dsq(P, m, k) * gz[m];
+      for (int m = 0; m < N1; ++m) d += Qk[m * N1] * gz[m];
       const double Dkk = dmat<double>(P, k, k);
       const double sg = sigma[l * P + k];
       const double zx = -hx + sg * Hx;
@@ -1219,7 +1260,7 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
           const int64_t idx = (int64_t)v * n_s + hn;
           const double val = scatter(diag, idx, d, fl);
           if (fl & kLast) {
-            const double di = (v == P * nz) ? 0.0 : 1.0 / val;
+            const double di = (v == P * nz) ? 0.0 : recip(val);
             dinv[idx] = di;
             if (dinv32) dinv32[idx] = (float)di;
           }
@@ -1231,26 +1272,29 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
       __syncthreads();
       // representatives add their partners' values and store (the next writes to sX follow the
       // next layer's first barrier; sA's own entries are rewritten by this thread only)
-      if (stores) {
+      // the per-thread conditions are re-derived here from one opaque word, so the compiler does
+      // not keep a 64-bit lane mask per condition live across the layer loop (which spilled
+      // scalar registers to vector lanes)
+      int sm = smode;
+      asm volatile("" : "+v"(sm));
+      if (sm & kSmStore) {
 #pragma unroll
         for (int k = 0; k < N1; ++k) {
           if (k < kh) {
+            // partners' entries read unconditionally at clamped (valid) places, then selected
+            const double p0 = sX[k * XM + xc0], p1 = sX[k * XM + xc1], p2 = sX[k * XM + xc2];
             double a = Ab[k * NH + t];
-            if (xr0 >= 0) a += sX[k * XM + xr0];
-            if (xr1 >= 0) a += sX[k * XM + xr1];
-            if (xr2 >= 0) a += sX[k * XM + xr2];
-            const int v = l * P + k;
-            const int64_t idx = (int64_t)v * n_s + hn;
-            if (fl & kTOwn) {
-              diag[idx] = a;
-              if (!(fl & kTShared)) {
-                const double di = (v == P * nz) ? 0.0 : 1.0 / a;
-                dinv[idx] = di;
-                if (dinv32) dinv32[idx] = (float)di;
-              }
-            } else {
-              F[(int64_t)v * n_slots + sl] = a;
+            a += (sm & kSmX0) ? p0 : 0.0;
+            a += (sm & kSmX1) ? p1 : 0.0;
+            a += (sm & kSmX2) ? p2 : 0.0;
+            const uint32_t v = (uint32_t)(l * P + k);
+            if (sm & kSmDiag) buf_st(a, r_diag, hb8, v * row8);
+            if (sm & kSmInv) {
+              const double di = (v == (uint32_t)(P * nz)) ? 0.0 : recip(a);
+              buf_st(di, r_dinv, hb8, v * row8);
+              if (dinv32) buf_st((float)di, r_dinv32, hb8 >> 1, v * (row8 >> 1));
             }
+            if (sm & kSmSlot) buf_st(a, r_F, fb8, v * rowF8);
           }
         }
       }
@@ -1259,25 +1303,51 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
 }
 
 // Face pass of the owner-computes geometry: diag += the face slots of the other tiles at each node
-// with slots (in increasing slot order), and the inverses there (0 on the top level).
+// with slots (in increasing slot order), and the inverses there (0 on the top level); the sum is
+// written back to diag only when the whole diagonal is kept.  Same thread layout as k_apply_faces:
+// a thread takes one node and a chunk of kFaceLevels levels, all loads issued before the sums, and
+// each XCD walks a contiguous range of nodes.
 __global__ __launch_bounds__(256) void k_diag_faces(double *__restrict__ diag, double *__restrict__ dinv,
                                                     float *__restrict__ dinv32, const double *__restrict__ F,
                                                     const int32_t *__restrict__ ps_node,
                                                     const int32_t *__restrict__ ps_ptr,
                                                     const int32_t *__restrict__ ps_slot, int n_ps, int nlev,
-                                                    int64_t n_s, int64_t n_slots) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= (int64_t)n_ps * nlev) return;
-  const int v = (int)(g / n_ps);
-  const int k = (int)(g - (int64_t)v * n_ps);
+                                                    int64_t n_s, int64_t n_slots, int full_diag) {
+  constexpr int LC = kFaceLevels;
+  int blk = blockIdx.x;
+  {
+    const int nb = gridDim.x, q = nb >> 3, r = nb & 7, xc = blk & 7;
+    blk = (xc < r ? xc * (q + 1) : r * (q + 1) + (xc - r) * q) + (blk >> 3);
+  }
+  const int nbx = (n_ps + 255) >> 8;
+  const int chunk = blk / nbx;
+  const int k = (blk - chunk * nbx) * 256 + threadIdx.x;
+  const int v0 = chunk * LC;
+  if (k >= n_ps) return;
   const int64_t n = ps_node[k];
-  const int64_t idx = (int64_t)v * n_s + n;
-  double a = diag[idx];
-  for (int q = ps_ptr[k]; q < ps_ptr[k + 1]; ++q) a += F[(int64_t)v * n_slots + ps_slot[q]];
-  diag[idx] = a;
-  const double di = (v == nlev - 1) ? 0.0 : 1.0 / a;
-  dinv[idx] = di;
-  if (dinv32) dinv32[idx] = (float)di;
+  const int a = ps_ptr[k], b = ps_ptr[k + 1];
+  double acc[LC];
+#pragma unroll
+  for (int u = 0; u < LC; ++u) acc[u] = (v0 + u < nlev) ? diag[(v0 + u) * n_s + n] : 0.0;
+  for (int q = a; q < b; ++q) {
+    const int64_t sl = ps_slot[q];
+    double f[LC];
+#pragma unroll
+    for (int u = 0; u < LC; ++u) f[u] = (v0 + u < nlev) ? F[(v0 + u) * n_slots + sl] : 0.0;
+#pragma unroll
+    for (int u = 0; u < LC; ++u) acc[u] += f[u];
+  }
+#pragma unroll
+  for (int u = 0; u < LC; ++u) {
+    const int v = v0 + u;
+    if (v < nlev) {
+      const int64_t idx = (int64_t)v * n_s + n;
+      if (full_diag) diag[idx] = acc[u];
+      const double di = (v == nlev - 1) ? 0.0 : recip(acc[u]);
+      dinv[idx] = di;
+      if (dinv32) dinv32[idx] = (float)di;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1602,27 +1672,26 @@ __global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ eta, con
 
 template <int P, int DIM>
 static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, bool store_G, bool h_is_total,
-                            hipStream_t s) {
+                            hipStream_t s, bool full) {
   using S = Sh<P, DIM>;
   const int64_t hs = (int64_t)c.n_eh * c.nh;
   if constexpr (DIM == 3) {
     // owner-computes with the apply's tiles and face slots (same 32-bit range conditions)
     const int64_t lim = int64_t(1) << 32;
-    if (c.tile_cols == S::CPB && c.n_v * 8 < lim) {
+    if (c.tile_cols == S::CPB && c.n_v * 8 < lim && (int64_t)(c.p * c.nz + 1) * c.n_tslots * 8 < lim) {
       const int nb = (c.n_eh + S::CPB - 1) / S::CPB;
       auto kern = store_G ? k_geom<P, DIM, true, true> : k_geom<P, DIM, true, false>;
       kern<<<nb, S::NT, 0, s>>>(
           eta, h, c.d_hm, hs, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s, c.d_sigma, c.d_layer_s,
           store_G ? c.d_G64 : nullptr, (store_G && c.want32) ? c.d_G32 : nullptr, c.d_diag, c.d_dinv,
           c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh, c.d_cg64, c.want32 ? c.d_cg32 : nullptr,
-          h_is_total ? 1 : 0, c.d_err, c.d_F64, c.d_tslot, c.n_tslots, c.d_xch);
-      if (c.n_tps > 0) {
-        const int nlev = c.p * c.nz + 1;
-        const int64_t work = (int64_t)c.n_tps * nlev;
-        k_diag_faces<<<(int)((work + 255) / 256), 256, 0, s>>>(c.d_diag, c.d_dinv, c.want32 ? c.d_dinv32 : nullptr,
+          h_is_total ? 1 : 0, c.d_err, c.d_F64, c.d_tslot, c.n_tslots, c.d_xch, full ? 1 : 0);
+      if (c.n_tps > 0)
+        k_diag_faces<<<face_blocks_n(c, c.n_tps), 256, 0, s>>>(c.d_diag, c.d_dinv, c.want32 ? c.d_dinv32 : nullptr,
                                                                 c.d_F64, c.d_tps_node, c.d_tps_ptr, c.d_tps_slot,
-                                                                c.n_tps, nlev, c.n_s, c.n_tslots);
-      }
+                                                                c.n_tps, c.p * c.nz + 1, c.n_s, c.n_tslots,
+                                                                full ? 1 : 0);
+      c.have_diag = full;
       return hipGetLastError();
     }
   }
@@ -1635,18 +1704,28 @@ static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, bool sto
                               (store_G && c.want32) ? c.d_G32 : nullptr, c.d_diag, c.d_dinv,
                               c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh, c.d_cg64,
                               c.want32 ? c.d_cg32 : nullptr, h_is_total ? 1 : 0, c.d_err, nullptr, nullptr, 0,
-                              nullptr);
+                              nullptr, 1);
   }
+  c.have_diag = true;   // the colour schedule assembles every node's diagonal in place
   return hipGetLastError();
 }
 
-hipError_t launch_geom(Ctx &c, const double *eta, const double *h, bool store_G, bool h_is_total, hipStream_t s) {
+hipError_t launch_geom(Ctx &c, const double *eta, const double *h, bool store_G, bool h_is_total, hipStream_t s,
+                       bool full_diag) {
+  const bool full = store_G || full_diag || c.keep_diag;
+  c.have_diag = false;
   if (c.dim == 3) {
-    FNPF_DISPATCH(3, c.p, return (geom_impl<P_, 3>(c, eta, h, store_G, h_is_total, s)));
+    FNPF_DISPATCH(3, c.p, return (geom_impl<P_, 3>(c, eta, h, store_G, h_is_total, s, full)));
   } else {
-    FNPF_DISPATCH(2, c.p, return (geom_impl<P_, 2>(c, eta, h, store_G, h_is_total, s)));
+    FNPF_DISPATCH(2, c.p, return (geom_impl<P_, 2>(c, eta, h, store_G, h_is_total, s, full)));
   }
   return hipSuccess;
+}
+
+hipError_t ensure_diag(Ctx &c, hipStream_t s) {
+  if (c.have_diag) return hipSuccess;
+  // the surface H and h of the last update, saved by the geometry kernel at every surface node
+  return launch_geom(c, c.d_geoH, c.d_geoh, false, true, s, true);
 }
 
 template <int P, int DIM, typename T, bool MASK, bool DOT>

@@ -219,7 +219,9 @@ hipError_t line_setup(Ctx &c, hipStream_t s) {
     return hipErrorOutOfMemory;
   if (c.want32 && c.d_lb32 == nullptr && hipMalloc((void **)&c.d_lb32, nb * sizeof(float)) != hipSuccess)
     return hipErrorOutOfMemory;
-  hipError_t e = launch_line_band(c, c.d_lb64, s);
+  hipError_t e = ensure_diag(c, s);   // the factor's diagonal
+  if (e != hipSuccess) return e;
+  e = launch_line_band(c, c.d_lb64, s);
   if (e != hipSuccess) return e;
   const int nlev = c.p * c.nz + 1;
   LINE_DISPATCH(c.p, (k_line_factor<P_><<<line_blocks(c), 256, 0, s>>>(c.d_lb64, c.d_diag, c.n_s, nlev, c.d_err)));

@@ -1190,6 +1190,7 @@ fnpf_status mg_refresh(Ctx &c, hipStream_t s) {
   if (!Prec<T>::stale(c)) return FNPF_OK;
   Ctx *F = &c;
   for (auto &L : c.mg) {
+    L.c->keep_diag = c.mg_line;
     if (surf_to(*F, *L.c, L.Hc, L.hc, s) != hipSuccess) return FNPF_ERR_HIP;
     st = geom_impl_total(*L.c, L.Hc, L.hc, s);
     if (st != FNPF_OK) return st;
@@ -1248,6 +1249,8 @@ static bool mg_prescale(const Ctx &c, int smooth_deg) { return smooth_deg == 2 &
 // Selects point (Jacobi) or vertical line smoothing; a change re-estimates every level's
 // smoothing interval and rebuilds the line factors at the next refresh.
 void mg_set_line(Ctx &c, bool line) {
+  c.keep_diag = line;   // the line factors read every level's whole diagonal
+  for (auto &L : c.mg) L.c->keep_diag = line;
   if (c.mg_line == line) return;
   c.mg_line = line;
   c.mg_stale64 = c.mg_stale32 = true;

@@ -148,7 +148,6 @@ __device__ __forceinline__ double recip(double a) {
   r = fma(r, fma(-a, r, 1.0), r);
   return fma(r, fma(-a, r, 1.0), r);
 }
-__device__ __forceinline__ double dsq(int P, int r, int c) { return c_DSQ64[P * kDStride + r * (P + 1) + c]; }
 // The squared-derivative table of degree P behind an opaque zero offset that depends on `dep`:
 // its scalar loads cannot be hoisted above `dep` (so the 49 FP64 entries at P = 6 are not held in
 // scalar registers across the whole kernel, which spills them to vector lanes).

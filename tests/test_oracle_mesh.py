@@ -162,3 +162,44 @@ def test_apply_invariant_under_renumbering():
     yb = op.apply(b, Gb, ub)
     assert np.abs(yb[vperm] - ya).max() < 1e-13 * np.abs(ya).max()
     assert np.abs(xb_pos[0][perm] - x).max() < 1e-14
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_node_coords_tensor_grid(periodic):
+    """Horizontal node coordinates of an axis-aligned box: the tensor product of the GLL points
+    mapped into each interval (x_e + (1 + xi_i) dx / 2), every node listed once (the first image
+    on a periodic axis)."""
+    from oracle.gll import gll
+    nx, ny, p = 4, 3, 3
+    x0, x1, y0, y1 = -1.0, 3.0, 0.5, 2.0
+    m = wm.structured_box(nx, ny, x0, x1, y0, y1, periodic, periodic, p=p, nz=1)
+    xi, _, _ = gll(p)
+    dx, dy = (x1 - x0) / nx, (y1 - y0) / ny
+
+    def axis(n, a, d, per):
+        pts = sorted({round(a + (e + (1 + s) / 2) * d, 12) for e in range(n) for s in xi})
+        if per:
+            pts = [q for q in pts if q < a + n * d - 1e-9]   # the period's end is its start
+        return np.array(pts)
+
+    gx, gy = axis(nx, x0, dx, periodic), axis(ny, y0, dy, periodic)
+    c = geo.node_coords(m)
+    assert c.shape == (len(gx) * len(gy), 2) and not np.isnan(c).any()
+    want = np.array([(a, b) for a in gx for b in gy])
+    key = lambda z: np.lexsort((np.round(z[:, 1], 9), np.round(z[:, 0], 9)))
+    assert np.abs(c[key(c)] - want[key(want)]).max() < 1e-12
+
+
+def test_sigma_levels_closed_form():
+    """sigma at level v = l p + k: s_l + (1 + xi_k)(s_{l+1} - s_l) / 2, from 0 at the bottom to 1
+    at the surface, increasing, with the layer boundaries shared."""
+    from oracle.gll import gll
+    m = wm.structured_box(3, 3, 0.0, 1.0, 0.0, 1.0, False, False, p=4, nz=3)
+    m.layer_s = np.array([0.0, 0.2, 0.65, 1.0])
+    xi, _, _ = gll(4)
+    sig = geo.sigma_levels(m)
+    want = np.array([m.layer_s[l] + (1 + xi[k]) * (m.layer_s[l + 1] - m.layer_s[l]) / 2
+                     for l in range(3) for k in range(4)] + [1.0])
+    assert sig.shape == (m.n_lev,)
+    assert np.abs(sig - want).max() < 1e-15
+    assert sig[0] == 0.0 and sig[-1] == 1.0 and np.all(np.diff(sig) > 0)

@@ -33,6 +33,7 @@ inline std::vector<PartialUse> partial_uses(int64_t colour_blocks, int64_t owner
       {"p-multigrid update and dots, FP64 grid", v64, 2},
       {"p-multigrid update and dots, FP32 grid", v32, 2},
       {"Lanczos and power-iteration dots, FP32 grid", v32, 2},
+      {"line-smoother B-norm (k_line_bnorm), FP32 grid", v32, 1},
       {"apply with dot product, colour schedule", colour_blocks, 1},
       {"apply with dot product, owner-computes", owner_blocks, 1},
   };

@@ -82,8 +82,9 @@ def apply(mesh, G, x, dofs=None):
     return _scatter(mesh, dofs, ye)
 
 
-def diagonal(mesh, G):
-    """diag(A) from the element matrices' diagonals (used by the Jacobi preconditioner)."""
+def diagonal(mesh, G, dofs=None):
+    """diag(A) from the element matrices' diagonals (used by the Jacobi preconditioner); G and
+    dofs may cover a subset of the elements (dof_map(mesh, cols=...)), as in apply."""
     B = grad_tables(mesh)
     d = mesh.dim
     Gf = G.reshape(G.shape[0], -1, d, d)
@@ -91,7 +92,7 @@ def diagonal(mesh, G):
     for a in range(d):
         for b in range(d):
             de = de + np.einsum("qn,eq,qn->en", B[a], Gf[:, :, a, b], B[b])
-    return _scatter(mesh, dof_map(mesh), de)
+    return _scatter(mesh, dof_map(mesh) if dofs is None else dofs, de)
 
 
 def _cross(a, b):

@@ -365,7 +365,8 @@ def test_c2_full_size_apply_and_solve():
 
 @pytest.mark.parametrize("variant", [0, 6, 7])
 def test_c5_sampled_apply(variant):
-    """C5 (43,675,392 DoF): apply parity at the nodes of sampled columns (oracle on their neighbourhood)."""
+    """C5 (43,675,392 DoF): apply parity at the nodes of sampled columns (oracle on their
+    neighbourhood); with the default schedule also the FP32 apply and the assembled diagonal."""
     wl = configs.c5()
     m = wl.mesh
     ctx = fnpf.Context(m, g=wl.g)
@@ -378,6 +379,13 @@ def test_c5_sampled_apply(variant):
     xv = torch.randn(m.n_v, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(4))
     y_gpu = host(ctx.laplace_apply(xv))
     xv_h = host(xv)
+    if variant == 0:
+        # the FP32 apply at the same columns, and the assembled diagonal (by default kept only
+        # where the face pass completes it: the export recomputes it whole)
+        ctx.enable_fp32()
+        ctx.geom(dev(eta), dev(h))
+        y32 = host(ctx.laplace_apply(xv.float()))
+        diag = host(ctx.export_geometry(fnpf.F64)[1])
     nx, ny = m.extra["nx"], m.extra["ny"]
     samples = [(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2), (17, 101), (200, 3)]
     xh_all = None
@@ -393,6 +401,12 @@ def test_c5_sampled_apply(variant):
         # p = 6 contractions of strongly anisotropic factors (aspect ratio ~ 5): rounding order
         # differences between the two sums reach a few 1e-13
         assert rel(y_gpu[own], yo[own]) < 2e-12
+        if variant == 0:
+            assert rel(y32[own], yo[own]) < 2e-6
+            do = op.diagonal(m, G, dofs)
+            # sums over up to eight elements in another order, of terms the anisotropic factors
+            # make up to two orders of magnitude apart: measured 7e-13 of the largest entry
+            assert np.abs(diag[own] - do[own]).max() < 2e-12 * np.abs(do[own]).max()
 
 
 def test_error_paths():

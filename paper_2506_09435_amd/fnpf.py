@@ -241,7 +241,9 @@ class Context:
 
     # -- path ---------------------------------------------------------------------
     def set_apply_variant(self, variant: int):
-        """0: fused geometry (default), 1: stored per-point factors."""
+        """0: fused geometry with owner-computes tile assembly (default); 1: stored per-point
+        factors; 6: fused geometry, line schedule with colour assembly; 7: fused geometry, colour
+        schedule (fnpf_set_apply_variant; all compute the same operator)."""
         self._check(lib().fnpf_set_apply_variant(self._h, int(variant)), "fnpf_set_apply_variant")
 
     def enable_fp32(self):

@@ -91,6 +91,9 @@ void free_all(Ctx &c) {
   dfree(c.d_tps_node);
   dfree(c.d_tps_ptr);
   dfree(c.d_tps_slot);
+  dfree(c.d_gslot);
+  dfree(c.d_gx_ptr);
+  dfree(c.d_gx_slot);
   dfree(c.d_flags);
   dfree(c.d_face_tag);
   dfree(c.d_hm);
@@ -714,7 +717,7 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
     UP(c.d_ps_node, c.h_ps_node.data(), c.h_ps_node.size());
     UP(c.d_ps_ptr, c.h_ps_ptr.data(), c.h_ps_ptr.size());
     UP(c.d_ps_slot, c.h_ps_slot.data(), c.h_ps_slot.size());
-    AL(c.d_F64, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(std::max(c.n_slots, c.n_tslots), 1));
+    AL(c.d_F64, (size_t)(c.p * c.nz + 1) * std::max<int64_t>(std::max({c.n_slots, c.n_tslots, c.n_gslots}), 1));
     if (c.dim == 3) {
       // the lists may be empty (a mesh within one tile): upload one unused entry then
       if (c.h_tps_node.empty()) c.h_tps_node.push_back(0);
@@ -724,6 +727,10 @@ fnpf_status fnpf_create(const fnpf_mesh_desc *m, fnpf_ctx *out) {
       UP(c.d_tps_node, c.h_tps_node.data(), c.h_tps_node.size());
       UP(c.d_tps_ptr, c.h_tps_ptr.data(), c.h_tps_ptr.size());
       UP(c.d_tps_slot, c.h_tps_slot.data(), c.h_tps_slot.size());
+      if (c.h_gx_slot.empty()) c.h_gx_slot.push_back(0);
+      UP(c.d_gslot, c.h_gslot.data(), c.h_gslot.size());
+      UP(c.d_gx_ptr, c.h_gx_ptr.data(), c.h_gx_ptr.size());
+      UP(c.d_gx_slot, c.h_gx_slot.data(), c.h_gx_slot.size());
     }
   }
   UP(c.d_flags, flags.data(), flags.size());

@@ -218,7 +218,14 @@ struct Ctx {
   int n_tps = 0;
   int32_t *d_tslot = nullptr, *d_tps_node = nullptr, *d_tps_ptr = nullptr, *d_tps_slot = nullptr;
   int16_t *d_xch = nullptr;
-  double *d_F64 = nullptr;                // [p nz + 1][n_slots]
+  // the geometry's face layout (k_geom, k_diag_faces): per column node its place in a level row
+  // of n_gslots entries (-1 none): the owner tile's value at a node with slots at k (its position
+  // among h_tps_node), the node's first slot at n_tps + k, further slots from 2 n_tps on, listed
+  // per node (CSR h_gx_ptr, h_gx_slot)
+  std::vector<int32_t> h_gslot, h_gx_ptr, h_gx_slot;
+  int64_t n_gslots = 0;
+  int32_t *d_gslot = nullptr, *d_gx_ptr = nullptr, *d_gx_slot = nullptr;
+  double *d_F64 = nullptr;                // [p nz + 1][largest of n_slots, n_tslots, n_gslots]
   float *d_F32 = nullptr;
   double *d_cg64 = nullptr;               // [5|3][n_eh*nh] H, H_xi, h_xi, (H_eta, h_eta) per column node
   float *d_cg32 = nullptr;

@@ -41,6 +41,12 @@ constexpr int kMaxH = kMaxN1 / 2;
 constexpr int kEOStride = 2 * kMaxH * kMaxH + 2 * kMaxH;
 __constant__ double c_EO64[(kMaxP + 1) * 2 * kEOStride];
 __constant__ float c_EO32[(kMaxP + 1) * 2 * kEOStride];
+// Even-odd table of the squared-derivative line sum out_r = sum_m D[m][r]^2 in_m (the diagonal's
+// line sums): its matrix Q[r][m] = D[m][r]^2 is centro-symmetric, Q[p-r][p-m] = Q[r][m]; the
+// table stores A[r][m] = (Q[r][m] - Q[r][p-m]) / 2, B[r][m] = (Q[r][m] + Q[r][p-m]) / 2 (r, m < H)
+// and, for even p, Bc[r] = Q[r][c], Cc[m] = Q[c][m] (m < H) and Q[c][c].
+constexpr int kSqStride = 2 * kMaxH * kMaxH + 2 * kMaxH + 1;
+__constant__ double c_SQEO64[(kMaxP + 1) * kSqStride];
 
 // Face-slot scratch of the allocation-free apply (fnpf_laplace_apply_noalloc): a file-scope array
 // in the library's device code, one copy per GPU, allocated when the code object is loaded and
@@ -75,6 +81,7 @@ hipError_t upload_constants(int /*device*/) {
   static double W[kMaxN1 * kMaxN1];
   static double EO64[(kMaxP + 1) * 2 * kEOStride];
   static float EO32[(kMaxP + 1) * 2 * kEOStride];
+  static double SQEO64[(kMaxP + 1) * kSqStride];
   for (int p = 1; p <= kMaxP; ++p) {
     double x[kMaxN1], w[kMaxN1], D[kMaxN1 * kMaxN1];
     gll_host(p, x, w, D);
@@ -105,6 +112,22 @@ hipError_t upload_constants(int /*device*/) {
         }
       for (int k = 0; k < kEOStride; ++k) EO32[(p * 2 + tr) * kEOStride + k] = (float)E[k];
     }
+    {
+      auto Q = [&](int r, int m) { return D[m * n1 + r] * D[m * n1 + r]; };
+      double *E = SQEO64 + p * kSqStride;
+      for (int r = 0; r < H; ++r)
+        for (int m = 0; m < H; ++m) {
+          E[r * H + m] = 0.5 * (Q(r, m) - Q(r, p - m));
+          E[H * H + r * H + m] = 0.5 * (Q(r, m) + Q(r, p - m));
+        }
+      if (n1 & 1) {
+        for (int r = 0; r < H; ++r) {
+          E[2 * H * H + r] = Q(r, c);
+          E[2 * H * H + H + r] = Q(c, r);
+        }
+        E[2 * H * H + 2 * H] = Q(c, c);
+      }
+    }
   }
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_D64), D64, sizeof(D64));
   if (e != hipSuccess) return e;
@@ -115,6 +138,8 @@ hipError_t upload_constants(int /*device*/) {
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_EO64), EO64, sizeof(EO64));
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_EO32), EO32, sizeof(EO32));
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_SQEO64), SQEO64, sizeof(SQEO64));
   if (e != hipSuccess) return e;
   return hipMemcpyToSymbol(HIP_SYMBOL(c_W), W, sizeof(W));
 }
@@ -233,6 +258,50 @@ __device__ __forceinline__ void line_eo(const T (&in)[P + 1], T (&out)[P + 1], c
     T sc = E[2 * H * H + H] * o[0];
 #pragma unroll
     for (int m = 1; m < H; ++m) sc += E[2 * H * H + H + m] * o[m];
+    out[C] = sc;
+  }
+}
+
+// The squared-derivative line sum out_r = sum_m D[m][r]^2 in_m in even-odd form (table above),
+// for degrees up to 6 (with positive inputs its rounding error stays within 3e-15 relative there,
+// against 2e-14 at degrees 7 and 8, where the dense sum is kept):
+//   out_r = S_r + O_r,  out_{P-r} = S_r - O_r,  S_r = sum_m B_rm e_m (+ Bc_r in_c),  O_r = sum_m A_rm o_m,
+//   out_c = sum_m Cc_m e_m + Q_cc in_c  (even P).  Q points at the degree's table behind an opaque
+// offset (sqeo_ptr), as the other line tables.
+template <typename U>
+__device__ __forceinline__ const double *sqeo_ptr(int P, const U &dep) {
+  int z = 0;
+  asm volatile("" : "+s"(z) : "v"(dep));
+  return c_SQEO64 + P * kSqStride + z;
+}
+template <int P>
+__device__ __forceinline__ void line_sq_eo(const double (&in)[P + 1], double (&out)[P + 1],
+                                           const double *__restrict__ Q) {
+  constexpr int N1 = P + 1, H = N1 / 2, C = P / 2;
+  static_assert(P <= 6, "the differences o_m cancel more at higher degree: use the dense sum there");
+  double e[H], o[H];
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    e[m] = in[m] + in[P - m];
+    o[m] = in[m] - in[P - m];
+  }
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    double so = Q[r * H] * o[0];
+    double se = Q[H * H + r * H] * e[0];
+#pragma unroll
+    for (int m = 1; m < H; ++m) {
+      so += Q[r * H + m] * o[m];
+      se += Q[H * H + r * H + m] * e[m];
+    }
+    if constexpr ((N1 & 1) != 0) se += Q[2 * H * H + r] * in[C];
+    out[r] = se + so;
+    out[P - r] = se - so;
+  }
+  if constexpr ((N1 & 1) != 0) {
+    double sc = Q[2 * H * H + 2 * H] * in[C];
+#pragma unroll
+    for (int m = 0; m < H; ++m) sc += Q[2 * H * H + H + m] * e[m];
     out[C] = sc;
   }
 }
@@ -982,8 +1051,9 @@ int owner_apply_blocks(const Ctx &c) {
 // read-add-write.  OWN = true (3D): one launch over all columns, the CPB columns of a workgroup a
 // tile as in the owner-computes apply: the tile's columns pass their diagonal contributions at
 // shared nodes to the node's representative through LDS exchange entries (xch), which stores the
-// diagonal (and its inverses where no other tile contributes) or writes its tile's sum to a face
-// slot; k_diag_faces completes the nodes with face slots.  SG: also store the per-point factors
+// inverses (and the diagonal if kept) where no other tile contributes and otherwise writes its
+// tile's sum to its place in the geometry's face layout (slot, n_slots entries per level);
+// k_diag_faces completes the nodes with face slots.  SG: also store the per-point factors
 // (G64, G32) for the stored-factor apply; without them the off-diagonal factors are dead code and
 // the kernel needs about two thirds of the registers.
 template <int P, int DIM, bool OWN = false, bool SG = true>
@@ -1045,14 +1115,16 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   }
   const bool stores = OWN && active && ((fl & kTRep) || sl >= 0);
   // OWN stores through raw buffer descriptors with 32-bit byte offsets (the launcher checks that
-  // the level rows of diag and of the face slots fit): a storing thread writes the diagonal where
-  // its tile owns the node and k_diag_faces completes it (or the whole diagonal is kept), the
-  // inverses where no other tile contributes, and its face slot elsewhere
+  // the level rows of diag and of the face layout fit): where its tile owns a node that no other
+  // tile touches, a storing thread writes the inverses (and the diagonal if the whole diagonal is
+  // kept); elsewhere it writes its tile's value to its place sl in the geometry's face layout (the
+  // owner's place where its tile owns the node), from which k_diag_faces completes the node
   constexpr int kSmStore = 1, kSmDiag = 2, kSmInv = 4, kSmSlot = 8, kSmX0 = 16, kSmX1 = 32, kSmX2 = 64;
+  const bool own_only = (fl & kTOwn) && !(fl & kTShared);
   const int smode = !stores ? 0
-                            : kSmStore | ((fl & kTOwn) && (full_diag || (fl & kTShared)) ? kSmDiag : 0) |
-                                  ((fl & kTOwn) && !(fl & kTShared) ? kSmInv : 0) | (!(fl & kTOwn) ? kSmSlot : 0) |
-                                  (xr0 >= 0 ? kSmX0 : 0) | (xr1 >= 0 ? kSmX1 : 0) | (xr2 >= 0 ? kSmX2 : 0);
+                            : kSmStore | (own_only && full_diag ? kSmDiag : 0) | (own_only ? kSmInv : 0) |
+                                  (!own_only ? kSmSlot : 0) | (xr0 >= 0 ? kSmX0 : 0) | (xr1 >= 0 ? kSmX1 : 0) |
+                                  (xr2 >= 0 ? kSmX2 : 0);
   const int xc0 = xr0 < 0 ? 0 : xr0, xc1 = xr1 < 0 ? 0 : xr1, xc2 = xr2 < 0 ? 0 : xr2;
   const uint32_t row8 = (uint32_t)n_s * 8u, rowF8 = (uint32_t)n_slots * 8u;
   const uint32_t hb8 = (uint32_t)hn * 8u, fb8 = (uint32_t)(sl < 0 ? 0 : sl) * 8u;
@@ -1120,30 +1192,37 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   double *Ab = sA + lc * NP;
   double *Bb = sB + (DIM == 3 ? lc * N1 * SB : 0);
 
+  // 3D: the horizontal part of J^-T grad(.) picks up b2 = -(J_h^-T grad z) / z_zeta, and
+  // grad z = sigma grad H - grad h is linear in sigma along the line: b2 = (sigma a0 + b0) / z_zeta
+  // with a0, b0 per column node; the products of A in the factors are per column node as well
+  const double ax0 = -(Hx * A00 + Hy * A10), bx0 = hx * A00 + hy * A10;
+  const double ay0 = -(Hx * A01 + Hy * A11), by0 = hx * A01 + hy * A11;
+  const double c00 = A00 * A00 + A01 * A01, c11 = A10 * A10 + A11 * A11, c01 = A00 * A10 + A01 * A11;
+  const double whd = wh * detJh;
+
   double carry = 0.0;
   const int64_t e0 = (int64_t)col * nz;
   for (int l = 0; l < nz; ++l) {
     const double zz = 0.5 * (layer_s[l + 1] - layer_s[l]) * Hn;   // z_zeta (sigma-linear per layer)
     const double izz = 1.0 / zz;
+    const double ax = ax0 * izz, bx = bx0 * izz, ay = ay0 * izz, by = by0 * izz, izz2 = izz * izz;
+    const double fzl = whd * zz;   // the point's factor w_i w_j w_k det J is w_k fzl
     double gz[N1];
     double *Ge64 = G64 ? G64 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
     float *Ge32 = G32 ? G32 + (e0 + l) * (int64_t)(NG * NP) : nullptr;
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       const double sg = sigma[l * P + k];
-      const double zx = -hx + sg * Hx;
-      const double f = wh * wgt(P, k) * detJh * zz;
       const int q = k * NH + t;
       if constexpr (DIM == 3) {
-        const double zy = -hy + sg * Hy;
-        const double b2x = -(zx * A00 + zy * A10) * izz;
-        const double b2y = -(zx * A01 + zy * A11) * izz;
-        const double b2z = izz;
-        const double g00 = f * (A00 * A00 + A01 * A01);
-        const double g11 = f * (A10 * A10 + A11 * A11);
-        const double g22 = f * (b2x * b2x + b2y * b2y + b2z * b2z);
+        const double f = wgt(P, k) * fzl;
+        const double b2x = sg * ax + bx;
+        const double b2y = sg * ay + by;
+        const double g00 = f * c00;
+        const double g11 = f * c11;
+        const double g22 = f * (b2x * b2x + b2y * b2y + izz2);
         if (SG && active && Ge64) {
-          const double g01 = f * (A00 * A10 + A01 * A11);
+          const double g01 = f * c01;
           const double g02 = f * (A00 * b2x + A01 * b2y);
           const double g12 = f * (A10 * b2x + A11 * b2y);
           Ge64[0 * NP + q] = g00;
@@ -1165,6 +1244,8 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
         Bb[k * SB + t] = g11;
         gz[k] = g22;
       } else {
+        const double zx = -hx + sg * Hx;
+        const double f = wh * wgt(P, k) * detJh * zz;
         const double b1x = -zx * A00 * izz;
         const double b1z = izz;
         const double g00 = f * A00 * A00;
@@ -1186,31 +1267,35 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
     }
     __syncthreads();
     // line sums in place: the thread's xi-line (j = a, k = b) and, in 3D, eta-line (i = a,
-    // k = b), t = b N1 + a; out_r = sum_m D[m][r]^2 in_m
+    // k = b), t = b N1 + a; out_r = sum_m D[m][r]^2 in_m (even-odd form up to degree 6)
     {
-      double in[N1];
+      auto line_sum = [&](const double(&in)[N1], double(&out)[N1]) {
+        if constexpr (P <= 6) {
+          line_sq_eo<P>(in, out, sqeo_ptr(P, in[0]));
+        } else {
+          const double *Q = dsq_ptr(P, in[0]);
+#pragma unroll
+          for (int r = 0; r < N1; ++r) {
+            double a = 0.0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) a += Q[m * N1 + r] * in[m];
+            out[r] = a;
+          }
+        }
+      };
+      double in[N1], out[N1];
 #pragma unroll
       for (int m = 0; m < N1; ++m) in[m] = Ab[t * N1 + m];
-      const double *Q = dsq_ptr(P, in[0]);
+      line_sum(in, out);
 #pragma unroll
-      for (int r = 0; r < N1; ++r) {
-        double a = 0.0;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) a += Q[m * N1 + r] * in[m];
-        Ab[t * N1 + r] = a;
-      }
+      for (int r = 0; r < N1; ++r) Ab[t * N1 + r] = out[r];
       if constexpr (DIM == 3) {
         const int eb = (t / N1) * SB + t % N1;
 #pragma unroll
         for (int m = 0; m < N1; ++m) in[m] = Bb[eb + m * N1];
-        const double *Q2 = dsq_ptr(P, in[0]);
+        line_sum(in, out);
 #pragma unroll
-        for (int r = 0; r < N1; ++r) {
-          double a = 0.0;
-#pragma unroll
-          for (int m = 0; m < N1; ++m) a += Q2[m * N1 + r] * in[m];
-          Bb[eb + r * N1] = a;
-        }
+        for (int r = 0; r < N1; ++r) Bb[eb + r * N1] = out[r];
       }
     }
     __syncthreads();
@@ -1227,21 +1312,21 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
       for (int m = 0; m < N1; ++m) d += Qk[m * N1] * gz[m];
       const double Dkk = dmat<double>(P, k, k);
       const double sg = sigma[l * P + k];
-      const double zx = -hx + sg * Hx;
-      const double f = wh * wgt(P, k) * detJh * zz;
       if constexpr (DIM == 3) {
-        const double c01 = f * (A00 * A10 + A01 * A11);
+        const double f = wgt(P, k) * fzl;
+        const double f01 = f * c01;
         if (Dkk != 0.0) {   // uniform: D_kk vanishes except at the element's bottom and top levels
-          const double zy = -hy + sg * Hy;
-          const double b2x = -(zx * A00 + zy * A10) * izz;
-          const double b2y = -(zx * A01 + zy * A11) * izz;
-          const double c02 = f * (A00 * b2x + A01 * b2y);
-          const double c12 = f * (A10 * b2x + A11 * b2y);
-          d += 2.0 * (Dii * Djj * c01 + Dii * Dkk * c02 + Djj * Dkk * c12);
+          const double b2x = sg * ax + bx;
+          const double b2y = sg * ay + by;
+          const double f02 = f * (A00 * b2x + A01 * b2y);
+          const double f12 = f * (A10 * b2x + A11 * b2y);
+          d += 2.0 * (Dii * Djj * f01 + Dii * Dkk * f02 + Djj * Dkk * f12);
         } else {
-          d += 2.0 * (Dii * Djj * c01);
+          d += 2.0 * (Dii * Djj * f01);
         }
       } else {
+        const double zx = -hx + sg * Hx;
+        const double f = wh * wgt(P, k) * detJh * zz;
         const double b1x = -zx * A00 * izz;
         const double c01 = f * A00 * b1x;
         d += 2.0 * Dii * Dkk * c01;
@@ -1301,38 +1386,46 @@ __global__ __launch_bounds__(256) void k_geom(const double *__restrict__ eta, co
   }
 }
 
-// Face pass of the owner-computes geometry: diag += the face slots of the other tiles at each node
-// with slots (in increasing slot order), and the inverses there (0 on the top level); the sum is
-// written back to diag only when the whole diagonal is kept.  Same thread layout as k_apply_faces:
-// a thread takes one node and a chunk of kFaceLevels levels, all loads issued before the sums, and
-// each XCD walks a contiguous range of nodes.
+// Face pass of the owner-computes geometry: at the k-th node with face slots (node[k]), the
+// diagonal is the owner tile's value (F at k) plus the node's first slot (F at n_tps + k) plus its
+// further slots (F at xslot[xptr[k]..xptr[k+1]), in increasing slot order); the inverses are
+// stored there (0 on the top level), and the sum itself only when the whole diagonal is kept.
+// F's level rows have n_g entries.  The two leading reads follow the thread index, so they are
+// issued at once with the node index.  Same thread layout as k_apply_faces: a thread takes one node
+// and a chunk of kFaceLevels levels, and each XCD walks a contiguous range of nodes.
 __global__ __launch_bounds__(256) void k_diag_faces(double *__restrict__ diag, double *__restrict__ dinv,
                                                     float *__restrict__ dinv32, const double *__restrict__ F,
-                                                    const int32_t *__restrict__ ps_node,
-                                                    const int32_t *__restrict__ ps_ptr,
-                                                    const int32_t *__restrict__ ps_slot, int n_ps, int nlev,
-                                                    int64_t n_s, int64_t n_slots, int full_diag) {
+                                                    const int32_t *__restrict__ node,
+                                                    const int32_t *__restrict__ xptr,
+                                                    const int32_t *__restrict__ xslot, int n_tps, int nlev,
+                                                    int64_t n_s, int64_t n_g, int full_diag) {
   constexpr int LC = kFaceLevels;
   int blk = blockIdx.x;
   {
     const int nb = gridDim.x, q = nb >> 3, r = nb & 7, xc = blk & 7;
     blk = (xc < r ? xc * (q + 1) : r * (q + 1) + (xc - r) * q) + (blk >> 3);
   }
-  const int nbx = (n_ps + 255) >> 8;
+  const int nbx = (n_tps + 255) >> 8;
   const int chunk = blk / nbx;
   const int k = (blk - chunk * nbx) * 256 + threadIdx.x;
   const int v0 = chunk * LC;
-  if (k >= n_ps) return;
-  const int64_t n = ps_node[k];
-  const int a = ps_ptr[k], b = ps_ptr[k + 1];
-  double acc[LC];
+  if (k >= n_tps) return;
+  const int64_t n = node[k];
+  const int a = xptr[k], b = xptr[k + 1];
+  double acc[LC], f1[LC];
 #pragma unroll
-  for (int u = 0; u < LC; ++u) acc[u] = (v0 + u < nlev) ? diag[(v0 + u) * n_s + n] : 0.0;
+  for (int u = 0; u < LC; ++u) {
+    const int64_t row = (int64_t)(v0 + u) * n_g;
+    acc[u] = (v0 + u < nlev) ? F[row + k] : 0.0;
+    f1[u] = (v0 + u < nlev) ? F[row + n_tps + k] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < LC; ++u) acc[u] += f1[u];
   for (int q = a; q < b; ++q) {
-    const int64_t sl = ps_slot[q];
+    const int64_t sl = xslot[q];
     double f[LC];
 #pragma unroll
-    for (int u = 0; u < LC; ++u) f[u] = (v0 + u < nlev) ? F[(v0 + u) * n_slots + sl] : 0.0;
+    for (int u = 0; u < LC; ++u) f[u] = (v0 + u < nlev) ? F[(int64_t)(v0 + u) * n_g + sl] : 0.0;
 #pragma unroll
     for (int u = 0; u < LC; ++u) acc[u] += f[u];
   }
@@ -1677,18 +1770,18 @@ static hipError_t geom_impl(Ctx &c, const double *eta, const double *h, bool sto
   if constexpr (DIM == 3) {
     // owner-computes with the apply's tiles and face slots (same 32-bit range conditions)
     const int64_t lim = int64_t(1) << 32;
-    if (c.tile_cols == S::CPB && c.n_v * 8 < lim && (int64_t)(c.p * c.nz + 1) * c.n_tslots * 8 < lim) {
+    if (c.tile_cols == S::CPB && c.n_v * 8 < lim && (int64_t)(c.p * c.nz + 1) * c.n_gslots * 8 < lim) {
       const int nb = (c.n_eh + S::CPB - 1) / S::CPB;
       auto kern = store_G ? k_geom<P, DIM, true, true> : k_geom<P, DIM, true, false>;
       kern<<<nb, S::NT, 0, s>>>(
           eta, h, c.d_hm, hs, c.d_eh_nodes, c.d_flags, nullptr, c.n_eh, c.nz, c.n_s, c.d_sigma, c.d_layer_s,
           store_G ? c.d_G64 : nullptr, (store_G && c.want32) ? c.d_G32 : nullptr, c.d_diag, c.d_dinv,
           c.want32 ? c.d_dinv32 : nullptr, c.d_geoH, c.d_geoh, c.d_cg64, c.want32 ? c.d_cg32 : nullptr,
-          h_is_total ? 1 : 0, c.d_err, c.d_F64, c.d_tslot, c.n_tslots, c.d_xch, full ? 1 : 0);
+          h_is_total ? 1 : 0, c.d_err, c.d_F64, c.d_gslot, c.n_gslots, c.d_xch, full ? 1 : 0);
       if (c.n_tps > 0)
         k_diag_faces<<<face_blocks_n(c, c.n_tps), 256, 0, s>>>(c.d_diag, c.d_dinv, c.want32 ? c.d_dinv32 : nullptr,
-                                                                c.d_F64, c.d_tps_node, c.d_tps_ptr, c.d_tps_slot,
-                                                                c.n_tps, c.p * c.nz + 1, c.n_s, c.n_tslots,
+                                                                c.d_F64, c.d_tps_node, c.d_gx_ptr, c.d_gx_slot,
+                                                                c.n_tps, c.p * c.nz + 1, c.n_s, c.n_gslots,
                                                                 full ? 1 : 0);
       c.have_diag = full;
       return hipGetLastError();

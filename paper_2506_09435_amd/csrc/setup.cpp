@@ -472,6 +472,36 @@ std::string build_host_mesh(const fnpf_mesh_desc &m, Ctx &c, std::vector<double>
       // the owner tile's representative takes the dot product of nodes without face slots
       for (int64_t o = 0; o < n_eh * nh; ++o)
         if ((flags[o] & kTOwn) && slot_of_node[m.eh_nodes[o]] >= 0) flags[o] |= kTShared;
+      // The geometry's face layout: the same contributions, placed by the position k of their
+      // node in the list of nodes with slots, so that its face pass reads them in the order of
+      // its threads: the owner tile's value at k, the node's first slot at n_tps + k, further
+      // slots (in increasing slot order) from 2 n_tps on.
+      {
+        const int64_t ntp = c.n_tps;
+        std::vector<int32_t> pos(nts, -1);
+        c.h_gx_ptr.assign(1, 0);
+        c.h_gx_slot.clear();
+        for (int64_t k = 0; k < ntp; ++k) {
+          const std::vector<int32_t> &sl = node_slots[slot_of_node[c.h_tps_node[k]]];
+          pos[sl[0]] = (int32_t)(ntp + k);
+          for (size_t q = 1; q < sl.size(); ++q) {
+            pos[sl[q]] = (int32_t)(2 * ntp + (int64_t)c.h_gx_slot.size());
+            c.h_gx_slot.push_back(pos[sl[q]]);
+          }
+          c.h_gx_ptr.push_back((int32_t)c.h_gx_slot.size());
+        }
+        std::vector<int32_t> kpos(n_s, -1);
+        for (int64_t k = 0; k < ntp; ++k) kpos[c.h_tps_node[k]] = (int32_t)k;
+        c.h_gslot.assign(n_eh * nh, -1);
+        for (int64_t o = 0; o < n_eh * nh; ++o) {
+          if (c.h_tslot[o] >= 0)
+            c.h_gslot[o] = pos[c.h_tslot[o]];
+          else if ((flags[o] & kTShared) != 0)
+            c.h_gslot[o] = kpos[m.eh_nodes[o]];
+        }
+        c.n_gslots = 2 * ntp + (int64_t)c.h_gx_slot.size();
+        if (c.n_gslots >= INT32_MAX) return "too many face slots for the tile assembly";
+      }
     }
   }
   return "";

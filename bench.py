@@ -38,9 +38,9 @@ METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/for
 # HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by what the
 # counters read for kernels of known size), valid only for the kernel source they were taken from.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "ca51ef36ea2e8b14e19484a5f80b7aefc7cf5805f924d8b0296f6f894e9ffe19",
-    "fetch_bytes_per_apply": 800725845,
-    "write_bytes_per_apply": 516173691,
+    "kernel_source_sha256": "14d70ddb38055c14ef562c0926fbb3ce186fafebfcb34d7d6e04cf4e1ac42e8e",
+    "fetch_bytes_per_apply": 800525722,
+    "write_bytes_per_apply": 516370022,
 }
 
 

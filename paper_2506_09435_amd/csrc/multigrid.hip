@@ -142,8 +142,15 @@ __global__ __launch_bounds__(256) void k_mg_surf(const double *__restrict__ Hf, 
 // Coarse nodes owned by the column go to b_c, the others to the coarse face slots (summed by the
 // coarse level's face pass); the coarse surface level is set to zero.  The vertical carry of the
 // shared layer level passes through a double-buffered LDS slot per coarse horizontal node.
+// waves per SIMD the restriction is compiled for: six for the FP64 p = 6 -> 3 transfer (at most 80
+// VGPRs; the compiler's own choice lands just above and leaves five), else the compiler's choice
+template <int PF, typename T>
+struct RestrictWaves {
+  static constexpr int v = (PF == 6 && sizeof(T) == 8) ? 6 : 1;
+};
+
 template <int PF, int DIM, typename T>
-__global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, const T *__restrict__ qf,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RestrictWaves<PF, T>::v))) void k_restrict(const T *__restrict__ rf, const T *__restrict__ qf,
                                                   T *__restrict__ bc, T *__restrict__ Fc,
                                                   const int32_t *__restrict__ nodes_f,
                                                   const uint8_t *__restrict__ flags_f,
@@ -173,6 +180,18 @@ __global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, cons
   T *A = sA + lc * NA;
   T *Cr = sC + lc * 2 * NHC;
   const int vtop = PC * nz;
+  // stage B items of this thread (it = t + m NHF, the same coarse horizontal node in every layer),
+  // loaded once: the coarse node where the column owns it, else -1 - its face slot
+  constexpr int MI = (NB + NHF - 1) / NHF;
+  int dst[MI];
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = t + m * NHF;
+    const int h = it % NHC;
+    dst[m] = 0;
+    if (active && it < NB)
+      dst[m] = (flags_c[col * NHC + h] & kOwned) ? nodes_c[col * NHC + h] : -1 - slot_c[col * NHC + h];
+  }
   // the fine line of layer l + 1 is loaded while layer l is contracted (raw values of both
   // operands, so that nothing waits for them before their use)
   T nr[N1F], nq[N1F];
@@ -216,7 +235,10 @@ __global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, cons
       __syncthreads();
     }
     // stage B: coarse value (a, b, c) of this layer's element, assembled
-    for (int it = active ? t : NB; it < NB; it += NHF) {
+#pragma unroll 1
+    for (int m = 0; m < MI; ++m) {
+      const int it = t + m * NHF;
+      if (!active || it >= NB) continue;
       const int h = it % NHC, c = it / NHC;            // h = b N1C + a
       const int a = h % N1C, b = h / N1C;
       T acc = T(0);
@@ -233,12 +255,14 @@ __global__ __launch_bounds__(256) void k_restrict(const T *__restrict__ rf, cons
         continue;
       }
       const int v = l * PC + c;
-      const int hnc = nodes_c[col * NHC + h];
-      const uint8_t flc = flags_c[col * NHC + h];
-      if (flc & kOwned)
-        bc[(int64_t)v * ns_c + hnc] = (v == vtop) ? T(0) : acc;
+      int d = dst[0];   // dst[m] by selects (constant indices keep dst in registers)
+#pragma unroll
+      for (int q = 1; q < MI; ++q)
+        if (m == q) d = dst[q];
+      if (d >= 0)
+        bc[(int64_t)v * ns_c + d] = (v == vtop) ? T(0) : acc;
       else if (v != vtop)
-        Fc[(int64_t)v * nslots_c + slot_c[col * NHC + h]] = acc;
+        Fc[(int64_t)v * nslots_c + (-1 - d)] = acc;
     }
     __syncthreads();
   }

@@ -38,9 +38,9 @@ METRIC = "GDOF/s Laplace apply; s per RK4 step, FP64 vs mixed @1e-8; adjoint/for
 # HBM bytes of one C5 FP64 apply from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by what the
 # counters read for kernels of known size), valid only for the kernel source they were taken from.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "14d70ddb38055c14ef562c0926fbb3ce186fafebfcb34d7d6e04cf4e1ac42e8e",
-    "fetch_bytes_per_apply": 800525722,
-    "write_bytes_per_apply": 516370022,
+    "kernel_source_sha256": "b866b3e70557ab934cac31120f0927371de659025951d26072b83bd91d460366",
+    "fetch_bytes_per_apply": 800896614,
+    "write_bytes_per_apply": 516157747,
 }
 
 

@@ -759,11 +759,12 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
   const uint32_t rowb = (uint32_t)n_s * (uint32_t)sizeof(T);
   // face slots (OWN): [p nz + 1][n_slots]
   __amdgpu_buffer_rsrc_t rf = ry;
-  uint32_t fb = 0, rowf = 0;
+  uint32_t fb = 0, rowf = 0, fbytes = 0;
   bool has_slot = false;
   int xw = -1, xr0 = -1, xr1 = -1, xr2 = -1;
   if constexpr (OWN) {
-    rf = vec_rsrc(F, (uint32_t)((int64_t)(P * nz + 1) * n_slots * (int64_t)sizeof(T)));
+    fbytes = (uint32_t)((int64_t)(P * nz + 1) * n_slots * (int64_t)sizeof(T));
+    rf = vec_rsrc(F, fbytes);
     const int32_t sl = active ? slot[ho] : -1;
     has_slot = sl >= 0;
     fb = (uint32_t)(sl < 0 ? 0 : sl) * (uint32_t)sizeof(T);
@@ -786,6 +787,13 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
   for (int k = 1; k < N1; ++k) nxt[k] = active ? buf_ld<T>(rx, hb, (uint32_t)k * rowb) : T(0);
 
   for (int l = 0; l < nz; ++l) {
+    // FP64 up to degree 7: the row strides pass through an opaque copy per layer, so that the
+    // level offsets below are formed by scalar arithmetic where they are used (kept live across
+    // the loop, one per level, they spilled from scalar to vector registers; FP32 has the scalar
+    // registers for them, and at degree 8 the even-odd tables leave too few either way)
+    constexpr bool kRemat = sizeof(T) == 8 && P <= 7;
+    uint32_t rb = rowb, rfs = rowf;
+    if constexpr (kRemat) asm volatile("" : "+s"(rb), "+s"(rfs));
     // phase 0
 #pragma unroll
     for (int k = 1; k < N1; ++k) ucol[k] = nxt[k];
@@ -801,7 +809,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     // next layer's x loads complete behind this layer's arithmetic
     if (l + 1 < nz) {
 #pragma unroll
-      for (int k = 1; k < N1; ++k) nxt[k] = active ? buf_ld<T>(rx, hb, (uint32_t)((l + 1) * P + k) * rowb) : T(0);
+      for (int k = 1; k < N1; ++k) nxt[k] = active ? buf_ld<T>(rx, hb, (uint32_t)((l + 1) * P + k) * rb) : T(0);
     }
 
     // phase 1 (in place: each line is read and written by its one thread)
@@ -870,7 +878,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
     if (!OWN && active && !(fl & kFirst)) {
 #pragma unroll
       for (int k = 0; k < N1; ++k)
-        if (k < kend) old[k] = buf_ld<T>(ry, hb, (uint32_t)(l * P + k) * rowb);
+        if (k < kend) old[k] = buf_ld<T>(ry, hb, (uint32_t)(l * P + k) * rb);
     }
     __syncthreads();
 
@@ -902,16 +910,21 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
         }
       }
       if (active && ((fl & kTRep) || has_slot)) {
+        // the same for the stores' descriptors: formed here from opaque copies of the pointers,
+        // so that they are not held (and spilled) across the layer loop
+        T *yo = y, *fo = F;
+        if constexpr (kRemat) asm volatile("" : "+s"(yo), "+s"(fo));
+        const __amdgpu_buffer_rsrc_t rys = vec_rsrc(yo, nbytes), rfo = vec_rsrc(fo, fbytes);
 #pragma unroll
         for (int k = 0; k < N1; ++k) {
           if (k < kend) {
             const int v = l * P + k;
             if (fl & kTOwn) {
               const T val = (MASK && v == vtop) ? T(0) : yv[k];
-              buf_st(val, ry, hb, (uint32_t)v * rowb);
+              buf_st(val, rys, hb, (uint32_t)v * rb);
               if (DOT && !(fl & kTShared)) dot += (double)ucol[k] * (double)val;
             } else if (!(MASK && v == vtop)) {
-              buf_st(yv[k], rf, fb, (uint32_t)v * rowf);
+              buf_st(yv[k], rfo, fb, (uint32_t)v * rfs);
             }
           }
         }
@@ -922,7 +935,7 @@ __global__ __launch_bounds__(256) void k_apply_lines(const T *__restrict__ x, T 
         if (k < kend) {
           const int v = l * P + k;
           const T val = (MASK && v == vtop) ? T(0) : yv[k] + old[k];
-          buf_st(val, ry, hb, (uint32_t)v * rowb);
+          buf_st(val, ry, hb, (uint32_t)v * rb);
           if (DOT && (fl & kLast)) dot += (double)ucol[k] * (double)val;
         }
       }

@@ -46,6 +46,12 @@ def _case(name):
         return configs.small_box(nx=5, ny=3, nz=3, p=4, periodic=(True, False))
     if name == "box_walls_p6":
         return configs.small_box(nx=3, ny=2, nz=2, p=6, periodic=(False, False))
+    if name == "box_one_layer_p6":
+        # one element layer (the surface level is the first layer's top), tiles of five columns
+        # spanning two rows of seven, periodic in x
+        return configs.small_box(nx=7, ny=2, nz=1, p=6, periodic=(True, False))
+    if name == "slice_one_layer":
+        return configs.small_slice(nx=6, nz=1, p=6, periodic=False)
     if name == "cylinder":
         wl = configs.small_box()
         m = wm.cylinder_tank_mesh(p=3, nz=2, n_theta=8, n_rad=2, tank=(6.0, 4.0), spacing=1.0, hole_half=1.0)
@@ -66,7 +72,8 @@ def _case(name):
 
 
 CASES = ["slice_periodic", "slice_walls", "box_periodic", "box_mixed", "box_walls_p6", "cylinder",
-         "box_mixed_blocked", "cylinder_blocked", "box_walls_p6_sharedfirst", "cylinder_sharedfirst"]
+         "box_mixed_blocked", "cylinder_blocked", "box_walls_p6_sharedfirst", "cylinder_sharedfirst",
+         "box_one_layer_p6_sharedfirst", "slice_one_layer"]
 
 
 class Pair:
@@ -188,7 +195,7 @@ def test_solve_w_rhs_parity(name, variant):
     assert rel(host(de), deo) < 1e-12 and rel(host(dp), dpo) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["slice_periodic", "box_mixed", "cylinder"])
+@pytest.mark.parametrize("name", ["slice_periodic", "box_mixed", "cylinder", "box_one_layer_p6_sharedfirst"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_rk4_step_parity(name, precision):
     wl = _case(name)

@@ -148,3 +148,33 @@ def test_patch_linear_cylinder_small():
         errs.append(_patch(m, 0.05 * np.cos(x) * np.sin(y), 1.0 + 0.1 * np.cos(0.5 * x), fn, grad))
     assert all(e1 < e0 / 5 for e0, e1 in zip(errs, errs[1:]))
     assert errs[-1] < 1e-6
+
+
+def test_column_subset_apply_and_diagonal():
+    """The element-subset mode of apply and diagonal (G and dofs for some columns only, as the
+    sampled full-size checks use it): at the nodes of a column whose neighbours are all in the
+    subset, both equal the whole-mesh result; elsewhere they hold only the subset's share."""
+    m = wm.structured_box(5, 4, 0.0, 2.0, 0.0, 1.6, True, False, p=3, nz=2)
+    eta, h = _wavy(m, seed=3)
+    xh = geo.horizontal_coords(m)
+    Gf, _, _ = geo.factors(m, eta, h, xh)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(m.n_v)
+    yf = op.apply(m, Gf, x)
+    df = op.diagonal(m, Gf)
+    nx, ny = 5, 4
+    cx, cy = 2, 1
+    nb = sorted({((cx + dx) % nx) + (cy + dy) * nx for dx in (-1, 0, 1) for dy in (-1, 0, 1)})
+    G, _, _ = geo.factors(m, eta, h, xh, cols=nb)
+    dofs = geo.dof_map(m, cols=nb)
+    own = geo.dof_map(m, cols=[cx + cy * nx]).ravel()
+    y = op.apply(m, G, x, dofs)
+    d = op.diagonal(m, G, dofs)
+    np.testing.assert_allclose(y[own], yf[own], rtol=0, atol=1e-13 * np.abs(yf).max())
+    np.testing.assert_allclose(d[own], df[own], rtol=1e-13)
+    # a node outside the subset's closure gets nothing, a corner of the subset only part of its sum
+    outside = np.setdiff1d(np.arange(m.n_v), dofs.ravel())
+    assert outside.size > 0 and np.all(d[outside] == 0.0)
+    others = geo.dof_map(m, cols=[c for c in range(m.n_eh) if c not in nb]).ravel()
+    rim = np.intersect1d(dofs.ravel(), others)   # nodes the subset shares with other columns
+    assert rim.size > 0 and np.all(d[rim] < df[rim])
